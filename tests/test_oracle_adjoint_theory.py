@@ -1,0 +1,100 @@
+"""Pins for the oracle's adjoint gradient and the Section 4 formulas (CPU).
+
+Gradient anchors: central finite differences (h=1e-4 in log space), a closed
+form with a single training point, and torch float64 autograd through a dense
+Cholesky solve on the CPU.  Theory anchors: the worked values printed after
+Corollary tradeoff (tests/golden/rank_bound_examples.json) and the algebra
+linking Eq. cgrate to Eq. precond_rate2.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as oa
+from oracle import kernel as ok
+from oracle import theory as th
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rank_bound_examples.json")
+
+
+def _data(n=150, m=40, d=3, seed=0):
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(d) / 2
+    Xtr = 0.5 * rng.standard_normal((n, d))
+    Xv = 0.5 * rng.standard_normal((m, d))
+    return Xtr, np.tanh(Xtr @ w) + 0.1 * rng.standard_normal(n), Xv, np.tanh(Xv @ w)
+
+
+def test_adjoint_vs_finite_differences():
+    Xtr, ytr, Xv, yv = _data()
+    eps, beta = 2.0, 1e-2
+    L, ge, gb, _, _ = oa.val_loss_grad(Xtr, ytr, Xv, yv, eps, beta)
+    fe, fb = oa.fd_grad(Xtr, ytr, Xv, yv, eps, beta, h=1e-4)
+    assert abs(ge - fe) <= 1e-6 * max(abs(ge), 1e-12) + 1e-10
+    assert abs(gb - fb) <= 1e-6 * max(abs(gb), 1e-12) + 1e-10
+    assert L == pytest.approx(oa.val_loss(Xtr, ytr, Xv, yv, eps, beta), rel=1e-13)
+
+
+def test_adjoint_single_training_point_closed_form():
+    rng = np.random.default_rng(1)
+    x0 = rng.random((1, 2))
+    Xv = rng.random((5, 2))
+    y0, yv = np.array([0.7]), rng.standard_normal(5)
+    eps, beta = 0.3, 0.2
+    D2 = ((Xv - x0) ** 2).sum(1)
+    kv = np.exp(-D2 / eps)
+    a = y0[0] / (1 + beta)                           # K = [1]
+    rv = kv * a - yv
+    want_L = 0.5 * rv @ rv
+    want_e = rv @ ((D2 / eps) * kv * a)              # K' = 0 on the single training pair
+    want_b = rv @ (kv * (-beta * y0[0] / (1 + beta) ** 2))
+    L, ge, gb, _, _ = oa.val_loss_grad(x0, y0, Xv, yv, eps, beta)
+    assert L == pytest.approx(want_L, rel=1e-14)
+    assert ge == pytest.approx(want_e, rel=1e-12)
+    assert gb == pytest.approx(want_b, rel=1e-12)
+
+
+def test_adjoint_vs_torch_autograd():
+    torch = pytest.importorskip("torch")
+    Xtr, ytr, Xv, yv = _data(n=90, m=30, seed=2)
+    eps, beta = 1.5, 3e-2
+    le = torch.tensor(math.log(eps), dtype=torch.float64, requires_grad=True)
+    lb = torch.tensor(math.log(beta), dtype=torch.float64, requires_grad=True)
+    Xt, Xvt = torch.from_numpy(Xtr), torch.from_numpy(Xv)
+    D2 = ((Xt[:, None, :] - Xt[None, :, :]) ** 2).sum(-1)
+    D2v = ((Xvt[:, None, :] - Xt[None, :, :]) ** 2).sum(-1)
+    K = torch.exp(-D2 / torch.exp(le))
+    Kv = torch.exp(-D2v / torch.exp(le))
+    A = K + torch.exp(lb) * torch.eye(len(ytr), dtype=torch.float64)
+    Lc = torch.linalg.cholesky(A)
+    alpha = torch.cholesky_solve(torch.from_numpy(ytr)[:, None], Lc)[:, 0]
+    loss = 0.5 * ((Kv @ alpha - torch.from_numpy(yv)) ** 2).sum()
+    loss.backward()
+    _, ge, gb, _, _ = oa.val_loss_grad(Xtr, ytr, Xv, yv, eps, beta)
+    assert ge == pytest.approx(le.grad.item(), rel=1e-9)
+    assert gb == pytest.approx(lb.grad.item(), rel=1e-9)
+
+
+def test_rank_bound_worked_examples():
+    g = json.load(open(GOLDEN))
+    for c in g["cases"]:
+        if c["what"] == "gamma":
+            got = th.rank_gamma(c["h"], c["n"], c["beta"], c["xi"])
+            assert 0 <= got - c["expected"] < 0.01       # printed to two decimals (3.3464 appears as 3.34)
+        else:
+            k = th.rank_bound([c["q"]] * c["d"], c["h"], c["n"], c["beta"], c["xi"])
+            assert k == c["expected_base"] ** c["expected_exponent"]
+            assert 1e46 < k < 1e47
+
+
+def test_cg_rate_formulas():
+    assert th.cg_error_bound(1.0, 3) == 0.0
+    # Eq. precond_rate2 equals Eq. cgrate solved for i with kappa = 1 + M lam/beta (without the factor 2)
+    lam, beta, M, delta = 5.0, 1e-2, 3.0, 1e-6
+    kappa = th.cond_bound(lam, beta, M)
+    i = th.iters_precond(lam, beta, M, delta)
+    s = math.sqrt(kappa)
+    assert ((s - 1) / (s + 1)) ** i == pytest.approx(delta, rel=1e-9)
