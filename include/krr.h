@@ -1,0 +1,222 @@
+/*
+ * krr.h — C ABI of the MI355X (gfx950) Gaussian kernel ridge regression library.
+ *
+ * Problem (arXiv 1905.10587, Sec. 1, Eq. 1 and Eq. ridge_regression): given points
+ * X in R^{n x d}, labels y and a ridge parameter beta > 0, solve (K + beta I) alpha = y
+ * with K_ij = exp(-||x_i - x_j||^2 / eps).  The paper writes the Gaussian with bandwidth
+ * h (Sec. 2.4, Eq. dscrt_gt); here eps = h^2.
+ *
+ * Conventions for every entry point
+ *   - Array arguments marked [dev] are DEVICE pointers, [host] are host pointers.
+ *     All matrices are C-contiguous row-major: X is n x d (point i at X + i*d),
+ *     a block of R vectors over n points is n x R (V[i*R + r]).
+ *   - The caller owns every buffer it passes.  A krr_precond handle owns its own
+ *     device buffers and frees them in krr_precond_free.
+ *   - All GPU work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *     Entry points that return host scalars synchronise that stream first.
+ *   - Return value: a krr_status.  Nothing aborts or throws across the ABI.  On an
+ *     error the outputs are left unspecified and krr_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Arguments are validated before any GPU work: n, m >= 1; 1 <= d <= KRR_MAX_D;
+ *     eps > 0 and finite; beta > 0 (Sec. 1); 1 <= k <= l <= n; R >= 1; tol > 0.
+ *     Violations return KRR_EINVAL.
+ *   - Device memory comes from the allocator registered with krr_set_allocator
+ *     (PyTorch's caching allocator in the Python binding) or from hipMalloc.
+ */
+#ifndef KRR_H_
+#define KRR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRR_MAX_D 128
+
+typedef enum {
+  KRR_OK = 0,
+  KRR_EINVAL = -1,      /* invalid argument (sizes, eps, beta, non-finite input, unknown beta) */
+  KRR_ENOMEM = -2,      /* device allocation failed */
+  KRR_EHIP = -3,        /* a HIP runtime call failed */
+  KRR_ENOTSPD = -4,     /* Cholesky of beta I + W^T W failed (impossible in exact arithmetic) */
+  KRR_EBREAKDOWN = -5,  /* PCG breakdown: p^T A p <= 0 or not finite */
+  KRR_ENOCONV = 1       /* warning: maxit reached; alpha holds the last iterate */
+} krr_status;
+
+typedef enum {
+  KRR_FP64 = 0,   /* everything in FP64 */
+  KRR_FP32 = 1,   /* kernel MVM in FP32 (differences, exp, accumulation), FP64 scalars and vectors */
+  KRR_MIXED = 2   /* cross term x_i.x_j as split-BF16 products on MFMA with FP32 accumulation,
+                     FP32 exp; FP64 scalars, vectors, residual replacement and core Cholesky */
+} krr_precision;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int krr_version(void);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* krr_last_error(void);
+
+/* Device memory provider.  alloc(bytes, stream, ctx) returns a device pointer or NULL;
+ * free_(ptr, ctx) releases it.  Passing alloc == NULL restores hipMalloc/hipFree.
+ * Buffers allocated for a call are released (stream-ordered) before the call returns. */
+int krr_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                      void (*free_)(void* ptr, void* ctx), void* ctx);
+
+/*
+ * Kernel matrix times a block of vectors (the paper's FIG(targets, sources, h, V);
+ * Sec. 2.4, Def. figtree_def, computed exactly by direct summation; Algorithm 5 applies
+ * it as Kx).
+ *
+ *   U[i, r] = sum_j k(Xt_i, Xs_j) V[j, r]  (+ shift[r] * V[i, r])
+ *
+ *   Xt [dev]  m x d targets;  Xs [dev] n x d sources (may equal Xt).
+ *   V  [dev]  n x R;  U [dev] m x R (deriv 0 or 1) or m x 2R (deriv 2: K V then K' V
+ *             interleaved per row: U[i, 0..R-1] = (K V)_i, U[i, R..2R-1] = (K' V)_i).
+ *   shift [host] R values or NULL; requires m == n and Xt describing the same points
+ *             as Xs (the ridge term beta I).
+ *   deriv: 0 -> K, 1 -> K' = eps dK/deps = (D^2/eps) K, 2 -> both.
+ *   prec: KRR_FP64, KRR_FP32 or KRR_MIXED (see krr_precision).
+ */
+int krr_kernel_mv(const double* Xt, int64_t m, const double* Xs, int64_t n, int32_t d,
+                  double eps, const double* V, int32_t R, const double* shift,
+                  int32_t deriv, int32_t prec, double* U, void* stream);
+
+/*
+ * Anchor-selection sketch (Algorithm 1 / Algorithm 2, Sec. 3).
+ *   Dense (Algorithm 1):  Y = K Omega^T, with Omega^T given as omega [dev] n x l.
+ *   Sparse (Algorithm 2): column i of Y is sum_s sign[i, s] K(:, idx[i, s]),
+ *                         idx [dev] int64 l x r (point indices in [0, n)),
+ *                         sign [dev] l x r (Rademacher +-1; any values are accepted).
+ *   Exactly one of omega / (idx, sign) must be non-NULL.
+ *   Y [dev] n x l output, FP64.  prec selects the MVM precision.
+ */
+int krr_sketch(const double* X, int64_t n, int32_t d, double eps,
+               const double* omega, const int64_t* idx, const double* sign, int32_t l, int32_t r,
+               int32_t prec, double* Y, void* stream);
+
+/*
+ * Column-pivoted QR of Y^T (l x n) for anchor selection (Algorithm 1/2, last steps).
+ * Y [dev] n x l (the sketch), k pivot steps.  Outputs: piv [dev] int64 k (point
+ * indices, the first k pivots S), rdiag [dev] k (|R_jj|, the residual norm of each
+ * pivot when chosen).  Ties go to the lowest point index.  Plain pivoted QR stands in
+ * for strong RRQR (remark in Sec. 3).  prec: KRR_FP64 or KRR_FP32 arithmetic on Y.
+ */
+int krr_qrcp(const double* Y, int64_t n, int32_t l, int32_t k, int32_t prec,
+             int64_t* piv, double* rdiag, void* stream);
+
+typedef struct krr_precond krr_precond;   /* opaque */
+
+/* Flags for krr_build_precond */
+#define KRR_KEEP_SKETCH 1   /* keep Y (n x l) in the handle for inspection */
+
+/*
+ * Setup stage (Sec. 3, Algorithms 1-3): sketch -> pivoted QR -> anchors S ->
+ * K_SS = U^{-1} -> symmetric EVD -> W = C V_kept diag(lam_kept)^{-1/2} (C = K(X, X_S))
+ * -> M = W^T W (FP64 accumulation) -> for each beta: Cholesky L L^T = beta I + M
+ * (Eq. chol_factor) and its inverse.
+ *
+ *   X [dev] n x d; betas [host] nbeta values; k anchors, l sketch columns;
+ *   sketch random inputs as in krr_sketch (omega for Algorithm 1, idx/sign with r per column
+ *   for Algorithm 2); tau: eigenvalues of K_SS <= tau * max are dropped (tau <= 0: 1e-12).
+ *   prec: KRR_FP64 builds the FP64 factor only; KRR_FP32/KRR_MIXED also build an FP32 copy of
+ *   W (and its own core from exactly that copy) used by FP32/mixed solves.
+ *   *out receives the handle.  Returns KRR_ENOTSPD if a core Cholesky fails.
+ */
+int krr_build_precond(const double* X, int64_t n, int32_t d, double eps,
+                      const double* betas, int32_t nbeta, int32_t k, int32_t l,
+                      const double* omega, const int64_t* idx, const double* sign, int32_t r,
+                      double tau, int32_t prec, int32_t flags,
+                      krr_precond** out, void* stream);
+
+/* Sizes and host copies of small results.  Any output pointer may be NULL.
+ *   S_host [host] int64 k anchors; kept: rank kept after the EVD truncation;
+ *   lam_host [host] k eigenvalues of K_SS (ascending); rdiag_host [host] k QR diagonals. */
+int krr_precond_info(const krr_precond* P, int64_t* S_host, int32_t* kept,
+                     double* lam_host, double* rdiag_host, int32_t* k, int32_t* nbeta);
+
+/* Copy an internal device buffer into caller memory (testing and inspection).
+ *   what: 0 = W FP64 (n x kept), 1 = W FP32 (n x kept, float), 2 = L FP64 (kept x kept,
+ *         for betas[bidx]), 3 = Y sketch (n x l, needs KRR_KEEP_SKETCH), 4 = M = W^T W FP64.
+ *   dst [dev], bytes = size of dst (must be at least the buffer's size). */
+int krr_precond_get(const krr_precond* P, int32_t what, int32_t bidx, void* dst, size_t bytes,
+                    void* stream);
+
+/*
+ * Woodbury apply (Algorithm 4 with W = C U^{1/2}; Eq. woodbury):
+ *   out[:, r] = (x[:, r] - W z_r) / beta_r,  z_r = (beta_r I + W^T W)^{-1} W^T x[:, r]
+ *   x, out [dev] n x R; betas [host] R values, each equal to one of the handle's betas.
+ *   prec: KRR_FP64 uses the FP64 factor; KRR_FP32 / KRR_MIXED the FP32 W (needs a handle
+ *   built with that precision).
+ */
+int krr_precond_apply(const krr_precond* P, const double* x, int32_t R, const double* betas,
+                      int32_t prec, double* out, void* stream);
+
+void krr_precond_free(krr_precond* P);
+
+typedef struct {
+  int32_t iters_max;      /* largest iteration count over the columns */
+  int32_t n_mvm;          /* kernel MVMs issued in the working precision */
+  int32_t n_mvm_fp64;     /* FP64 MVMs for residual replacement / final check */
+  int32_t n_replace;      /* residual replacements performed */
+  double t_total_ms;      /* wall time of the solve (host clock, stream synchronised) */
+  double t_mvm_ms;        /* HIP-event time in working-precision MVMs (if timing enabled) */
+  double t_mvm_fp64_ms;   /* HIP-event time in FP64 MVMs */
+  double t_precond_ms;    /* HIP-event time in Woodbury applies */
+  double kappa_est;       /* Lanczos estimate of the preconditioned condition number, column 0 */
+} krr_solve_stats;
+
+/*
+ * PCG on (K + beta_r I) alpha_r = y_r for R right-hand sides in lockstep (Algorithm 5):
+ * one shared kernel MVM of the whole block per iteration, per-column FP64 scalars, converged
+ * columns frozen.  Stops a column when its true relative residual
+ * ||y - (K + beta I) alpha||_2 / ||y||_2 <= tol (checked with the FP64 operator).
+ *
+ *   X [dev] n x d;  Yrhs [dev] n x R;  betas [host] R values (each one of P's betas when P
+ *   is given);  P: preconditioner or NULL (plain CG);  replace_every: every that many
+ *   iterations the recursive residual is replaced by the FP64 true residual (0: never);
+ *   alpha [dev] n x R: in = initial guess x0 (zeros for a cold start), out = solution;
+ *   iters [host] R, relres [host] R: per-column iteration counts and final true relative
+ *   residuals;  stats [host] optional (NULL);  timing != 0 records HIP-event phase times.
+ *   Returns KRR_ENOCONV if some column did not reach tol within maxit.
+ */
+int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps,
+                  const double* Yrhs, int32_t R, const double* betas,
+                  const krr_precond* P, double tol, int32_t maxit, int32_t replace_every,
+                  int32_t prec, double* alpha, int32_t* iters, double* relres,
+                  krr_solve_stats* stats, int32_t timing, void* stream);
+
+/*
+ * Gradient of the validation loss L = 1/2 ||K(Xval, Xtr) alpha - yval||^2, alpha solving
+ * (K + beta I) alpha = ytr, with respect to log eps and log beta, by the adjoint method:
+ *   lambda = (K + beta I)^{-1} K_vt^T r_v,
+ *   dL/dlog eps = r_v^T K'_vt alpha - lambda^T K' alpha,  dL/dlog beta = -beta lambda^T alpha,
+ * with K' = (D^2/eps) K.  One forward and one adjoint PCG (same preconditioner P, may be NULL),
+ * fused (K, K') products.  Host scalars out; alpha_out [dev] n (optional), lambda_out [dev] n
+ * (optional).
+ */
+int krr_grad(const double* Xtr, int64_t n, const double* ytr,
+             const double* Xval, int64_t m, const double* yval, int32_t d,
+             double eps, double beta, const krr_precond* P,
+             double tol, int32_t maxit, int32_t replace_every, int32_t prec,
+             double* loss, double* dloss_dlog_eps, double* dloss_dlog_beta,
+             double* alpha_out, double* lambda_out, void* stream);
+
+/*
+ * Tile-shape autotuner for the kernel MVM (project-written; the paper has none).
+ * Times every kernel variant for (d, R, prec) on a synthetic problem of n points and records
+ * the fastest in the process-wide table used by all later calls.  best_variant [host] out.
+ * krr_autotune_save / krr_autotune_load persist the table as JSON.
+ */
+int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32_t* best_variant, void* stream);
+int krr_autotune_save(const char* path);
+int krr_autotune_load(const char* path);
+/* Force a variant for (d, R, prec) (-1 clears the entry).  Number of variants: krr_num_variants. */
+int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t variant);
+int krr_num_variants(int32_t prec, int32_t R);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRR_H_ */

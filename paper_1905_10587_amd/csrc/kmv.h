@@ -1,0 +1,67 @@
+// Kernel matrix-vector products U = K(Xt, Xs) V on gfx950 (the operation the paper delegates
+// to FIG(targets, sources, h, V), Sec. 2.4; computed here by exact direct summation, never
+// storing K).
+#pragma once
+
+#include "krr_internal.h"
+
+namespace krr {
+
+// Derived device copies of a point set used by the MVM kernels (stage inputs).
+//   x64: npad x dpad FP64 (zero padded rows/columns)
+//   x32: npad x dpad FP32, (x - center) * sqrt(log2(e)/eps)
+//   sa / sb: npad x ka bf16 split vectors of (x - center) for the MFMA cross term
+//            (target side / source side), ka = 32 * nchunk
+struct Staged {
+  int64_t n = 0, npad = 0;
+  int d = 0, dpad = 0, ka = 0;
+  int prec = KRR_FP64;
+  double eps = 0;
+  DevBuf<double> x64;
+  DevBuf<float> x32;
+  DevBuf<uint16_t> sa, sb;
+  DevBuf<double> center;   // dpad
+};
+
+constexpr int kRowPad = 1024;   // targets/sources are padded to multiples of this
+
+// Pads d up to the instantiated widths of the direct (FP64/FP32) kernels.
+int padded_dim(int d);
+// Number of 32-wide K chunks of the split-BF16 cross term for dimension d.
+int mixed_chunks(int d);
+
+// Stage a point set.  center: dpad FP64 on device (translation applied to FP32 and split copies;
+// the kernel is translation invariant).  Pass the same center for targets and sources.
+void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int prec,
+                  const double* center, bool as_target, bool as_source, hipStream_t s);
+// Mean of the points (FP64), written to center[dpad].
+void point_mean(const double* X, int64_t n, int d, int dpad, double* center, hipStream_t s);
+
+// V (n x R FP64, row-major) -> padded column-block layout used by the kernels.
+struct StagedVec {
+  int64_t npad = 0;
+  int R = 0;            // columns padded to a multiple of 8
+  int Rreal = 0;
+  DevBuf<double> v64;   // npad x R
+  DevBuf<float> v32;    // npad x R
+};
+void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
+                   hipStream_t s);
+
+// Core launcher: U[i, col0 + c] (row stride ldu) for the staged operands.
+//   deriv: 0 K, 1 K', 2 both (K columns first, then K' columns).
+//   shift: per-column ridge term added as shift[c] * V[i, c] (targets == sources) or nullptr.
+//   Vraw: the original FP64 V (n x R) for the shift term.
+void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
+                const double* shift_host, const double* Vraw, int prec, double* U, int64_t ldu,
+                hipStream_t s, int variant = -1);
+
+// Variant bookkeeping for the autotuner.
+int kmv_num_variants(int prec, int R);
+int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t n);
+void kmv_set_override(int d, int R, int prec, int variant);
+int kmv_get_override(int d, int R, int prec);
+std::string kmv_table_json();
+void kmv_table_from_json(const std::string& s);
+
+}  // namespace krr

@@ -1,0 +1,356 @@
+// Exact Gaussian kernel MVM kernels for gfx950.
+//
+//   U[i, c] = sum_j exp(-||t_i - s_j||^2 / eps) V[j, c]          (Sec. 1 Eq. 1; Sec. 2.4 Eq. dscrt_gt with eps = h^2)
+//   K'  :    sum_j (D2_ij/eps) exp(-D2_ij/eps) V[j, c]             (eps dK/deps, for the gradient path)
+//
+// Three arithmetic forms:
+//   FP64  direct differences, FP64 exp written from its Cody-Waite reduction and Taylor series.
+//   FP32  direct differences on coordinates pre-scaled by sqrt(log2 e / eps), hardware exp2.
+//   MIXED the exp2 argument q_ij = -log2(e) ||t_i - s_j||^2 / eps comes straight out of one
+//         v_mfma_f32_16x16x32_bf16 per 32-wide K chunk: both operands are 3-way BF16 splits of
+//         the centred coordinates (hi/mid/lo, six cross products) plus the split row norms, so the
+//         MFMA's FP32 accumulation yields q without any VALU work; the VALU then does only
+//         exp2 and one FMA with v per pair.
+// Sources are split across the grid's y dimension; every block writes FP64 partial sums which a
+// finishing kernel adds in a fixed order (deterministic), together with the ridge term.
+#include "kmv.h"
+#include "kmv_dispatch.h"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+namespace krr {
+
+// ------------------------------------------------------------------ dims / variants
+int padded_dim(int d) {
+  static const int widths[] = {2, 3, 4, 6, 8, 16, 32, 64, 128};   // instantiated kernel widths
+  for (int w : widths)
+    if (d <= w) return w;
+  return -1;
+}
+int mixed_chunks(int d) {
+  static const int chunks[] = {1, 2, 3, 4, 6, 8, 13, 25};            // instantiated chunk counts
+  const int need = (int)ceil_div(6 * d + 6, 32);
+  for (int c : chunks)
+    if (need <= c) return c;
+  return -1;
+}
+
+// ------------------------------------------------------------------ staging kernels
+__global__ void k_point_sum(const double* __restrict__ X, int64_t n, int d, double* __restrict__ out) {
+  // one block per dimension, fixed-order tree reduction
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += X[i * d + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0] / (double)n;
+}
+
+__global__ void k_zero_tail(double* p, int from, int to) {
+  int i = from + threadIdx.x;
+  if (i < to) p[i] = 0.0;
+}
+
+void point_mean(const double* X, int64_t n, int d, int dpad, double* center, hipStream_t s) {
+  hipLaunchKernelGGL(k_point_sum, dim3(d), dim3(256), 0, s, X, n, d, center);
+  KRR_LAUNCH_CHECK();
+  if (dpad > d) {
+    hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(128), 0, s, center, d, dpad);
+    KRR_LAUNCH_CHECK();
+  }
+}
+
+__global__ void k_stage_f64(const double* __restrict__ X, int64_t n, int d, int64_t npad, int dpad,
+                            double* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npad * dpad) return;
+  int64_t i = idx / dpad;
+  int k = (int)(idx % dpad);
+  out[idx] = (i < n && k < d) ? X[i * d + k] : 0.0;
+}
+
+__global__ void k_stage_f32(const double* __restrict__ X, int64_t n, int d, int64_t npad, int dpad,
+                            const double* __restrict__ center, double scale, float* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npad * dpad) return;
+  int64_t i = idx / dpad;
+  int k = (int)(idx % dpad);
+  out[idx] = (i < n && k < d) ? (float)((X[i * d + k] - center[k]) * scale) : 0.0f;
+}
+
+__device__ __forceinline__ uint16_t bf16_rn(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ double bf16_to_double(uint16_t h) {
+  return (double)__uint_as_float(((uint32_t)h) << 16);
+}
+// x = h + m + l with each part a BF16 number; the residual of each step is exact in FP64.
+__device__ __forceinline__ void split3(double x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  h = bf16_rn((float)x);
+  double r = x - bf16_to_double(h);
+  m = bf16_rn((float)r);
+  r -= bf16_to_double(m);
+  l = bf16_rn((float)r);
+}
+
+// Split vectors for the MFMA cross term.  z = x - center, c = log2(e)/eps.
+//   target side a: [2c z]h [2c z]h [2c z]m [2c z]h [2c z]l [2c z]m | nh nm nl 1 1 1 | 0...
+//   source side b: [z]h    [z]m    [z]h    [z]l    [z]h    [z]m    | 1 1 1 nh nm nl | 0...
+// with n = -c ||z||^2 split into three parts.  sum_k a_k b_k = -c ||z_t - z_s||^2 up to the
+// dropped m*l, l*m, l*l products (relative size below 2^-24).
+__global__ void k_stage_split(const double* __restrict__ X, int64_t n, int d, int64_t npad, int ka,
+                              const double* __restrict__ center, double c, int side,
+                              uint16_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  uint16_t* o = out + i * ka;
+  for (int k = 0; k < ka; ++k) o[k] = 0;
+  if (i >= n) return;
+  const uint16_t one = 0x3F80;   // 1.0 in BF16
+  double nz = 0;
+  for (int k = 0; k < d; ++k) {
+    double z = X[i * d + k] - center[k];
+    nz += z * z;
+    double zz = side == 0 ? 2.0 * c * z : z;
+    uint16_t h, m, l;
+    split3(zz, h, m, l);
+    if (side == 0) {
+      o[0 * d + k] = h; o[1 * d + k] = h; o[2 * d + k] = m;
+      o[3 * d + k] = h; o[4 * d + k] = l; o[5 * d + k] = m;
+    } else {
+      o[0 * d + k] = h; o[1 * d + k] = m; o[2 * d + k] = h;
+      o[3 * d + k] = l; o[4 * d + k] = h; o[5 * d + k] = m;
+    }
+  }
+  uint16_t h, m, l;
+  split3(-c * nz, h, m, l);
+  const int base = 6 * d;
+  if (side == 0) {
+    o[base + 0] = h; o[base + 1] = m; o[base + 2] = l;
+    o[base + 3] = one; o[base + 4] = one; o[base + 5] = one;
+  } else {
+    o[base + 0] = one; o[base + 1] = one; o[base + 2] = one;
+    o[base + 3] = h; o[base + 4] = m; o[base + 5] = l;
+  }
+}
+
+void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int prec,
+                  const double* center, bool as_target, bool as_source, hipStream_t s) {
+  st.n = n;
+  st.d = d;
+  st.npad = round_up(n, kRowPad);
+  st.dpad = padded_dim(d);
+  st.prec = prec;
+  st.eps = eps;
+  KRR_REQUIRE(st.dpad > 0, "d exceeds KRR_MAX_D");
+  const int64_t tot = st.npad * st.dpad;
+  const int blk = 256;
+  if (prec == KRR_FP64) {
+    st.x64.alloc(tot, s);
+    hipLaunchKernelGGL(k_stage_f64, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
+                       st.x64.p);
+    KRR_LAUNCH_CHECK();
+  } else if (prec == KRR_FP32) {
+    st.x32.alloc(tot, s);
+    const double scale = std::sqrt(kLog2e / eps);
+    hipLaunchKernelGGL(k_stage_f32, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
+                       center, scale, st.x32.p);
+    KRR_LAUNCH_CHECK();
+  } else {
+    st.ka = 32 * mixed_chunks(d);
+    const double c = kLog2e / eps;
+    if (as_target) {
+      st.sa.alloc(st.npad * st.ka, s);
+      hipLaunchKernelGGL(k_stage_split, dim3(ceil_div(st.npad, blk)), dim3(blk), 0, s, X, n, d, st.npad,
+                         st.ka, center, c, 0, st.sa.p);
+      KRR_LAUNCH_CHECK();
+    }
+    if (as_source) {
+      st.sb.alloc(st.npad * st.ka, s);
+      hipLaunchKernelGGL(k_stage_split, dim3(ceil_div(st.npad, blk)), dim3(blk), 0, s, X, n, d, st.npad,
+                         st.ka, center, c, 1, st.sb.p);
+      KRR_LAUNCH_CHECK();
+    }
+  }
+}
+
+__global__ void k_stage_vec(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rp,
+                            double* __restrict__ o64, float* __restrict__ o32) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npad * Rp) return;
+  int64_t i = idx / Rp;
+  int c = (int)(idx % Rp);
+  double v = (i < n && c < R) ? V[i * R + c] : 0.0;
+  if (o64) o64[idx] = v;
+  if (o32) o32[idx] = (float)v;
+}
+
+void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
+                   hipStream_t s) {
+  sv.npad = npad;
+  sv.Rreal = R;
+  sv.R = (int)round_up(R, 8);   // column chunks are at most 8 wide
+  const int64_t tot = npad * sv.R;
+  if (prec == KRR_FP64) sv.v64.alloc(tot, s);
+  else sv.v32.alloc(tot, s);
+  hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R,
+                     sv.v64.p, sv.v32.p);
+  KRR_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ finishing kernel
+// U[i, oc] = sum_s part[s, i, pc] (+ shift[oc] * Vraw[i, oc] on K columns), where the part row holds
+// the K columns at [0, Rp) and the K' columns at [Rp, 2 Rp).
+struct ShiftArg {
+  double v[256];
+};
+
+__global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpad, int Rp, int Rout,
+                             int deriv, int64_t m, int R, int has_shift, ShiftArg sh,
+                             const double* __restrict__ Vraw, double* __restrict__ U, int64_t ldu) {
+  const int Rcols = deriv == 2 ? 2 * R : R;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * Rcols) return;
+  const int64_t i = idx / Rcols;
+  const int oc = (int)(idx % Rcols);
+  int pc;
+  bool kcol;
+  if (deriv == 0) { pc = oc; kcol = true; }
+  else if (deriv == 1) { pc = Rp + oc; kcol = false; }
+  else { kcol = oc < R; pc = kcol ? oc : Rp + (oc - R); }
+  double acc = 0;
+  for (int p = 0; p < S; ++p) acc += part[((int64_t)p * mpad + i) * Rout + pc];
+  if (has_shift && kcol) acc += sh.v[oc] * Vraw[i * R + oc];
+  U[i * ldu + oc] = acc;
+}
+
+// ------------------------------------------------------------------ variants and launcher
+namespace {
+std::mutex g_mu;
+std::map<std::string, int> g_override;   // "prec:d:R" -> variant
+std::string vkey(int d, int R, int prec) {
+  std::ostringstream o;
+  o << prec << ":" << d << ":" << (R > 1 ? 2 : 1);
+  return o.str();
+}
+const int kTM[3] = {1, 2, 4};
+const int kNF[4] = {1, 2, 4, 8};
+}  // namespace
+
+int kmv_num_variants(int prec, int) { return prec == KRR_MIXED ? 4 : 3; }
+
+int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t) {
+  if (prec == KRR_MIXED) return mixed_max_nf(mixed_chunks(d)) >= 8 ? 3 : 1;
+  if (padded_dim(d) >= 32) return 0;
+  return m >= 65536 ? 1 : 0;
+}
+
+void kmv_set_override(int d, int R, int prec, int variant) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (variant < 0) g_override.erase(vkey(d, R, prec));
+  else g_override[vkey(d, R, prec)] = variant;
+}
+
+int kmv_get_override(int d, int R, int prec) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_override.find(vkey(d, R, prec));
+  return it == g_override.end() ? -1 : it->second;
+}
+
+std::string kmv_table_json() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::ostringstream o;
+  o << "{\"arch\": \"gfx950\", \"variants\": {";
+  bool first = true;
+  for (auto& kv : g_override) {
+    o << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  o << "}}\n";
+  return o.str();
+}
+
+void kmv_table_from_json(const std::string& s) {
+  // minimal parser for the format written above: "p:d:r": v pairs inside "variants"
+  size_t pos = s.find("\"variants\"");
+  KRR_REQUIRE(pos != std::string::npos, "autotune table: no variants object");
+  std::lock_guard<std::mutex> lk(g_mu);
+  while (true) {
+    size_t q1 = s.find('"', s.find_first_of("{,", pos + 1) + 0);
+    if (q1 == std::string::npos) break;
+    size_t q2 = s.find('"', q1 + 1);
+    size_t colon = s.find(':', q2);
+    if (q2 == std::string::npos || colon == std::string::npos) break;
+    std::string key = s.substr(q1 + 1, q2 - q1 - 1);
+    int val = std::atoi(s.c_str() + colon + 1);
+    if (std::count(key.begin(), key.end(), ':') == 2) g_override[key] = val;
+    pos = colon;
+    if (s.find_first_of(",", pos) == std::string::npos) break;
+    pos = s.find_first_of(",", pos);
+  }
+}
+
+void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv, const double* shift_host,
+                const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant) {
+  KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
+  const int R = V.Rreal, Rp = V.R;
+  KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
+  const int DV = deriv == 0 ? 0 : 2;
+  const int Rout = (DV == 2 ? 2 : 1) * Rp;
+  if (variant < 0) variant = kmv_get_override(T.d, R, prec);
+  if (variant < 0) variant = kmv_default_variant(prec, T.d, R, T.n, S.n);
+  KRR_REQUIRE(variant < kmv_num_variants(prec, R), "unknown kernel variant");
+  int64_t rows;
+  int gz, TM = 1, NF = 1, RC = R == 1 ? 1 : R <= 4 ? 4 : 8;
+  const int D = T.dpad;
+  if (prec == KRR_MIXED) {
+    NF = std::min(kNF[variant], mixed_max_nf(T.ka / 32));
+    rows = 64 * NF;
+    gz = 1;
+  } else {
+    TM = D >= 32 ? 1 : kTM[variant];
+    rows = 256 * TM;
+    gz = Rp / RC;
+  }
+  const int64_t gx = T.npad / rows;
+  const int64_t nsrc = S.npad;
+  int64_t split = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, gx * gz), nsrc / 256));
+  const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
+  split = ceil_div(nsrc, src_len);
+  DevBuf<double> part(split * T.npad * Rout, s);
+  KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, Rp, Rout};
+  bool ok = true;
+  if (prec == KRR_FP64) {
+    ok = launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, 1.0 / T.eps, part.p, s);
+  } else if (prec == KRR_FP32) {
+    ok = launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
+  } else {
+    for (int c = 0; c < R && ok; ++c) {
+      ok = launch_kmv_mixed(T.ka / 32, NF, DV, g, T.sa.p, S.sb.p, V.v32.p, c, part.p, s);
+      KRR_LAUNCH_CHECK();
+    }
+  }
+  KRR_REQUIRE(ok, "kernel variant not instantiated for this shape");
+  KRR_LAUNCH_CHECK();
+  ShiftArg sh{};
+  const int has_shift = shift_host != nullptr;
+  if (has_shift)
+    for (int c = 0; c < R; ++c) sh.v[c] = shift_host[c];
+  const int Rcols = deriv == 2 ? 2 * R : R;
+  const int64_t tot = T.n * Rcols;
+  hipLaunchKernelGGL(k_kmv_finish, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, part.p, (int)split,
+                     T.npad, Rp, Rout, deriv, T.n, R, has_shift, sh, Vraw, U, ldu);
+  KRR_LAUNCH_CHECK();
+}
+
+}  // namespace krr

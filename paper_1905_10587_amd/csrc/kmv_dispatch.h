@@ -1,0 +1,26 @@
+// Launch entry points of the per-precision kernel instantiations.
+#pragma once
+
+#include "kmv.h"
+
+namespace krr {
+
+struct KmvGrid {
+  dim3 grid;
+  int64_t src_len, n_src, mpad;
+  int Rp, Rout;
+};
+
+// FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),
+// RC in {1,4,8}, DV in {0,2}.  Return false if the combination is not instantiated.
+bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
+                    const double* v, double inv_eps, double* part, hipStream_t s);
+bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,
+                    const float* v, double* part, hipStream_t s);
+// MFMA kernel (one column per launch): NCH in {1,2,3,4,6,8,13,25}, NF in {1,2,4,8} (limited by NCH),
+// DV in {0,2}.
+bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+                      const float* v, int col, double* part, hipStream_t s);
+int mixed_max_nf(int nch);
+
+}  // namespace krr

@@ -1,0 +1,40 @@
+// FP64 direct-difference kernel instantiations.
+#include "kmv_dispatch.h"
+#include "kmv_kernels.h"
+
+namespace krr {
+
+template <int D, int TM, int RC, int DV>
+static void go64(const KmvGrid& g, const double* xt, const double* xs, const double* v, double inv_eps,
+                 double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_kmv_f64<D, TM, RC, DV>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
+                     inv_eps, part, g.mpad, g.Rout);
+}
+
+#define KRR_DV(D, TM, RC)                                   \
+  if (DV == 0) { go64<D, TM, RC, 0>(g, xt, xs, v, inv_eps, part, s); return true; } \
+  if (DV == 2) { go64<D, TM, RC, 2>(g, xt, xs, v, inv_eps, part, s); return true; }
+#define KRR_RC(D, TM) \
+  if (RC == 1) { KRR_DV(D, TM, 1) } if (RC == 4) { KRR_DV(D, TM, 4) } if (RC == 8) { KRR_DV(D, TM, 8) }
+#define KRR_TM3(D) \
+  if (TM == 1) { KRR_RC(D, 1) } if (TM == 2) { KRR_RC(D, 2) } if (TM == 4) { KRR_RC(D, 4) }
+#define KRR_TM1(D) \
+  if (TM == 1) { KRR_RC(D, 1) }
+
+bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
+                    const double* v, double inv_eps, double* part, hipStream_t s) {
+  switch (D) {
+    case 2: KRR_TM3(2) break;
+    case 3: KRR_TM3(3) break;
+    case 4: KRR_TM3(4) break;
+    case 6: KRR_TM3(6) break;
+    case 8: KRR_TM3(8) break;
+    case 16: KRR_TM3(16) break;
+    case 32: KRR_TM1(32) break;
+    case 64: KRR_TM1(64) break;
+    case 128: KRR_TM1(128) break;
+  }
+  return false;
+}
+
+}  // namespace krr

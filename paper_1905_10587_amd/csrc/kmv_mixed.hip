@@ -1,0 +1,44 @@
+// Split-BF16 MFMA kernel instantiations.
+#include "kmv_dispatch.h"
+#include "kmv_kernels.h"
+
+namespace krr {
+
+int mixed_max_nf(int nch) { return nch <= 2 ? 8 : nch <= 4 ? 4 : nch <= 8 ? 2 : 1; }
+
+template <int NCH, int NF, int DV>
+static void gom(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const float* v, int col, double* part,
+                hipStream_t s) {
+  hipLaunchKernelGGL((k_kmv_mixed<NCH, NF, DV>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), v, g.Rp, col, g.src_len, g.n_src, part, g.mpad, g.Rout,
+                     col);
+}
+
+#define KRR_MDV(NCH, NF)                                                        \
+  if (DV == 0) { gom<NCH, NF, 0>(g, A, B, v, col, part, s); return true; }   \
+  if (DV == 2) { gom<NCH, NF, 2>(g, A, B, v, col, part, s); return true; }
+#define KRR_NF8(NCH) \
+  if (NF == 1) { KRR_MDV(NCH, 1) } if (NF == 2) { KRR_MDV(NCH, 2) } if (NF == 4) { KRR_MDV(NCH, 4) } if (NF == 8) { KRR_MDV(NCH, 8) }
+#define KRR_NF4(NCH) \
+  if (NF == 1) { KRR_MDV(NCH, 1) } if (NF == 2) { KRR_MDV(NCH, 2) } if (NF == 4) { KRR_MDV(NCH, 4) }
+#define KRR_NF2(NCH) \
+  if (NF == 1) { KRR_MDV(NCH, 1) } if (NF == 2) { KRR_MDV(NCH, 2) }
+#define KRR_NF1(NCH) \
+  if (NF == 1) { KRR_MDV(NCH, 1) }
+
+bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+                      const float* v, int col, double* part, hipStream_t s) {
+  switch (NCH) {
+    case 1: KRR_NF8(1) break;
+    case 2: KRR_NF8(2) break;
+    case 3: KRR_NF4(3) break;
+    case 4: KRR_NF4(4) break;
+    case 6: KRR_NF2(6) break;
+    case 8: KRR_NF2(8) break;
+    case 13: KRR_NF1(13) break;
+    case 25: KRR_NF1(25) break;
+  }
+  return false;
+}
+
+}  // namespace krr
