@@ -1,0 +1,102 @@
+// C ABI: kernel-variant control and the tile-shape autotuner (the table consulted by every kernel MVM
+// launch).  The autotuner times each variant of (d, R, prec) on synthetic points with HIP events and
+// keeps the fastest; the table can be saved and loaded as JSON.
+#include <fstream>
+#include <sstream>
+
+#include "kmv.h"
+
+namespace krr {
+
+// splitmix64-based uniform numbers in [0, 1) (synthetic timing inputs only)
+__global__ void k_fill_uniform(double* __restrict__ a, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  a[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace krr
+
+extern "C" int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t variant) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(d >= 1 && d <= KRR_MAX_D, "d must be in [1, KRR_MAX_D]");
+    KRR_REQUIRE(prec >= KRR_FP64 && prec <= KRR_MIXED, "unknown precision");
+    KRR_REQUIRE(variant < krr::kmv_num_variants(prec, R), "variant out of range");
+    krr::kmv_set_override(d, R, prec, variant);
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_num_variants(int32_t prec, int32_t R) { return krr::kmv_num_variants(prec, R); }
+
+extern "C" int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32_t* best_variant, void* stream) {
+  using namespace krr;
+  return guarded([&] {
+    KRR_REQUIRE(d >= 1 && d <= KRR_MAX_D, "d must be in [1, KRR_MAX_D]");
+    KRR_REQUIRE(prec >= KRR_FP64 && prec <= KRR_MIXED, "unknown precision");
+    KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
+    KRR_REQUIRE(n >= 1024 && n <= (int64_t)1 << 26, "n must be in [1024, 2^26]");
+    KRR_REQUIRE(best_variant != nullptr, "best_variant must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<double> X(n * d, s), V(n * R, s), U(n * R, s);
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, X.p, n * d, 1234ull);
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, V.p, n * R, 99ull);
+    KRR_LAUNCH_CHECK();
+    const double eps = 0.05 * d;
+    const int dpad = padded_dim(d);
+    DevBuf<double> center(dpad, s);
+    point_mean(X.p, n, d, dpad, center.p, s);
+    Staged S;
+    stage_points(S, X.p, n, d, eps, prec, center.p, true, true, s);
+    StagedVec SV;
+    stage_vectors(SV, V.p, n, S.npad, R, prec, s);
+    DevBuf<double> ws;
+    hipEvent_t e0, e1;
+    KRR_CHECK_HIP(hipEventCreate(&e0));
+    KRR_CHECK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestv = 0;
+    const int nv = kmv_num_variants(prec, R);
+    for (int v = 0; v < nv; ++v) {
+      kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws);   // warm-up
+      KRR_CHECK_HIP(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep) kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws);
+      KRR_CHECK_HIP(hipEventRecord(e1, s));
+      KRR_CHECK_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      KRR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; bestv = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    kmv_set_override(d, R, prec, bestv);
+    *best_variant = bestv;
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_autotune_save(const char* path) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(path != nullptr, "path must not be NULL");
+    std::ofstream f(path);
+    KRR_REQUIRE(f.good(), std::string("cannot open ") + path);
+    f << krr::kmv_table_json();
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_autotune_load(const char* path) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(path != nullptr, "path must not be NULL");
+    std::ifstream f(path);
+    KRR_REQUIRE(f.good(), std::string("cannot open ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    krr::kmv_table_from_json(ss.str());
+    return (int)KRR_OK;
+  });
+}

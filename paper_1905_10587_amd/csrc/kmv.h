@@ -54,7 +54,7 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
 //   Vraw: the original FP64 V (n x R) for the shift term.
 void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
                 const double* shift_host, const double* Vraw, int prec, double* U, int64_t ldu,
-                hipStream_t s, int variant = -1);
+                hipStream_t s, int variant = -1, DevBuf<double>* ws = nullptr);
 
 // Variant bookkeeping for the autotuner.
 int kmv_num_variants(int prec, int R);

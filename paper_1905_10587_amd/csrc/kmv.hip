@@ -17,6 +17,7 @@
 #include "kmv_dispatch.h"
 
 #include <algorithm>
+#include <cctype>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -201,8 +202,11 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
   sv.Rreal = R;
   sv.R = (int)round_up(R, 8);   // column chunks are at most 8 wide
   const int64_t tot = npad * sv.R;
-  if (prec == KRR_FP64) sv.v64.alloc(tot, s);
-  else sv.v32.alloc(tot, s);
+  if (prec == KRR_FP64) {
+    if (sv.v64.n != (size_t)tot) sv.v64.alloc(tot, s);
+  } else {
+    if (sv.v32.n != (size_t)tot) sv.v32.alloc(tot, s);
+  }
   hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R,
                      sv.v64.p, sv.v32.p);
   KRR_LAUNCH_CHECK();
@@ -281,27 +285,34 @@ std::string kmv_table_json() {
 }
 
 void kmv_table_from_json(const std::string& s) {
-  // minimal parser for the format written above: "p:d:r": v pairs inside "variants"
+  // entries are "prec:d:r": variant pairs inside the "variants" object
   size_t pos = s.find("\"variants\"");
   KRR_REQUIRE(pos != std::string::npos, "autotune table: no variants object");
-  std::lock_guard<std::mutex> lk(g_mu);
-  while (true) {
-    size_t q1 = s.find('"', s.find_first_of("{,", pos + 1) + 0);
-    if (q1 == std::string::npos) break;
-    size_t q2 = s.find('"', q1 + 1);
-    size_t colon = s.find(':', q2);
-    if (q2 == std::string::npos || colon == std::string::npos) break;
-    std::string key = s.substr(q1 + 1, q2 - q1 - 1);
-    int val = std::atoi(s.c_str() + colon + 1);
-    if (std::count(key.begin(), key.end(), ':') == 2) g_override[key] = val;
-    pos = colon;
-    if (s.find_first_of(",", pos) == std::string::npos) break;
-    pos = s.find_first_of(",", pos);
+  pos = s.find('{', pos);
+  KRR_REQUIRE(pos != std::string::npos, "autotune table: malformed variants object");
+  std::map<std::string, int> parsed;
+  size_t i = pos + 1;
+  while (i < s.size() && s[i] != '}') {
+    if (s[i] != '"') { ++i; continue; }
+    const size_t q2 = s.find('"', i + 1);
+    KRR_REQUIRE(q2 != std::string::npos, "autotune table: unterminated key");
+    const std::string key = s.substr(i + 1, q2 - i - 1);
+    size_t j = q2 + 1;
+    while (j < s.size() && (s[j] == ' ' || s[j] == ':')) ++j;
+    size_t e = j;
+    while (e < s.size() && (std::isdigit((unsigned char)s[e]) || s[e] == '-')) ++e;
+    KRR_REQUIRE(e > j, "autotune table: missing value for " + key);
+    KRR_REQUIRE(std::count(key.begin(), key.end(), ':') == 2, "autotune table: bad key " + key);
+    parsed[key] = std::atoi(s.substr(j, e - j).c_str());
+    i = e;
   }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : parsed) g_override[kv.first] = kv.second;
 }
 
 void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv, const double* shift_host,
-                const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant) {
+                const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant,
+                DevBuf<double>* ws) {
   KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
   const int R = V.Rreal, Rp = V.R;
   KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
@@ -320,14 +331,17 @@ void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
   } else {
     TM = D >= 32 ? 1 : kTM[variant];
     rows = 256 * TM;
-    gz = Rp / RC;
+    gz = (int)ceil_div(R, RC);   // real columns only (Rp is padded to 8)
   }
   const int64_t gx = T.npad / rows;
   const int64_t nsrc = S.npad;
   int64_t split = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, gx * gz), nsrc / 256));
   const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
   split = ceil_div(nsrc, src_len);
-  DevBuf<double> part(split * T.npad * Rout, s);
+  DevBuf<double> own;
+  DevBuf<double>& part = ws ? *ws : own;
+  const size_t need = (size_t)split * T.npad * Rout;
+  if (part.n < need) part.alloc(need, s);
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, Rp, Rout};
   bool ok = true;
   if (prec == KRR_FP64) {

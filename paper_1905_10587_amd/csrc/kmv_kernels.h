@@ -36,15 +36,25 @@ __device__ __forceinline__ double exp_neg_f64(double t) {
   return t < 708.0 ? res : 0.0;
 }
 
-// ------------------------------------------------------------------ FP64 direct kernel
-// Block: 256 threads, each owns TM targets (strided by 256) and RC columns.  Source coordinates
-// and weights are wave-uniform (scalar loads); grid.y splits the sources, grid.z the columns.
+// ------------------------------------------------------------------ direct kernels (FP64 / FP32)
+// Block: 256 threads, each owns TM targets (strided by 256) and RC columns.  Sources stream through
+// LDS in tiles of TS points (coalesced cooperative loads); every wave then reads a source's
+// coordinates and weights with one wave-uniform (broadcast) LDS access.  grid.y splits the sources,
+// grid.z the column chunks.
+template <int D>
+struct DirectTile {
+  static constexpr int TS = D <= 16 ? 256 : (D <= 32 ? 128 : 64);
+};
+
 template <int D, int TM, int RC, int DV>
 __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, const double* __restrict__ xs,
                                                  const double* __restrict__ v, int Rp, int64_t src_len,
                                                  int64_t n_src, double inv_eps, double* __restrict__ part,
                                                  int64_t mpad, int Rout) {
   constexpr int NO = DV == 2 ? 2 : 1;
+  constexpr int TS = DirectTile<D>::TS;
+  __shared__ double sx[TS * D];
+  __shared__ double sv[TS * RC];
   const int64_t ibase = (int64_t)blockIdx.x * (256 * TM) + threadIdx.x;
   const int c0 = blockIdx.z * RC;
   const int64_t jb = (int64_t)blockIdx.y * src_len;
@@ -61,31 +71,37 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
     for (int c = 0; c < RC; ++c)
 #pragma unroll
       for (int o = 0; o < NO; ++o) acc[t][c][o] = 0.0;
+  for (int64_t jt = jb; jt < je; jt += TS) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < TS * D; u += 256) sx[u] = xs[jt * D + u];
+    for (int u = threadIdx.x; u < TS * RC; u += 256) sv[u] = v[(jt + u / RC) * Rp + c0 + u % RC];
+    __syncthreads();
 #pragma unroll 2
-  for (int64_t j = jb; j < je; ++j) {
-    double xj[D], vj[RC];
+    for (int j = 0; j < TS; ++j) {
+      double xj[D], vj[RC];
 #pragma unroll
-    for (int k = 0; k < D; ++k) xj[k] = xs[j * D + k];
+      for (int k = 0; k < D; ++k) xj[k] = sx[j * D + k];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) vj[c] = v[j * Rp + c0 + c];
+      for (int c = 0; c < RC; ++c) vj[c] = sv[j * RC + c];
 #pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      double d2 = 0.0;
+      for (int t = 0; t < TM; ++t) {
+        double d2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const double df = xi[t][k] - xj[k];
-        d2 = __builtin_fma(df, df, d2);
-      }
-      const double tt = d2 * inv_eps;
-      const double e = exp_neg_f64(tt);
-      if (DV == 0 || DV == 2) {
+        for (int k = 0; k < D; ++k) {
+          const double df = xi[t][k] - xj[k];
+          d2 = __builtin_fma(df, df, d2);
+        }
+        const double tt = d2 * inv_eps;
+        const double e = exp_neg_f64(tt);
+        if (DV == 0 || DV == 2) {
 #pragma unroll
-        for (int c = 0; c < RC; ++c) acc[t][c][0] = __builtin_fma(e, vj[c], acc[t][c][0]);
-      }
-      if (DV >= 1) {
-        const double ed = tt * e;
+          for (int c = 0; c < RC; ++c) acc[t][c][0] = __builtin_fma(e, vj[c], acc[t][c][0]);
+        }
+        if (DV >= 1) {
+          const double ed = tt * e;
 #pragma unroll
-        for (int c = 0; c < RC; ++c) acc[t][c][NO - 1] = __builtin_fma(ed, vj[c], acc[t][c][NO - 1]);
+          for (int c = 0; c < RC; ++c) acc[t][c][NO - 1] = __builtin_fma(ed, vj[c], acc[t][c][NO - 1]);
+        }
       }
     }
   }
@@ -101,15 +117,17 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
   }
 }
 
-// ------------------------------------------------------------------ FP32 direct kernel
-// Coordinates are pre-scaled so that q = -||t'-s'||^2 is the exp2 argument.  Per pair: D subs,
-// D FMAs, one v_exp_f32, RC FMAs.  FP32 partial sums are folded into FP64 every 256 sources.
+// FP32 form: coordinates pre-scaled so that q = -||t'-s'||^2 is the exp2 argument.  Per pair: D subs,
+// D FMAs, one v_exp_f32, RC FMAs.  FP32 partial sums are folded into FP64 once per 256 sources.
 template <int D, int TM, int RC, int DV>
 __global__ __launch_bounds__(256) void k_kmv_f32(const float* __restrict__ xt, const float* __restrict__ xs,
                                                  const float* __restrict__ v, int Rp, int64_t src_len,
                                                  int64_t n_src, double* __restrict__ part, int64_t mpad,
                                                  int Rout) {
   constexpr int NO = DV == 2 ? 2 : 1;
+  constexpr int TS = 256;
+  __shared__ float sx[TS * D];
+  __shared__ float sv[TS * RC];
   const int64_t ibase = (int64_t)blockIdx.x * (256 * TM) + threadIdx.x;
   const int c0 = blockIdx.z * RC;
   const int64_t jb = (int64_t)blockIdx.y * src_len;
@@ -127,7 +145,11 @@ __global__ __launch_bounds__(256) void k_kmv_f32(const float* __restrict__ xt, c
 #pragma unroll
       for (int o = 0; o < NO; ++o) acc[t][c][o] = 0.0;
   constexpr float kLn2f = 0.69314718055994531f;
-  for (int64_t j0 = jb; j0 < je; j0 += 256) {
+  for (int64_t jt = jb; jt < je; jt += TS) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < TS * D; u += 256) sx[u] = xs[jt * D + u];
+    for (int u = threadIdx.x; u < TS * RC; u += 256) sv[u] = v[(jt + u / RC) * Rp + c0 + u % RC];
+    __syncthreads();
     float a32[TM][RC][NO];
 #pragma unroll
     for (int t = 0; t < TM; ++t)
@@ -136,12 +158,12 @@ __global__ __launch_bounds__(256) void k_kmv_f32(const float* __restrict__ xt, c
 #pragma unroll
         for (int o = 0; o < NO; ++o) a32[t][c][o] = 0.0f;
 #pragma unroll 2
-    for (int64_t j = j0; j < j0 + 256; ++j) {
+    for (int j = 0; j < TS; ++j) {
       float xj[D], vj[RC];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xj[k] = xs[j * D + k];
+      for (int k = 0; k < D; ++k) xj[k] = sx[j * D + k];
 #pragma unroll
-      for (int c = 0; c < RC; ++c) vj[c] = v[j * Rp + c0 + c];
+      for (int c = 0; c < RC; ++c) vj[c] = sv[j * RC + c];
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
         float d2 = 0.0f;
@@ -218,6 +240,10 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
       for (int o = 0; o < NO; ++o) acc[f][e][o] = 0.0;
   constexpr float kNegLn2f = -0.69314718055994531f;
 
+  bf16x8 bn[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, B[(jb + r16) * KV + ch * 4 + kq]);
+  float vn = v[(jb + r16) * Rp + col];
   for (int64_t j0 = jb; j0 < je; j0 += 256) {
     float a32[NF][4][NO];
 #pragma unroll
@@ -227,10 +253,15 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
 #pragma unroll
         for (int o = 0; o < NO; ++o) a32[f][e][o] = 0.0f;
     for (int64_t j = j0; j < j0 + 256; j += 16) {
+      // the fragment for j was loaded one step ahead; issue the load for j + 16 now
       bf16x8 b[NCH];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) b[ch] = __builtin_bit_cast(bf16x8, B[(j + r16) * KV + ch * 4 + kq]);
-      const float vj = v[(j + r16) * Rp + col];
+      for (int ch = 0; ch < NCH; ++ch) b[ch] = bn[ch];
+      const float vj = vn;
+      const int64_t jn = j + 16 < je ? j + 16 : j;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, B[(jn + r16) * KV + ch * 4 + kq]);
+      vn = v[(jn + r16) * Rp + col];
       f32x4 q[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) {

@@ -1,0 +1,461 @@
+// Preconditioned conjugate gradient for (K + beta_c I) alpha_c = y_c, c = 0..R-1 (Algorithm 5, Sec. 3).
+//
+// All R recurrences advance in lockstep and share one kernel MVM of the whole block per iteration
+// (multi-right-hand-side batching); every column keeps its own FP64 scalars (rho, gamma, beta) and is
+// frozen once its true relative residual reaches tol.  Vectors x, r, z, p, q are FP64, n x R
+// row-major.  The MVM runs in the working precision (FP64, FP32 or split-BF16 mixed); every
+// `replace_every` iterations, and whenever a column's recursive residual claims convergence, the
+// residual is recomputed as y - (K + beta I) x with the FP64 MVM (residual replacement).
+// Convergence is decided on the host from the R residual norms read back once per iteration.
+#include <chrono>
+#include <cstring>
+#include <memory>
+
+#include "kmv.h"
+#include "pcg.h"
+#include "precond.h"
+
+namespace krr {
+
+void validate_common(int64_t m, int64_t n, int32_t d, double eps);
+void validate_prec(int32_t prec);
+
+// ------------------------------------------------------------------ column reductions
+// Block: 256 threads = CB columns x (256/CB) rows.  Deterministic two-stage sum:
+// part[by * R + c] over row groups, then a fixed-order sum over by.
+constexpr int kRedBlocks = 256;
+
+template <int MODE>   // 0: sum a*b ; 1: sum a*a
+__global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, const double* __restrict__ b,
+                                                int64_t n, int R, int CB, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int cl = threadIdx.x % CB;
+  const int rl = threadIdx.x / CB;
+  const int rows_per = 256 / CB;
+  const int c = blockIdx.x * CB + cl;
+  double s = 0;
+  if (c < R) {
+    for (int64_t i = (int64_t)blockIdx.y * rows_per + rl; i < n; i += (int64_t)gridDim.y * rows_per) {
+      const double u = a[i * R + c];
+      s = __builtin_fma(u, MODE == 1 ? u : b[i * R + c], s);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = rows_per / 2; w > 0; w >>= 1) {
+    if (rl < w) red[threadIdx.x] += red[threadIdx.x + w * CB];
+    __syncthreads();
+  }
+  if (rl == 0 && c < R) part[(int64_t)blockIdx.y * R + c] = red[threadIdx.x];
+}
+
+__global__ void k_colsum_final(const double* __restrict__ part, int nby, int R, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  double s = 0;
+  for (int b = 0; b < nby; ++b) s += part[(int64_t)b * R + c];
+  out[c] = s;
+}
+
+struct ColReducer {
+  DevBuf<double> part;
+  int R = 0, CB = 1;
+  void init(int R_, hipStream_t s) {
+    R = R_;
+    CB = 1;
+    while (CB * 2 <= R && CB < 64) CB *= 2;
+    part.alloc((size_t)kRedBlocks * R, s);
+  }
+  // out[c] = sum_i a[i,c] * b[i,c]  (b == nullptr: sum a^2)
+  void dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
+    dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
+    if (b) hipLaunchKernelGGL(k_coldot<0>, grid, dim3(256), 0, s, a, b, n, R, CB, part.p);
+    else hipLaunchKernelGGL(k_coldot<1>, grid, dim3(256), 0, s, a, a, n, R, CB, part.p);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, part.p, kRedBlocks, R, out);
+    KRR_LAUNCH_CHECK();
+  }
+};
+
+// ------------------------------------------------------------------ elementwise / scalar kernels
+// gamma_c = rho_c / (p^T q)_c for active columns (0 otherwise); flags a breakdown.
+__global__ void k_gamma(const double* __restrict__ rho, const double* __restrict__ pq, const int* __restrict__ active,
+                        int R, double* __restrict__ gamma, int* __restrict__ breakdown) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  double g = 0.0;
+  if (active[c]) {
+    const double d = pq[c];
+    if (!(d > 0.0) || !isfinite(d)) atomicOr(breakdown, 1);
+    else g = rho[c] / d;
+  }
+  gamma[c] = g;
+}
+
+// x += gamma p ; r -= gamma q
+__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                        const double* __restrict__ q, const double* __restrict__ gamma, int64_t n, int R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const double g = gamma[t % R];
+  x[t] = __builtin_fma(g, p[t], x[t]);
+  r[t] = __builtin_fma(-g, q[t], r[t]);
+}
+
+// r = y - q for active columns
+__global__ void k_residual(double* __restrict__ r, const double* __restrict__ y, const double* __restrict__ q,
+                           const int* __restrict__ active, int64_t n, int R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  if (active[t % R]) r[t] = y[t] - q[t];
+}
+
+// beta_c = rho_new_c / rho_c ; rho_c = rho_new_c (active columns)
+__global__ void k_beta(double* __restrict__ rho, const double* __restrict__ rho_new, const int* __restrict__ active,
+                       int R, double* __restrict__ beta) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  double b = 0.0;
+  if (active[c]) {
+    b = rho[c] != 0.0 ? rho_new[c] / rho[c] : 0.0;
+    rho[c] = rho_new[c];
+  }
+  beta[c] = b;
+}
+
+// p = z + beta p (active columns)
+__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ beta,
+                           const int* __restrict__ active, int64_t n, int R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int c = (int)(t % R);
+  if (active[c]) p[t] = __builtin_fma(beta[c], p[t], z[t]);
+}
+
+__global__ void k_copy_active(double* __restrict__ dst, const double* __restrict__ src,
+                              const int* __restrict__ active, int64_t n, int R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  if (active[t % R]) dst[t] = src[t];
+}
+
+__global__ void k_absmax_flag(const double* __restrict__ a, int64_t cnt, int* __restrict__ flag) {
+  int f = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    f |= a[i] != 0.0;
+  if (f) atomicOr(flag, 1);
+}
+
+static unsigned nb(int64_t n) { return (unsigned)ceil_div(n, 256); }
+
+// ------------------------------------------------------------------ solver
+struct EventTimer {
+  bool on;
+  hipStream_t s;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double* acc;
+  EventTimer(bool on_, hipStream_t s_) : on(on_), s(s_), acc(nullptr) {}
+  void start(double* where) {
+    if (!on) return;
+    hipEvent_t a, b;
+    KRR_CHECK_HIP(hipEventCreate(&a));
+    KRR_CHECK_HIP(hipEventCreate(&b));
+    KRR_CHECK_HIP(hipEventRecord(a, s));
+    ev.push_back({a, b});
+    acc = where;
+    pending.push_back(where);
+  }
+  void stop() {
+    if (!on) return;
+    KRR_CHECK_HIP(hipEventRecord(ev.back().second, s));
+  }
+  // collect after a synchronise
+  void collect() {
+    for (size_t i = 0; i < ev.size(); ++i) {
+      float ms = 0;
+      KRR_CHECK_HIP(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
+      *pending[i] += ms;
+      (void)hipEventDestroy(ev[i].first);
+      (void)hipEventDestroy(ev[i].second);
+    }
+    ev.clear();
+    pending.clear();
+  }
+  std::vector<double*> pending;
+  ~EventTimer() {
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
+};
+
+// Staged operator (K + beta I) on one point set in one precision.
+struct Operator {
+  Staged S;
+  StagedVec V;
+  DevBuf<double> ws;
+  int prec = KRR_FP64;
+  const double* X = nullptr;
+  int64_t n = 0;
+  int R = 0;
+  void init(const double* X_, int64_t n_, int d, double eps, int prec_, const double* center, int R_, hipStream_t s) {
+    X = X_;
+    n = n_;
+    prec = prec_;
+    R = R_;
+    stage_points(S, X, n, d, eps, prec, center, true, true, s);
+  }
+  // out = (K + diag(shift)) v   (shift may be null)
+  void apply(const double* v, const double* shift, double* out, hipStream_t s) {
+    stage_vectors(V, v, n, S.npad, R, prec, s);
+    kmv_launch(S, S, V, 0, shift, v, prec, out, R, s, -1, &ws);
+  }
+};
+
+PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double* Y, int R, const double* betas,
+                    const krr_precond* P, double tol, int maxit, int replace_every, int prec, double* x,
+                    bool timing, hipStream_t s) {
+  using clk = std::chrono::steady_clock;
+  const auto t_start = clk::now();
+  PcgResult res;
+  res.iters.assign(R, 0);
+  res.relres.assign(R, 0.0);
+  std::vector<int> bidx(R, 0);
+  if (P) {
+    for (int c = 0; c < R; ++c) {
+      bidx[c] = beta_index(*P, betas[c]);
+      KRR_REQUIRE(bidx[c] >= 0, "a column's beta is not among the preconditioner's betas");
+    }
+    KRR_REQUIRE(P->n == n && P->d == d && P->eps == eps, "preconditioner was built for a different problem");
+    KRR_REQUIRE(prec == KRR_FP64 || P->W32.p, "FP32/mixed solve needs a preconditioner built with FP32 factors");
+  }
+  const int64_t nR = n * R;
+  const int dpad = padded_dim(d);
+  DevBuf<double> center(dpad, s);
+  point_mean(X, n, d, dpad, center.p, s);
+  Operator Aw, A64;
+  Aw.init(X, n, d, eps, prec, center.p, R, s);
+  Operator* Atrue = &Aw;
+  if (prec != KRR_FP64) {
+    A64.init(X, n, d, eps, KRR_FP64, center.p, R, s);
+    Atrue = &A64;
+  }
+  DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s);
+  DevBuf<double> sc(8 * (size_t)R, s);   // rho, pq, gamma, beta, rr, rho_new, yy, spare
+  double* rho = sc.p;
+  double* pq = sc.p + R;
+  double* gamma = sc.p + 2 * R;
+  double* beta = sc.p + 3 * R;
+  double* rr = sc.p + 4 * R;
+  double* rho_new = sc.p + 5 * R;
+  double* yy = sc.p + 6 * R;
+  DevBuf<int> active(R, s), flags(2, s);
+  ColReducer red;
+  red.init(R, s);
+  std::vector<int> act(R, 1);
+  std::vector<double> h(3 * (size_t)R);
+  EventTimer tm(timing, s);
+
+  // ||y_c||
+  red.dot(Y, nullptr, n, yy, s);
+  std::vector<double> ynorm(R);
+  KRR_CHECK_HIP(hipMemcpyAsync(h.data(), yy, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < R; ++c) {
+    ynorm[c] = std::sqrt(h[c]);
+    if (!(ynorm[c] > 0)) act[c] = 0;
+  }
+  KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+  // zero-rhs columns: alpha = 0
+  // initial residual r = y - (K + beta I) x0 (FP64), skipped for a zero initial guess
+  KRR_CHECK_HIP(hipMemsetAsync(flags.p, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(k_absmax_flag, dim3(std::min<unsigned>(nb(nR), 2048)), dim3(256), 0, s, x, nR, flags.p);
+  int hflags[2];
+  KRR_CHECK_HIP(hipMemcpyAsync(hflags, flags.p, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  if (hflags[0]) {
+    tm.start(&res.st.t_mvm_fp64_ms);
+    Atrue->apply(x, betas, q.p, s);
+    tm.stop();
+    res.st.n_mvm_fp64++;
+    KRR_CHECK_HIP(hipMemcpyAsync(r.p, Y, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+  } else {
+    KRR_CHECK_HIP(hipMemcpyAsync(r.p, Y, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+  }
+  auto precondition = [&](const double* in, double* out) {
+    if (P) {
+      tm.start(&res.st.t_precond_ms);
+      woodbury_apply(*P, in, R, bidx.data(), prec != KRR_FP64, out, s);
+      tm.stop();
+    } else {
+      KRR_CHECK_HIP(hipMemcpyAsync(out, in, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+    }
+  };
+  precondition(r.p, z.p);
+  KRR_CHECK_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+  red.dot(r.p, z.p, n, rho, s);
+
+  std::vector<double> lanczos_g, lanczos_b;
+  bool any_active = false;
+  for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
+  int it = 0;
+  bool breakdown = false;
+  while (any_active && it < maxit) {
+    ++it;
+    // q = (K + beta I) p in the working precision
+    tm.start(&res.st.t_mvm_ms);
+    Aw.apply(p.p, betas, q.p, s);
+    tm.stop();
+    res.st.n_mvm++;
+    red.dot(p.p, q.p, n, pq, s);
+    hipLaunchKernelGGL(k_gamma, dim3(nb(R)), dim3(256), 0, s, rho, pq, active.p, R, gamma, flags.p + 1);
+    hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, p.p, q.p, gamma, n, R);
+    red.dot(r.p, nullptr, n, rr, s);
+    KRR_LAUNCH_CHECK();
+    KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipMemcpyAsync(h.data() + R, gamma, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipMemcpyAsync(hflags, flags.p, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    tm.collect();
+    if (hflags[1]) { breakdown = true; break; }
+    if (act[0]) lanczos_g.push_back(h[R]);
+    bool candidate = false;
+    for (int c = 0; c < R; ++c) {
+      if (!act[c]) continue;
+      res.iters[c] = it;
+      if (std::sqrt(h[c]) / ynorm[c] <= tol) candidate = true;
+    }
+    const bool scheduled = replace_every > 0 && it % replace_every == 0;
+    if (candidate || scheduled) {
+      // true residual in FP64 (replaces the recursive one)
+      tm.start(&res.st.t_mvm_fp64_ms);
+      Atrue->apply(x, betas, q.p, s);
+      tm.stop();
+      res.st.n_mvm_fp64++;
+      if (scheduled) res.st.n_replace++;
+      hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+      red.dot(r.p, nullptr, n, rr, s);
+      KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+      KRR_CHECK_HIP(hipStreamSynchronize(s));
+      tm.collect();
+      bool changed = false;
+      for (int c = 0; c < R; ++c) {
+        if (!act[c]) continue;
+        const double rel = std::sqrt(h[c]) / ynorm[c];
+        res.relres[c] = rel;
+        if (rel <= tol) {
+          act[c] = 0;
+          changed = true;
+        }
+      }
+      if (changed) KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    }
+    any_active = false;
+    for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
+    if (!any_active) break;
+    precondition(r.p, z.p);
+    red.dot(r.p, z.p, n, rho_new, s);
+    hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
+    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, p.p, z.p, beta, active.p, n, R);
+    KRR_LAUNCH_CHECK();
+    if (R == 1 || act[0]) {
+      double b0;
+      KRR_CHECK_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, s));
+      KRR_CHECK_HIP(hipStreamSynchronize(s));
+      lanczos_b.push_back(b0);
+    }
+  }
+  // final true residuals for columns still active (maxit or breakdown)
+  bool unfinished = false;
+  for (int c = 0; c < R; ++c) unfinished |= act[c] != 0;
+  if (unfinished) {
+    Atrue->apply(x, betas, q.p, s);
+    res.st.n_mvm_fp64++;
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+    red.dot(r.p, nullptr, n, rr, s);
+    KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < R; ++c)
+      if (act[c]) res.relres[c] = std::sqrt(h[c]) / ynorm[c];
+    res.status = breakdown ? KRR_EBREAKDOWN : KRR_ENOCONV;
+  }
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  tm.collect();
+  // Lanczos tridiagonal of column 0 -> extreme eigenvalues (kappa estimate) by bisection-free power:
+  // the tridiagonal is small; use a symmetric QR-free estimate from its Gershgorin-refined bounds
+  // computed with the Sturm-sequence bisection below.
+  {
+    const int m = (int)std::min(lanczos_g.size(), lanczos_b.size() + 1);
+    if (m >= 2) {
+      std::vector<double> dg(m), od(m > 1 ? m - 1 : 0);
+      for (int j = 0; j < m; ++j) {
+        dg[j] = 1.0 / lanczos_g[j] + (j > 0 ? lanczos_b[j - 1] / lanczos_g[j - 1] : 0.0);
+        if (j + 1 < m) od[j] = std::sqrt(std::max(lanczos_b[j], 0.0)) / lanczos_g[j];
+      }
+      auto count_below = [&](double x) {   // Sturm count of eigenvalues < x
+        int cnt = 0;
+        double dd = dg[0] - x;
+        if (dd < 0) ++cnt;
+        for (int j = 1; j < m; ++j) {
+          const double den = dd == 0.0 ? 1e-300 : dd;
+          dd = dg[j] - x - od[j - 1] * od[j - 1] / den;
+          if (dd < 0) ++cnt;
+        }
+        return cnt;
+      };
+      double lo = 1e300, hi = -1e300;
+      for (int j = 0; j < m; ++j) {
+        const double rad = (j > 0 ? std::fabs(od[j - 1]) : 0.0) + (j + 1 < m ? std::fabs(od[j]) : 0.0);
+        lo = std::min(lo, dg[j] - rad);
+        hi = std::max(hi, dg[j] + rad);
+      }
+      auto kth = [&](int k) {   // k-th smallest eigenvalue (0-based)
+        double a = lo, b = hi;
+        for (int t = 0; t < 200; ++t) {
+          const double mid = 0.5 * (a + b);
+          if (count_below(mid) > k) b = mid;
+          else a = mid;
+        }
+        return 0.5 * (a + b);
+      };
+      const double emin = kth(0), emax = kth(m - 1);
+      res.st.kappa_est = emin > 0 ? emax / emin : 0.0;
+    }
+  }
+  int mx = 0;
+  for (int c = 0; c < R; ++c) mx = std::max(mx, res.iters[c]);
+  res.st.iters_max = mx;
+  res.st.t_total_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
+  return res;
+}
+
+}  // namespace krr
+
+extern "C" int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps, const double* Yrhs, int32_t R,
+                             const double* betas, const krr_precond* P, double tol, int32_t maxit,
+                             int32_t replace_every, int32_t prec, double* alpha, int32_t* iters, double* relres,
+                             krr_solve_stats* stats, int32_t timing, void* stream) {
+  return krr::guarded([&] {
+    krr::validate_common(n, n, d, eps);
+    krr::validate_prec(prec);
+    KRR_REQUIRE(X && Yrhs && betas && alpha && iters && relres, "null pointer argument");
+    KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
+    KRR_REQUIRE(tol > 0 && std::isfinite(tol), "tol must be positive");
+    KRR_REQUIRE(maxit >= 0, "maxit must be >= 0");
+    KRR_REQUIRE(replace_every >= 0, "replace_every must be >= 0");
+    for (int c = 0; c < R; ++c) KRR_REQUIRE(betas[c] > 0 && std::isfinite(betas[c]), "beta must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    krr::check_finite_device(X, n * (int64_t)d, "X", s);
+    krr::check_finite_device(Yrhs, n * (int64_t)R, "y", s);
+    krr::check_finite_device(alpha, n * (int64_t)R, "initial alpha", s);
+    krr::PcgResult res =
+        krr::pcg_solve(X, n, d, eps, Yrhs, R, betas, P, tol, maxit, replace_every, prec, alpha, timing != 0, s);
+    for (int c = 0; c < R; ++c) {
+      iters[c] = res.iters[c];
+      relres[c] = res.relres[c];
+    }
+    if (stats) *stats = res.st;
+    return res.status;
+  });
+}

@@ -1,0 +1,530 @@
+// ID / Nystrom / Woodbury preconditioner (Sec. 3): build (Algorithms 1-3) and apply (Algorithm 4),
+// plus the C ABI entry points krr_sketch, krr_qrcp, krr_build_precond and the handle accessors.
+//
+// Build, all on the device:
+//   sketch Y (Algorithm 1: K Omega^T through the kernel MVM; Algorithm 2: sparse sketch kernel)
+//   -> pivoted QR of Y^T -> anchors S (first k pivots)
+//   -> K_SS = U^{-1} -> one-sided Jacobi EVD -> drop eigenvalues <= tau * max
+//   -> C = K(X, X_S) -> W = C V_kept diag(lam_kept)^{-1/2}  (so W W^T = C U C^T)
+//   -> M = W^T W (FP64) -> per beta: Cholesky L L^T = beta I + M (Eq. chol_factor), L^{-1},
+//      G = (beta I + M)^{-1} = L^{-T} L^{-1}.
+// For FP32/mixed handles W is also rounded to FP32 and a second core is built from exactly that
+// rounded copy, so the applied operator is the Woodbury inverse of W32 W32^T + beta I.
+// The dense products W = C T, M = W^T W and G = L^{-T} L^{-1} are plain GEMMs (rocBLAS).
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <numeric>
+
+#include "dense.h"
+#include "kmv.h"
+#include "precond.h"
+#include "sketch_qrcp.h"
+
+namespace krr {
+
+void validate_common(int64_t m, int64_t n, int32_t d, double eps);
+void validate_prec(int32_t prec);
+void kernel_mv_raw(const double* Xt, int64_t m, const double* Xs, int64_t n, int d, double eps, const double* V,
+                   int R, const double* shift, int deriv, int prec, double* U, int64_t ldu, hipStream_t s);
+
+// ------------------------------------------------------------------ rocBLAS
+rocblas_handle blas(hipStream_t s) {
+  thread_local rocblas_handle h = nullptr;
+  if (!h) {
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{KRR_EHIP, "rocblas_create_handle failed"};
+  }
+  if (rocblas_set_stream(h, s) != rocblas_status_success) throw Error{KRR_EHIP, "rocblas_set_stream failed"};
+  return h;
+}
+
+#define KRR_BLAS(expr)                                                                        \
+  do {                                                                                        \
+    rocblas_status st_ = (expr);                                                              \
+    if (st_ != rocblas_status_success)                                                        \
+      throw ::krr::Error{KRR_EHIP, std::string(#expr) + ": " + rocblas_status_to_string(st_)}; \
+  } while (0)
+
+// column-major C (m x n) = op(A) op(B)
+static void dgemm(hipStream_t s, bool ta, bool tb, int m, int n, int k, const double* A, int lda, const double* B,
+                  int ldb, double* C, int ldc, double beta = 0.0) {
+  const double one = 1.0;
+  KRR_BLAS(rocblas_dgemm(blas(s), ta ? rocblas_operation_transpose : rocblas_operation_none,
+                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, B, ldb,
+                         &beta, C, ldc));
+}
+static void sgemm(hipStream_t s, bool ta, bool tb, int m, int n, int k, const float* A, int lda, const float* B,
+                  int ldb, float* C, int ldc) {
+  const float one = 1.0f, zero = 0.0f;
+  KRR_BLAS(rocblas_sgemm(blas(s), ta ? rocblas_operation_transpose : rocblas_operation_none,
+                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, B, ldb,
+                         &zero, C, ldc));
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_make_T(const double* __restrict__ V, const double* __restrict__ lam, const int* __restrict__ idx,
+                         int k, int kept, double* __restrict__ T) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * kept) return;
+  const int r = (int)(t % k), c = (int)(t / k);
+  const int j = idx[c];
+  T[t] = V[(int64_t)j * k + r] / sqrt(lam[j]);
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_to_f64(const float* __restrict__ a, int64_t n, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+__global__ void k_add_diag(const double* __restrict__ M, int k, double beta, double* __restrict__ A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  A[t] = M[t] + ((t % k) == (t / k) ? beta : 0.0);
+}
+
+static unsigned nblk(int64_t n, int b = 256) { return (unsigned)ceil_div(n, b); }
+
+// ------------------------------------------------------------------ Woodbury apply kernels (one column)
+constexpr int kWRows = 1024;   // rows per block in the W^T x pass
+
+// partial[b, c] = sum_{i in block b} W[i, c] x[i]  (products and sums in FP64; W read once)
+template <typename TW>
+__global__ __launch_bounds__(256) void k_wt_partial(const TW* __restrict__ W, int64_t n, int kept,
+                                                    const double* __restrict__ x, int ldx,
+                                                    double* __restrict__ partial) {
+  const int64_t i0 = (int64_t)blockIdx.x * kWRows;
+  const int64_t i1 = i0 + kWRows < n ? i0 + kWRows : n;
+  for (int cb = 0; cb < kept; cb += 256) {
+    const int c = cb + threadIdx.x;
+    double acc = 0.0;
+    if (c < kept) {
+#pragma unroll 4
+      for (int64_t i = i0; i < i1; ++i) acc = __builtin_fma((double)W[i * kept + c], x[i * ldx], acc);
+      partial[(int64_t)blockIdx.x * kept + c] = acc;
+    }
+  }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nb, int kept, double* __restrict__ t) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= kept) return;
+  double s = 0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * kept + c];
+  t[c] = s;
+}
+
+// z[i] = sum_c G[i, c] t[c]; G symmetric, one wave per row reading row i of G contiguously.
+__global__ __launch_bounds__(256) void k_sym_gemv(const double* __restrict__ G, int kept, const double* __restrict__ t,
+                                                  double* __restrict__ z) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= kept) return;
+  double s = 0;
+  for (int c = lane; c < kept; c += 64) s = __builtin_fma(G[(int64_t)i * kept + c], t[c], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) z[i] = s;
+}
+
+// out[i] = (x[i] - sum_c W[i, c] z[c]) / beta; one wave per row, z staged in LDS.
+template <typename TW>
+__global__ __launch_bounds__(256) void k_w_z(const TW* __restrict__ W, int64_t n, int kept,
+                                             const double* __restrict__ z, const double* __restrict__ x, int ldx,
+                                             double inv_beta, double* __restrict__ out, int ldo) {
+  extern __shared__ double zs[];
+  for (int c = threadIdx.x; c < kept; c += 256) zs[c] = z[c];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    double s = 0;
+    const TW* wr = W + i * kept;
+    for (int c = lane; c < kept; c += 64) s = __builtin_fma((double)wr[c], zs[c], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[i * ldo] = (x[i * ldx] - s) * inv_beta;
+  }
+}
+
+// ------------------------------------------------------------------ block (R > 1) helpers
+__global__ void k_rows_to_f32(const double* __restrict__ X, int64_t n, int R, float* __restrict__ X32) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * R) X32[t] = (float)X[t];
+}
+// T[c, r] (kept x R, column-major) = sum_s Tpart[s][c, r]
+__global__ void k_reduce_batches(const float* __restrict__ Tp, int S, int64_t stride, int64_t cnt,
+                                 double* __restrict__ T) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  double s = 0;
+  for (int b = 0; b < S; ++b) s += (double)Tp[b * stride + t];
+  T[t] = s;
+}
+// Zsel[:, r] = Zall[bidx[r]][:, r]  (each Zall block kept x R column-major), converted to FP32
+__global__ void k_select_z(const double* __restrict__ Zall, int kept, int R, const int* __restrict__ bidx,
+                           float* __restrict__ Z32, double* __restrict__ Z64) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)kept * R) return;
+  const int r = (int)(t / kept);
+  const double v = Zall[(int64_t)bidx[r] * kept * R + t];
+  if (Z32) Z32[t] = (float)v;
+  if (Z64) Z64[t] = v;
+}
+// out[i, r] = (x[i, r] - WZ[r, i]) / beta_r   (WZ is R x n column-major = n x R row-major)
+template <typename T>
+__global__ void k_block_out(const double* __restrict__ x, const T* __restrict__ WZ, int64_t n, int R,
+                            const double* __restrict__ inv_beta, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int r = (int)(t % R);
+  out[t] = (x[t] - (double)WZ[t]) * inv_beta[r];
+}
+
+int beta_index(const krr_precond& P, double beta) {
+  for (size_t i = 0; i < P.betas.size(); ++i)
+    if (P.betas[i] == beta) return (int)i;
+  return -1;
+}
+
+void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
+                    hipStream_t s) {
+  const int kept = P.kept;
+  const int64_t n = P.n;
+  KRR_REQUIRE(!use32 || P.W32.p, "preconditioner was built without an FP32 factor");
+  if (R == 1) {
+    const int b = bidx_host[0];
+    const double* G = use32 ? P.G32[b].p : P.G64[b].p;
+    const int nb = (int)ceil_div(n, kWRows);
+    DevBuf<double> partial((size_t)nb * kept, s), t(kept, s), z(kept, s);
+    if (use32)
+      hipLaunchKernelGGL(k_wt_partial<float>, dim3(nb), dim3(256), 0, s, P.W32.p, n, kept, x, 1, partial.p);
+    else
+      hipLaunchKernelGGL(k_wt_partial<double>, dim3(nb), dim3(256), 0, s, P.W64.p, n, kept, x, 1, partial.p);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(kept)), dim3(256), 0, s, partial.p, nb, kept, t.p);
+    hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t.p, z.p);
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 4), 8192);
+    const size_t lds = (size_t)kept * sizeof(double);
+    if (use32)
+      hipLaunchKernelGGL(k_w_z<float>, dim3(g), dim3(256), lds, s, P.W32.p, n, kept, z.p, x, 1,
+                         1.0 / P.betas[b], out, 1);
+    else
+      hipLaunchKernelGGL(k_w_z<double>, dim3(g), dim3(256), lds, s, P.W64.p, n, kept, z.p, x, 1,
+                         1.0 / P.betas[b], out, 1);
+    KRR_LAUNCH_CHECK();
+    return;
+  }
+  // Block form: T = W^T X (split over rows, FP32 GEMMs summed in FP64) ; Z_b = G_b T for each beta;
+  // column r takes Z_{beta_r}; out = (X - W Z) diag(1/beta).
+  const int nbeta = (int)P.betas.size();
+  std::vector<double> ib(R);
+  for (int r = 0; r < R; ++r) ib[r] = 1.0 / P.betas[bidx_host[r]];
+  DevBuf<double> invb(R, s);
+  DevBuf<int> bidx(R, s);
+  KRR_CHECK_HIP(hipMemcpyAsync(invb.p, ib.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+  KRR_CHECK_HIP(hipMemcpyAsync(bidx.p, bidx_host, sizeof(int) * R, hipMemcpyHostToDevice, s));
+  DevBuf<double> T((size_t)kept * R, s), Zall((size_t)nbeta * kept * R, s);
+  if (use32) {
+    const int64_t chunk = 8192;
+    const int S = (int)ceil_div(n, chunk);
+    DevBuf<float> X32(n * R, s), Tp((size_t)S * kept * R, s), Z32((size_t)kept * R, s), WZ(n * R, s);
+    hipLaunchKernelGGL(k_rows_to_f32, dim3(nblk(n * R)), dim3(256), 0, s, x, n, R, X32.p);
+    // full chunks as one strided batch, the ragged tail separately
+    const int Sfull = (int)(n / chunk);
+    const float one = 1.0f, zero = 0.0f;
+    if (Sfull > 0)
+      KRR_BLAS(rocblas_sgemm_strided_batched(blas(s), rocblas_operation_none, rocblas_operation_transpose, kept, R,
+                                             (int)chunk, &one, P.W32.p, kept, chunk * kept, X32.p, R, chunk * R,
+                                             &zero, Tp.p, kept, (int64_t)kept * R, Sfull));
+    if (S > Sfull) {
+      const int64_t i0 = (int64_t)Sfull * chunk;
+      sgemm(s, false, true, kept, R, (int)(n - i0), P.W32.p + i0 * kept, kept, X32.p + i0 * R, R,
+            Tp.p + (int64_t)Sfull * kept * R, kept);
+    }
+    hipLaunchKernelGGL(k_reduce_batches, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Tp.p, S,
+                       (int64_t)kept * R, (int64_t)kept * R, T.p);
+    for (int b = 0; b < nbeta; ++b)
+      dgemm(s, false, false, kept, R, kept, P.G32[b].p, kept, T.p, kept, Zall.p + (int64_t)b * kept * R, kept);
+    hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p, Z32.p,
+                       (double*)nullptr);
+    sgemm(s, true, false, R, (int)n, kept, Z32.p, kept, P.W32.p, kept, WZ.p, R);
+    hipLaunchKernelGGL(k_block_out<float>, dim3(nblk(n * R)), dim3(256), 0, s, x, WZ.p, n, R, invb.p, out);
+  } else {
+    DevBuf<double> Z64((size_t)kept * R, s), WZ(n * R, s);
+    dgemm(s, false, true, kept, R, (int)n, P.W64.p, kept, x, R, T.p, kept);
+    for (int b = 0; b < nbeta; ++b)
+      dgemm(s, false, false, kept, R, kept, P.G64[b].p, kept, T.p, kept, Zall.p + (int64_t)b * kept * R, kept);
+    hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p,
+                       (float*)nullptr, Z64.p);
+    dgemm(s, true, false, R, (int)n, kept, Z64.p, kept, P.W64.p, kept, WZ.p, R);
+    hipLaunchKernelGGL(k_block_out<double>, dim3(nblk(n * R)), dim3(256), 0, s, x, WZ.p, n, R, invb.p, out);
+  }
+  KRR_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ build
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static void validate_sketch_inputs(const double* omega, const int64_t* idx, const double* sign, int64_t n, int l,
+                                   int r, hipStream_t s) {
+  KRR_REQUIRE((omega != nullptr) != (idx != nullptr), "give exactly one of omega (Algorithm 1) or idx/sign (Algorithm 2)");
+  if (idx) {
+    KRR_REQUIRE(sign != nullptr, "sign is required with idx");
+    KRR_REQUIRE(r >= 1, "r must be >= 1 for the sparse sketch");
+    std::vector<int64_t> h((size_t)l * r);
+    KRR_CHECK_HIP(hipMemcpyAsync(h.data(), idx, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    for (int64_t v : h) KRR_REQUIRE(v >= 0 && v < n, "sketch index out of range [0, n)");
+    check_finite_device(sign, (int64_t)l * r, "sign", s);
+  } else {
+    check_finite_device(omega, n * (int64_t)l, "omega", s);
+  }
+}
+
+// Sketch into Yt (l x ldy) in the working precision wprec (FP64 or FP32).
+static void make_sketch_t(const double* X, int64_t n, int d, double eps, const double* omega, const int64_t* idx,
+                          const double* sign, int l, int r, int prec, int wprec, void* Yt, int64_t ldy,
+                          double* keepY, hipStream_t s) {
+  if (omega) {
+    DevBuf<double> Y(n * l, s);
+    kernel_mv_raw(X, n, X, n, d, eps, omega, l, nullptr, 0, prec, Y.p, l, s);
+    transpose_to_t(Y.p, n, l, wprec, Yt, ldy, s);
+    if (keepY) KRR_CHECK_HIP(hipMemcpyAsync(keepY, Y.p, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
+  } else {
+    sketch_sparse_t(X, n, d, eps, idx, sign, l, r, wprec, Yt, ldy, s);
+    if (keepY) transpose_from_t(Yt, ldy, n, l, wprec, keepY, s);
+  }
+}
+
+static void build_core(krr_precond& P, const double* M, std::vector<DevBuf<double>>& G,
+                       std::vector<DevBuf<double>>* Ls, hipStream_t s) {
+  const int kept = P.kept;
+  const int64_t kk = (int64_t)kept * kept;
+  for (double beta : P.betas) {
+    DevBuf<double> A(kk, s), L(kk, s), Li(kk, s), Gb(kk, s);
+    hipLaunchKernelGGL(k_add_diag, dim3(nblk(kk)), dim3(256), 0, s, M, kept, beta, A.p);
+    KRR_LAUNCH_CHECK();
+    const int info = cholesky_lower(A.p, L.p, kept, s);
+    if (info != 0)
+      throw Error{KRR_ENOTSPD, "Cholesky of beta I + W^T W failed at column " + std::to_string(info - 1) +
+                                   " (beta = " + std::to_string(beta) + ")"};
+    lower_inverse(L.p, Li.p, kept, s);
+    dgemm(s, true, false, kept, kept, kept, Li.p, kept, Li.p, kept, Gb.p, kept);
+    G.push_back(std::move(Gb));
+    if (Ls) Ls->push_back(std::move(L));
+  }
+}
+
+void build_precond(krr_precond& P, const double* X, const double* omega, const int64_t* idx, const double* sign,
+                   int flags, hipStream_t s) {
+  using clk = std::chrono::steady_clock;
+  const auto t_all = clk::now();
+  const int64_t n = P.n;
+  const int d = P.d, k = P.k, l = P.l;
+  const int wprec = P.prec == KRR_FP64 ? KRR_FP64 : KRR_FP32;
+  const size_t esz = wprec == KRR_FP64 ? sizeof(double) : sizeof(float);
+  // 1. sketch (Algorithm 1 / 2)
+  auto t0 = clk::now();
+  const int64_t ldy = round_up(n, 256);
+  DevBuf<char> Yt((size_t)l * ldy * esz, s);
+  if (flags & KRR_KEEP_SKETCH) P.Ysk.alloc(n * l, s);
+  make_sketch_t(X, n, d, P.eps, omega, idx, sign, l, P.r, P.prec, wprec, Yt.p, ldy,
+                (flags & KRR_KEEP_SKETCH) ? P.Ysk.p : nullptr, s);
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  P.t_build_ms[0] = ms_since(t0);
+  // 2. pivoted QR of Y^T -> S
+  t0 = clk::now();
+  P.S.alloc(k, s);
+  DevBuf<double> rdiag(k, s);
+  qrcp_t(Yt.p, ldy, n, l, k, wprec, P.S.p, rdiag.p, s);
+  Yt.release();
+  P.S_host.resize(k);
+  P.rdiag_host.resize(k);
+  KRR_CHECK_HIP(hipMemcpyAsync(P.S_host.data(), P.S.p, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+  KRR_CHECK_HIP(hipMemcpyAsync(P.rdiag_host.data(), rdiag.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  P.t_build_ms[1] = ms_since(t0);
+  // 3. K_SS = U^{-1}, EVD, truncation
+  t0 = clk::now();
+  DevBuf<double> XS((size_t)k * d, s), Kss((size_t)k * k, s), V((size_t)k * k, s), lam(k, s);
+  gather_rows(X, n, d, P.S.p, k, XS.p, s);
+  kernel_block_colmajor(XS.p, k, XS.p, k, d, P.eps, Kss.p, k, s);
+  P.jacobi_sweeps = jacobi_evd(Kss.p, V.p, lam.p, k, s);
+  std::vector<double> lh(k);
+  KRR_CHECK_HIP(hipMemcpyAsync(lh.data(), lam.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  const double lmax = *std::max_element(lh.begin(), lh.end());
+  KRR_REQUIRE(lmax > 0 && std::isfinite(lmax), "anchor kernel block has no positive eigenvalue");
+  std::vector<int> keep;
+  for (int i = 0; i < k; ++i)
+    if (lh[i] > P.tau * lmax) keep.push_back(i);
+  P.kept = (int)keep.size();
+  P.lam_host = lh;
+  std::sort(P.lam_host.begin(), P.lam_host.end());
+  DevBuf<int> keep_d(P.kept, s);
+  KRR_CHECK_HIP(hipMemcpyAsync(keep_d.p, keep.data(), sizeof(int) * P.kept, hipMemcpyHostToDevice, s));
+  DevBuf<double> T((size_t)k * P.kept, s);
+  hipLaunchKernelGGL(k_make_T, dim3(nblk((int64_t)k * P.kept)), dim3(256), 0, s, V.p, lam.p, keep_d.p, k, P.kept,
+                     T.p);
+  KRR_LAUNCH_CHECK();
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  P.t_build_ms[2] = ms_since(t0);
+  // 4. C = K(X, X_S) and W = C T, M = W^T W
+  t0 = clk::now();
+  const int kept = P.kept;
+  {
+    DevBuf<double> C(n * k, s);
+    kernel_block_rowmajor(X, n, XS.p, k, d, P.eps, C.p, k, s);
+    P.W64.alloc(n * kept, s);
+    dgemm(s, true, false, kept, (int)n, k, T.p, k, C.p, k, P.W64.p, kept);
+  }
+  P.M64.alloc((size_t)kept * kept, s);
+  dgemm(s, false, true, kept, kept, (int)n, P.W64.p, kept, P.W64.p, kept, P.M64.p, kept);
+  if (P.prec != KRR_FP64) {
+    P.W32.alloc(n * kept, s);
+    hipLaunchKernelGGL(k_to_f32, dim3(nblk(n * kept)), dim3(256), 0, s, P.W64.p, n * kept, P.W32.p);
+    DevBuf<double> Wr(n * kept, s);
+    hipLaunchKernelGGL(k_to_f64, dim3(nblk(n * kept)), dim3(256), 0, s, P.W32.p, n * kept, Wr.p);
+    KRR_LAUNCH_CHECK();
+    P.M32.alloc((size_t)kept * kept, s);
+    dgemm(s, false, true, kept, kept, (int)n, Wr.p, kept, Wr.p, kept, P.M32.p, kept);
+  }
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  P.t_build_ms[3] = ms_since(t0);
+  // 5. per-beta core factors
+  t0 = clk::now();
+  build_core(P, P.M64.p, P.G64, &P.L64, s);
+  if (P.prec != KRR_FP64) build_core(P, P.M32.p, P.G32, nullptr, s);
+  KRR_CHECK_HIP(hipStreamSynchronize(s));
+  P.t_build_ms[4] = ms_since(t0);
+  P.t_build_ms[5] = ms_since(t_all);
+}
+
+}  // namespace krr
+
+// ================================================================== C ABI
+extern "C" int krr_sketch(const double* X, int64_t n, int32_t d, double eps, const double* omega, const int64_t* idx,
+                          const double* sign, int32_t l, int32_t r, int32_t prec, double* Y, void* stream) {
+  return krr::guarded([&] {
+    krr::validate_common(n, n, d, eps);
+    krr::validate_prec(prec);
+    KRR_REQUIRE(X && Y, "null pointer argument");
+    KRR_REQUIRE(l >= 1 && l <= 65535, "l must be in [1, 65535]");
+    hipStream_t s = (hipStream_t)stream;
+    krr::validate_sketch_inputs(omega, idx, sign, n, l, r, s);
+    if (omega) {
+      krr::kernel_mv_raw(X, n, X, n, d, eps, omega, l, nullptr, 0, prec, Y, l, s);
+    } else {
+      const int wprec = prec == KRR_FP64 ? KRR_FP64 : KRR_FP32;
+      const int64_t ldy = krr::round_up(n, 256);
+      krr::DevBuf<char> Yt((size_t)l * ldy * (wprec == KRR_FP64 ? 8 : 4), s);
+      krr::sketch_sparse_t(X, n, d, eps, idx, sign, l, r, wprec, Yt.p, ldy, s);
+      krr::transpose_from_t(Yt.p, ldy, n, l, wprec, Y, s);
+    }
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_qrcp(const double* Y, int64_t n, int32_t l, int32_t k, int32_t prec, int64_t* piv, double* rdiag,
+                        void* stream) {
+  return krr::guarded([&] {
+    krr::validate_prec(prec);
+    KRR_REQUIRE(Y && piv && rdiag, "null pointer argument");
+    KRR_REQUIRE(n >= 1 && l >= 1 && k >= 1 && k <= l && k <= n, "need 1 <= k <= l and k <= n");
+    hipStream_t s = (hipStream_t)stream;
+    const int wprec = prec == KRR_FP64 ? KRR_FP64 : KRR_FP32;
+    const int64_t ldy = krr::round_up(n, 256);
+    krr::DevBuf<char> Yt((size_t)l * ldy * (wprec == KRR_FP64 ? 8 : 4), s);
+    krr::transpose_to_t(Y, n, l, wprec, Yt.p, ldy, s);
+    krr::qrcp_t(Yt.p, ldy, n, l, k, wprec, piv, rdiag, s);
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_build_precond(const double* X, int64_t n, int32_t d, double eps, const double* betas,
+                                 int32_t nbeta, int32_t k, int32_t l, const double* omega, const int64_t* idx,
+                                 const double* sign, int32_t r, double tau, int32_t prec, int32_t flags,
+                                 krr_precond** out, void* stream) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(out != nullptr, "out must not be NULL");
+    *out = nullptr;
+    krr::validate_common(n, n, d, eps);
+    krr::validate_prec(prec);
+    KRR_REQUIRE(X && betas, "null pointer argument");
+    KRR_REQUIRE(nbeta >= 1 && nbeta <= 64, "nbeta must be in [1, 64]");
+    for (int i = 0; i < nbeta; ++i) KRR_REQUIRE(betas[i] > 0 && std::isfinite(betas[i]), "beta must be positive and finite");
+    KRR_REQUIRE(k >= 1 && k <= l && l <= n, "need 1 <= k <= l <= n");
+    KRR_REQUIRE(l <= 65535, "l must be <= 65535");
+    KRR_REQUIRE((size_t)k * sizeof(double) <= 160 * 1024, "k too large (at most 20480)");
+    hipStream_t s = (hipStream_t)stream;
+    krr::check_finite_device(X, n * (int64_t)d, "X", s);
+    krr::validate_sketch_inputs(omega, idx, sign, n, l, r, s);
+    auto P = std::make_unique<krr_precond>();
+    P->n = n; P->d = d; P->k = k; P->l = l; P->r = omega ? 0 : r; P->eps = eps; P->prec = prec;
+    P->tau = tau > 0 ? tau : 1e-12;
+    P->betas.assign(betas, betas + nbeta);
+    krr::build_precond(*P, X, omega, idx, sign, flags, s);
+    *out = P.release();
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_precond_info(const krr_precond* P, int64_t* S_host, int32_t* kept, double* lam_host,
+                                double* rdiag_host, int32_t* k, int32_t* nbeta) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(P != nullptr, "null handle");
+    if (S_host) std::copy(P->S_host.begin(), P->S_host.end(), S_host);
+    if (kept) *kept = P->kept;
+    if (lam_host) std::copy(P->lam_host.begin(), P->lam_host.end(), lam_host);
+    if (rdiag_host) std::copy(P->rdiag_host.begin(), P->rdiag_host.end(), rdiag_host);
+    if (k) *k = P->k;
+    if (nbeta) *nbeta = (int32_t)P->betas.size();
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_precond_get(const krr_precond* P, int32_t what, int32_t bidx, void* dst, size_t bytes,
+                               void* stream) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(P != nullptr && dst != nullptr, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const void* src = nullptr;
+    size_t need = 0;
+    const size_t kk = (size_t)P->kept * P->kept;
+    switch (what) {
+      case 0: src = P->W64.p; need = P->W64.bytes(); break;
+      case 1: src = P->W32.p; need = P->W32.bytes(); break;
+      case 2:
+        KRR_REQUIRE(bidx >= 0 && bidx < (int)P->L64.size(), "beta index out of range");
+        src = P->L64[bidx].p; need = kk * sizeof(double); break;
+      case 3: src = P->Ysk.p; need = P->Ysk.bytes(); break;
+      case 4: src = P->M64.p; need = P->M64.bytes(); break;
+      default: KRR_REQUIRE(false, "unknown buffer id");
+    }
+    KRR_REQUIRE(src != nullptr, "buffer not present in this handle");
+    KRR_REQUIRE(bytes >= need, "destination too small");
+    KRR_CHECK_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, s));
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_precond_apply(const krr_precond* P, const double* x, int32_t R, const double* betas, int32_t prec,
+                                 double* out, void* stream) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(P && x && out && betas, "null argument");
+    krr::validate_prec(prec);
+    KRR_REQUIRE(R >= 1 && R <= 4096, "R must be in [1, 4096]");
+    std::vector<int> bidx(R);
+    for (int r = 0; r < R; ++r) {
+      bidx[r] = krr::beta_index(*P, betas[r]);
+      KRR_REQUIRE(bidx[r] >= 0, "beta not among the preconditioner's betas");
+    }
+    krr::woodbury_apply(*P, x, R, bidx.data(), prec != KRR_FP64, out, (hipStream_t)stream);
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" void krr_precond_free(krr_precond* P) { delete P; }

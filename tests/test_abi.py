@@ -54,3 +54,18 @@ def test_host_validation_without_gpu(lib):
     assert st == -1 and b"d must" in lib.krr_last_error()
     lib.krr_version.restype = ctypes.c_int
     assert lib.krr_version() >= 10000
+
+
+def test_variant_table_roundtrip(lib, tmp_path):
+    import paper_1905_10587_amd as krr
+    L = krr.load()
+    krr._chk(L, L.krr_set_variant(4, 1, 2, 3))
+    krr._chk(L, L.krr_set_variant(8, 1, 1, 1))
+    a, b = tmp_path / "a.json", tmp_path / "b.json"
+    krr._chk(L, L.krr_autotune_save(str(a).encode()))
+    krr._chk(L, L.krr_set_variant(4, 1, 2, -1))         # clear, then restore from the file
+    krr._chk(L, L.krr_autotune_load(str(a).encode()))
+    krr._chk(L, L.krr_autotune_save(str(b).encode()))
+    assert a.read_text() == b.read_text()
+    assert '"2:4:1": 3' in a.read_text()
+    assert L.krr_set_variant(4, 1, 2, 99) == -1          # out of range

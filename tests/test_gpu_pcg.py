@@ -1,0 +1,113 @@
+"""GPU parity of the PCG solve (Algorithm 5) against the oracle.
+
+The solution alpha* = (K + beta I)^{-1} y is unique, so it is compared directly with a dense
+Cholesky solve (the oracle) within kappa * tol; the true relative residual is recomputed in FP64
+on the CPU; block solves must equal the corresponding single-column solves.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from oracle import kernel as ok
+from oracle import pcg as oc
+from oracle import precond as op
+
+
+def _true_relres(X, eps, beta, y, a):
+    K = ok.kernel_matrix(X, X, eps)
+    return np.linalg.norm(y - (K @ a + beta * a)) / np.linalg.norm(y)
+
+
+@pytest.fixture(scope="module")
+def small(gpu_lib):
+    wl = datagen.make_workload("small")
+    om = datagen.sketch_dense_omega(wl.n, wl.l, datagen.sketch_seed("small"))
+    P = gpu_lib.Preconditioner(torch.from_numpy(wl.X), wl.eps, [wl.betas[0], 1e-2], wl.k, wl.l,
+                               omega=torch.from_numpy(om), prec="mixed")
+    ref = oc.solve_dense(wl.X, wl.y, wl.eps, wl.betas[0])
+    return wl, om, P, ref
+
+
+@pytest.mark.gpu
+def test_pcg_fp64_small_workload(gpu_lib, small):
+    """Workload small (n=2000, d=3): rank-150 Alg. 1 preconditioner, PCG to 1e-10, alpha vs Cholesky."""
+    wl, om, P, ref = small
+    beta = wl.betas[0]
+    a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(wl.y), wl.eps, beta, P,
+                                                tol=wl.tol, maxit=5000, prec="fp64")
+    a = a.cpu().numpy()
+    print(f"fp64 PCG: {its[0]} iterations, relres {rel[0]:.2e}, kappa_est {st['kappa_est']:.1f}")
+    assert status == 0 and rel[0] <= wl.tol
+    assert _true_relres(wl.X, wl.eps, beta, wl.y, a) <= 2 * wl.tol
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    print(f"  alpha error vs Cholesky {err:.2e}")
+    assert err <= 1e-6
+    # the oracle's PCG with the same anchors needs a similar number of iterations
+    S = np.array(P.info()["S"])
+    W = op.nystrom_factor(wl.X, S, wl.eps)["W"]
+    L = op.core_cholesky(W, beta)
+    K = ok.kernel_matrix(wl.X, wl.X, wl.eps)
+    o = oc.pcg(lambda v: K @ v + beta * v, wl.y, lambda r: op.woodbury_apply(W, L, beta, r), tol=wl.tol)
+    assert abs(o["iters"] - its[0]) <= max(3, 0.05 * o["iters"])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_pcg_reduced_precision_with_replacement(gpu_lib, small, prec):
+    wl, om, P, ref = small
+    beta = wl.betas[0]
+    a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(wl.y), wl.eps, beta, P,
+                                                tol=1e-9, maxit=5000, replace_every=10, prec=prec)
+    a = a.cpu().numpy()
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    print(f"{prec} PCG: {its[0]} its, relres {rel[0]:.2e}, replacements {st['n_replace']}, alpha err {err:.2e}")
+    assert status == 0 and rel[0] <= 1e-9
+    assert _true_relres(wl.X, wl.eps, beta, wl.y, a) <= 2e-9
+    assert err <= 1e-4
+
+
+@pytest.mark.gpu
+def test_block_pcg_equals_single_solves(gpu_lib, small):
+    wl, om, P, ref = small
+    rng = np.random.default_rng(3)
+    Y = np.stack([wl.y, np.sin(5 * wl.X[:, 1]), rng.standard_normal(wl.n)], axis=1)
+    betas = [wl.betas[0], 1e-2, wl.betas[0]]
+    A, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(Y), wl.eps, betas, P,
+                                                tol=1e-9, maxit=5000, prec="fp64")
+    A = A.cpu().numpy()
+    assert status == 0
+    for c in range(3):
+        a1, i1, r1, _, _ = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(Y[:, c].copy()), wl.eps,
+                                             betas[c], P, tol=1e-9, maxit=5000, prec="fp64")
+        assert i1[0] == its[c]
+        np.testing.assert_allclose(A[:, c], a1.cpu().numpy(), rtol=1e-9, atol=1e-9 * np.abs(A[:, c]).max())
+        assert _true_relres(wl.X, wl.eps, betas[c], Y[:, c], A[:, c]) <= 2e-9
+
+
+@pytest.mark.gpu
+def test_plain_cg_and_warm_start(gpu_lib):
+    rng = np.random.default_rng(4)
+    X = rng.random((700, 2))
+    y = np.cos(4 * X[:, 0]) + 0.1 * rng.standard_normal(700)
+    eps, beta = 0.1, 1e-2
+    ref = oc.solve_dense(X, y, eps, beta)
+    a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y), eps, beta, None,
+                                                tol=1e-11, maxit=5000, prec="fp64")
+    assert status == 0
+    np.testing.assert_allclose(a.cpu().numpy(), ref, rtol=1e-6, atol=1e-8 * np.abs(ref).max())
+    # warm start from the solution converges immediately
+    a2, its2, rel2, _, status2 = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y), eps, beta, None,
+                                                   tol=1e-9, maxit=10, prec="fp64", x0=a)
+    assert status2 == 0 and its2[0] <= 1
+    # maxit reached -> KRR_ENOCONV (warning status 1), best iterate returned
+    a3, its3, rel3, _, status3 = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y), eps, beta, None,
+                                                   tol=1e-14, maxit=3, prec="fp64")
+    assert status3 == 1 and its3[0] == 3 and rel3[0] > 1e-14
+
+
+@pytest.mark.gpu
+def test_pcg_rejects_unknown_beta(gpu_lib, small):
+    wl, om, P, ref = small
+    with pytest.raises(gpu_lib.KRRError):
+        gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(wl.y), wl.eps, 0.123, P, tol=1e-6)
