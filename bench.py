@@ -1,0 +1,206 @@
+"""Benchmark: Gaussian KRR hot path on one MI355X (one JSON line on stdout).
+
+A step is one pass of the whole hot path over the workload: preconditioner build (Algorithm 2
+sparse sketch, pivoted QR, anchor EVD, Nystrom factor, per-beta core Cholesky) and the PCG solve
+(Algorithm 5) to relative residual tol with the Woodbury preconditioner, in the working precision
+with FP64 residual replacement.  Inputs (points, labels, sketch draws) are resident in HBM before
+the timed region starts.
+
+Default workload "mixed": n = 1,000,000, d = 4, x ~ U[0,1]^4, eps = 0.01, beta = 1e-3, k = 2000,
+l = 2020, r = 32, tol 1e-6, split-BF16 MFMA cross term / FP32 exp / FP64 scalars, replacement every
+10 iterations.
+
+value = kernel pairs evaluated by the step's MVMs (working-precision and FP64) / step wall time,
+in Gpairs/s.  Also reported: solve seconds, iterations, the kernel-MVM rates of the mixed and the
+FP64 kernels on the same GPU, the roofline of the dominant kernel (the mixed MVM) and the CPU oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PCG solve s to rel-res 1e-6 + kernel-MVM Gpairs/s; mixed vs FP64, same GPU"
+# VALU bound of the kernel MVM on MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s;
+# one pair needs one v_exp_f32 (half rate: 2 slots) and one FMA (1 slot) -> 13.1e12 pairs/s.
+PEAK_PAIRS = 256 * 4 * 16 * 2.4e9 / 3.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def oracle_baseline(X, eps, seconds=12.0):
+    """CPU oracle (FP64 NumPy, as written) timed on a bounded row sample of one kernel MVM."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import kernel as ok
+
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(X.shape[0])
+    rows_done, t_used, rows = 0, 0.0, 16
+    with threadpool_limits(limits=1):
+        while t_used < seconds:
+            idx = rng.integers(0, X.shape[0], rows)
+            t0 = time.perf_counter()
+            ok.kernel_mv_rows(X, eps, v, idx)
+            t_used += time.perf_counter() - t0
+            rows_done += rows
+            rows = min(rows * 2, 256)
+    pairs = rows_done * X.shape[0]
+    return pairs / t_used, rows_done, t_used
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "fp32", "small", "block", "adjoint"])
+    ap.add_argument("--prec", default=None, help="working precision (default: the workload's)")
+    ap.add_argument("--fp64-solve", action="store_true", help="also run the full FP64 solve (minutes)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--maxit", type=int, default=20000)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU row sharding of the "
+                                   "solver is a design (see the design notes), not an implementation",
+                          "n_gpus": a.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1905_10587_amd as krr
+
+    krr.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    wl = datagen.make_workload(a.workload)
+    prec = a.prec or {"mixed": "mixed", "fp32": "fp32", "small": "fp64", "block": "mixed", "adjoint": "mixed"}[a.workload]
+    replace_every = 0 if prec == "fp64" else 10
+    log(f"bench: workload {wl.name} n={wl.n} d={wl.d} eps={wl.eps} betas={wl.betas} k={wl.k} l={wl.l} "
+        f"r={wl.r} tol={wl.tol} prec={prec}")
+    dev = torch.device("cuda:0")
+    Xg = torch.from_numpy(wl.X).to(dev)
+    Y = wl.y if wl.y.ndim == 1 else wl.y
+    Yg = torch.from_numpy(Y).to(dev)
+    if wl.col_beta is not None:
+        betas_col = [float(b) for b in wl.col_beta]
+    else:
+        betas_col = [float(wl.betas[0])] * (1 if Y.ndim == 1 else Y.shape[1])
+    if wl.r > 0:
+        idx, sign = datagen.sketch_sparse_draws(wl.n, wl.l, wl.r, datagen.sketch_seed(wl.name))
+        sk = dict(idx=torch.from_numpy(idx).to(dev), sign=torch.from_numpy(sign).to(dev))
+    else:
+        sk = dict(omega=torch.from_numpy(datagen.sketch_dense_omega(wl.n, wl.l, datagen.sketch_seed(wl.name))).to(dev))
+    torch.cuda.synchronize()
+
+    def step():
+        t0 = time.perf_counter()
+        P = krr.Preconditioner(Xg, wl.eps, list(wl.betas), wl.k, wl.l, prec=prec, **sk)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        alpha, its, rel, st, status = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol, maxit=a.maxit,
+                                                    replace_every=replace_every, prec=prec, timing=True)
+        torch.cuda.synchronize()
+        return P, alpha, its, rel, st, status, tb, time.perf_counter() - t0
+
+    os.environ.setdefault("KRR_PROGRESS", "100")
+    for w in range(a.warmup):
+        log(f"bench: warmup step {w + 1}/{a.warmup}")
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: timing {a.steps} step(s)")
+    t_start = time.perf_counter()
+    results = []
+    for s in range(a.steps):
+        results.append(step())
+        log(f"bench: step {s + 1}: build {results[-1][6]:.2f} s, total {results[-1][7]:.2f} s, "
+            f"iterations {max(results[-1][2])}, relres {max(results[-1][3]):.2e}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    P, alpha, its, rel, st, status, t_build, t_step = results[-1]
+    R = len(betas_col)
+    n = wl.n
+    pairs_step = (st["n_mvm"] + st["n_mvm_fp64"]) * float(n) * n
+    ms_per_step = 1e3 * t_total / a.steps
+    value = pairs_step / (t_total / a.steps) / 1e9
+    avg_mvm_ms = st["t_mvm_ms"] / max(st["n_mvm"], 1)
+    achieved = float(n) * n / (avg_mvm_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "bf16x3-split/f32/f64", "fp32": "f32/f64", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: n={n} d={wl.d} eps={wl.eps} beta={list(wl.betas)} k={wl.k} "
+                               f"l={wl.l} r={wl.r} tol={wl.tol} rhs={R}",
+                   "precision": prec, "replace_every": replace_every},
+        "solve_s": round(t_step, 3),
+        "build_s": round(t_build, 3),
+        "iterations": max(its),
+        "relres_true": max(rel),
+        "status": status,
+        "n_mvm": st["n_mvm"],
+        "n_mvm_fp64": st["n_mvm_fp64"],
+        "t_mvm_s": round(st["t_mvm_ms"] / 1e3, 3),
+        "t_mvm_fp64_s": round(st["t_mvm_fp64_ms"] / 1e3, 3),
+        "t_precond_s": round(st["t_precond_ms"] / 1e3, 3),
+        "kappa_est": round(st["kappa_est"], 1),
+        "mvm_gpairs_s": round(achieved / 1e9, 1),
+        "roofline": {"bound": "alu", "kernel": f"k_kmv_mixed (exp2 + FMA per pair, d={wl.d})",
+                     "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_PAIRS / 1e12, 2),
+                     "unit": "Tpairs/s", "frac": round(achieved / PEAK_PAIRS, 3), "traffic": None},
+    }
+    # the FP64 kernel on the same GPU (one timed MVM of the same size)
+    if R == 1:
+        v = torch.randn(n, dtype=torch.float64, device=dev)
+        krr.kernel_mv(Xg[:4096], Xg[:4096], wl.eps, v[:4096], prec="fp64")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        krr.kernel_mv(Xg, None, wl.eps, v, prec="fp64")
+        e1.record()
+        torch.cuda.synchronize()
+        fp64_ms = e0.elapsed_time(e1)
+        out["mvm_gpairs_s_fp64"] = round(float(n) * n / fp64_ms / 1e6, 1)
+        out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
+        if a.fp64_solve and prec != "fp64":
+            log("bench: FP64 solve for comparison")
+            P64 = krr.Preconditioner(Xg, wl.eps, list(wl.betas), wl.k, wl.l, prec="fp64", **sk)
+            t0 = time.perf_counter()
+            a64, its64, rel64, st64, _ = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P64, tol=wl.tol, maxit=a.maxit,
+                                                       prec="fp64")
+            torch.cuda.synchronize()
+            out["fp64_solve_s"] = round(time.perf_counter() - t0, 2)
+            out["fp64_iterations"] = max(its64)
+            out["alpha_rel_err_vs_fp64"] = float(torch.linalg.norm(alpha - a64) / torch.linalg.norm(a64))
+        else:
+            out["fp64_solve_s_projected"] = round(max(its) * fp64_ms / 1e3, 1)
+    if not a.no_cpu:
+        log("bench: CPU oracle baseline")
+        rate, rows, secs = oracle_baseline(wl.X, wl.eps)
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle kernel_mv_rows (FP64 NumPy, one thread) on {rows} random rows x "
+                                         f"{n} sources ({rows * n:.3g} pairs, {secs:.1f} s); the oracle's solve "
+                                         f"runs the same MVM once per iteration"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -192,8 +192,9 @@ int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps,
  * (K + beta I) alpha = ytr, with respect to log eps and log beta, by the adjoint method:
  *   lambda = (K + beta I)^{-1} K_vt^T r_v,
  *   dL/dlog eps = r_v^T K'_vt alpha - lambda^T K' alpha,  dL/dlog beta = -beta lambda^T alpha,
- * with K' = (D^2/eps) K.  One forward and one adjoint PCG (same preconditioner P, may be NULL),
- * fused (K, K') products.  Host scalars out; alpha_out [dev] n (optional), lambda_out [dev] n
+ * with K' = (D^2/eps) K.  One forward and one adjoint PCG (same preconditioner P, may be NULL) in the
+ * working precision `prec`; the products that assemble the loss and gradient (K_vt alpha and K'_vt alpha
+ * fused, K_vt^T r_v, K' alpha) run in FP64.  Host scalars out; alpha_out [dev] n (optional), lambda_out [dev] n
  * (optional).
  */
 int krr_grad(const double* Xtr, int64_t n, const double* ytr,

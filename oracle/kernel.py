@@ -33,13 +33,14 @@ def kernel_deriv_matrix(Xt: np.ndarray, Xs: np.ndarray, eps: float) -> np.ndarra
     return (D2 / eps) * np.exp(-D2 / eps)
 
 
-def kernel_mv(Xt, Xs, eps, V, shift=None, deriv=0, block=512):
+def kernel_mv(Xt, Xs, eps, V, shift=None, deriv=0, block=None):
     """Matrix-free product U = K(Xt, Xs) V (+ V * shift per column), never storing K.
 
     V is n (or n x R).  ``shift`` (length R or scalar) adds shift_r * V[:, r];
     it requires Xt and Xs to be the same point set (the ridge term beta*I).
     deriv=0: K V;  deriv=1: K' V;  deriv=2: returns (K V, K' V).
-    Rows of the target set are processed in blocks of ``block``.
+    Rows of the target set are processed in blocks of ``block`` (default: sized so one block's
+    distance table stays near 256 MB); every row is computed the same way whatever the block size.
     """
     Xt = np.asarray(Xt, np.float64)
     Xs = np.asarray(Xs, np.float64)
@@ -47,6 +48,8 @@ def kernel_mv(Xt, Xs, eps, V, shift=None, deriv=0, block=512):
     vec = V.ndim == 1
     V2 = V[:, None] if vec else V
     m = Xt.shape[0]
+    if block is None:
+        block = int(max(1, min(512, (1 << 25) // max(1, Xs.shape[0] * Xs.shape[1]))))
     U = np.zeros((m, V2.shape[1]))
     Ud = np.zeros((m, V2.shape[1])) if deriv == 2 else None
     for s in range(0, m, block):

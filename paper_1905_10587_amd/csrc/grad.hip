@@ -6,7 +6,10 @@
 //   dL/dlog eps  = r_v^T K'_vt alpha - lambda^T K' alpha, K' = eps dK/deps = (D^2/eps) K
 //   dL/dlog beta = -beta lambda^T alpha
 // K_vt alpha and K'_vt alpha come from one fused (K, K') product; K' alpha on the training set from
-// a derivative-kernel product.  The preconditioner only changes how the solves converge.
+// a derivative-kernel product.  The two solves run in the working precision; these few products
+// that assemble the loss and the gradient run in FP64 (the validation residual r_v is a small
+// difference of large terms when the model fits well, so reduced-precision products would be
+// amplified).  The preconditioner only changes how the solves converge.
 #include "kmv.h"
 #include "pcg.h"
 #include "precond.h"
@@ -74,18 +77,18 @@ extern "C" int krr_grad(const double* Xtr, int64_t n, const double* ytr, const d
     PcgResult f = pcg_solve(Xtr, n, d, eps, ytr, 1, &beta, P, tol, maxit, replace_every, prec, alpha.p, false, s);
     if (f.status < 0) return f.status;
     // [K_vt alpha, K'_vt alpha]
-    kernel_mv_raw(Xval, m, Xtr, n, d, eps, alpha.p, 1, nullptr, 2, prec, Uv.p, 2, s);
+    kernel_mv_raw(Xval, m, Xtr, n, d, eps, alpha.p, 1, nullptr, 2, KRR_FP64, Uv.p, 2, s);
     hipLaunchKernelGGL(k_val_residual, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, Uv.p, yval, m, rv.p);
     KRR_LAUNCH_CHECK();
     const double L = 0.5 * dot_dev(rv.p, 1, rv.p, 1, m, tmp.p, s);
     const double t1 = dot_dev(rv.p, 1, Uv.p + 1, 2, m, tmp.p, s);    // r_v^T K'_vt alpha
     // g = K_vt^T r_v = K(Xtr, Xval) r_v
-    kernel_mv_raw(Xtr, n, Xval, m, d, eps, rv.p, 1, nullptr, 0, prec, g.p, 1, s);
+    kernel_mv_raw(Xtr, n, Xval, m, d, eps, rv.p, 1, nullptr, 0, KRR_FP64, g.p, 1, s);
     // adjoint solve
     PcgResult a = pcg_solve(Xtr, n, d, eps, g.p, 1, &beta, P, tol, maxit, replace_every, prec, lam.p, false, s);
     if (a.status < 0) return a.status;
     // K' alpha on the training set
-    kernel_mv_raw(Xtr, n, Xtr, n, d, eps, alpha.p, 1, nullptr, 1, prec, Kpa.p, 1, s);
+    kernel_mv_raw(Xtr, n, Xtr, n, d, eps, alpha.p, 1, nullptr, 1, KRR_FP64, Kpa.p, 1, s);
     const double t2 = dot_dev(lam.p, 1, Kpa.p, 1, n, tmp.p, s);      // lambda^T K' alpha
     const double t3 = dot_dev(lam.p, 1, alpha.p, 1, n, tmp.p, s);    // lambda^T alpha
     *loss = L;

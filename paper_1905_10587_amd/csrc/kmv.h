@@ -24,6 +24,7 @@ struct Staged {
 };
 
 constexpr int kRowPad = 1024;   // targets/sources are padded to multiples of this
+constexpr int kPrefetchRows = 16;   // extra allocated rows after the padded sources (prefetch reads)
 
 // Pads d up to the instantiated widths of the direct (FP64/FP32) kernels.
 int padded_dim(int d);
@@ -44,7 +45,15 @@ struct StagedVec {
   int Rreal = 0;
   DevBuf<double> v64;   // npad x R
   DevBuf<float> v32;    // npad x R
+  // block-MVM operands: BF16 parts in groups of four sources, V4[((j/4) * Rb + r) * 4 + j%4]
+  int Rb = 0;
+  DevBuf<uint16_t> vh, vm, vl;
 };
+// Block path: stage V into the BF16 parts (Rb = R padded to rpad).
+void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int rpad, int nsplit,
+                         hipStream_t s);
+// Whether kmv_launch takes the block (multi right-hand side) path for these parameters.
+bool kmv_uses_block(int prec, int d, int R, int deriv);
 void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
                    hipStream_t s);
 
@@ -52,7 +61,7 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
 //   deriv: 0 K, 1 K', 2 both (K columns first, then K' columns).
 //   shift: per-column ridge term added as shift[c] * V[i, c] (targets == sources) or nullptr.
 //   Vraw: the original FP64 V (n x R) for the shift term.
-void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
+void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv,
                 const double* shift_host, const double* Vraw, int prec, double* U, int64_t ldu,
                 hipStream_t s, int variant = -1, DevBuf<double>* ws = nullptr);
 

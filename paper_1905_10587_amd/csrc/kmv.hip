@@ -161,13 +161,15 @@ void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int
     hipLaunchKernelGGL(k_stage_f64, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
                        st.x64.p);
     KRR_LAUNCH_CHECK();
-  } else if (prec == KRR_FP32) {
-    st.x32.alloc(tot, s);
-    const double scale = std::sqrt(kLog2e / eps);
-    hipLaunchKernelGGL(k_stage_f32, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
-                       center, scale, st.x32.p);
-    KRR_LAUNCH_CHECK();
   } else {
+    if (prec == KRR_FP32) {
+      st.x32.alloc(tot, s);
+      const double scale = std::sqrt(kLog2e / eps);
+      hipLaunchKernelGGL(k_stage_f32, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
+                         center, scale, st.x32.p);
+      KRR_LAUNCH_CHECK();
+    }
+    // split vectors: the MFMA kernels (single column for MIXED, block for MIXED and FP32)
     st.ka = 32 * mixed_chunks(d);
     const double c = kLog2e / eps;
     if (as_target) {
@@ -177,7 +179,7 @@ void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int
       KRR_LAUNCH_CHECK();
     }
     if (as_source) {
-      st.sb.alloc(st.npad * st.ka, s);
+      st.sb.alloc((st.npad + kPrefetchRows) * st.ka, s);   // padding rows: read by the last prefetch only
       hipLaunchKernelGGL(k_stage_split, dim3(ceil_div(st.npad, blk)), dim3(blk), 0, s, X, n, d, st.npad,
                          st.ka, center, c, 1, st.sb.p);
       KRR_LAUNCH_CHECK();
@@ -202,13 +204,46 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
   sv.Rreal = R;
   sv.R = (int)round_up(R, 8);   // column chunks are at most 8 wide
   const int64_t tot = npad * sv.R;
+  const size_t cap = (size_t)(npad + kPrefetchRows) * sv.R;   // padding rows: read by the last prefetch only
   if (prec == KRR_FP64) {
-    if (sv.v64.n != (size_t)tot) sv.v64.alloc(tot, s);
+    if (sv.v64.n != cap) sv.v64.alloc(cap, s);
   } else {
-    if (sv.v32.n != (size_t)tot) sv.v32.alloc(tot, s);
+    if (sv.v32.n != cap) sv.v32.alloc(cap, s);
   }
   hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R,
                      sv.v64.p, sv.v32.p);
+  KRR_LAUNCH_CHECK();
+}
+
+__global__ void k_stage_v4(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rb, int nsplit,
+                           uint16_t* __restrict__ vh, uint16_t* __restrict__ vm, uint16_t* __restrict__ vl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npad * Rb) return;
+  const int64_t j = t / Rb;
+  const int r = (int)(t % Rb);
+  const double x = (j < n && r < R) ? V[j * R + r] : 0.0;
+  const int64_t o = ((j >> 2) * Rb + r) * 4 + (j & 3);
+  uint16_t h, m, l;
+  split3(x, h, m, l);
+  if (nsplit == 2) {   // two parts: lo takes the whole remainder x - hi
+    m = bf16_rn((float)(x - bf16_to_double(h)));
+  }
+  vh[o] = h;
+  vm[o] = m;
+  if (vl) vl[o] = l;
+}
+
+void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int rpad, int nsplit,
+                         hipStream_t s) {
+  sv.npad = npad;
+  sv.Rreal = R;
+  sv.Rb = (int)round_up(R, rpad);
+  const size_t tot = (size_t)npad * sv.Rb;
+  if (sv.vh.n != tot) sv.vh.alloc(tot, s);
+  if (sv.vm.n != tot) sv.vm.alloc(tot, s);
+  if (nsplit == 3 && sv.vl.n != tot) sv.vl.alloc(tot, s);
+  hipLaunchKernelGGL(k_stage_v4, dim3((unsigned)ceil_div((int64_t)tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.Rb,
+                     nsplit, sv.vh.p, sv.vm.p, nsplit == 3 ? sv.vl.p : nullptr);
   KRR_LAUNCH_CHECK();
 }
 
@@ -242,18 +277,35 @@ __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpa
 namespace {
 std::mutex g_mu;
 std::map<std::string, int> g_override;   // "prec:d:R" -> variant
+// shape classes of the variant table: 1 = one column, 2 = several columns (direct kernels),
+// 3 = block MVM (many columns on MFMA)
+int rclass(int prec, int R) {
+  if (R == 1) return 1;
+  if (prec == KRR_MIXED || (prec == KRR_FP32 && R > 8)) return 3;
+  return 2;
+}
 std::string vkey(int d, int R, int prec) {
   std::ostringstream o;
-  o << prec << ":" << d << ":" << (R > 1 ? 2 : 1);
+  o << prec << ":" << d << ":" << rclass(prec, R);
   return o.str();
 }
 const int kTM[3] = {1, 2, 4};
 const int kNF[4] = {1, 2, 4, 8};
+const int kBlockNT[6] = {2, 4, 1, 2, 4, 1};
+const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 }  // namespace
 
-int kmv_num_variants(int prec, int) { return prec == KRR_MIXED ? 4 : 3; }
+int kmv_num_variants(int prec, int R) {
+  if (rclass(prec, R) == 3) return 6;
+  return prec == KRR_MIXED ? 4 : 3;
+}
+
+bool kmv_uses_block(int prec, int d, int R, int deriv) {
+  return deriv == 0 && rclass(prec, R) == 3 && mixed_chunks(d) <= 4;
+}
 
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t) {
+  if (rclass(prec, R) == 3) return 0;
   if (prec == KRR_MIXED) return mixed_max_nf(mixed_chunks(d)) >= 8 ? 3 : 1;
   if (padded_dim(d) >= 32) return 0;
   return m >= 65536 ? 1 : 0;
@@ -310,7 +362,7 @@ void kmv_table_from_json(const std::string& s) {
   for (auto& kv : parsed) g_override[kv.first] = kv.second;
 }
 
-void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv, const double* shift_host,
+void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const double* shift_host,
                 const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant,
                 DevBuf<double>* ws) {
   KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
@@ -324,7 +376,19 @@ void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
   int64_t rows;
   int gz, TM = 1, NF = 1, RC = R == 1 ? 1 : R <= 4 ? 4 : 8;
   const int D = T.dpad;
-  if (prec == KRR_MIXED) {
+  const bool block = kmv_uses_block(prec, T.d, R, deriv);
+  int NT = 1, NRC = 1, Rpart = Rp;
+  if (block) {
+    const int vb = variant < 6 ? variant : 0;
+    int nrc_max = 1;
+    while (nrc_max * 2 <= ceil_div(R, 16)) nrc_max *= 2;
+    NT = kBlockNT[vb];
+    NRC = std::min(kBlockNRC[vb], nrc_max);
+    stage_vectors_block(V, Vraw, S.n, S.npad, R, 16 * NRC, prec == KRR_MIXED ? 2 : 3, s);
+    Rpart = V.Rb;
+    rows = 64 * NT;
+    gz = V.Rb / (16 * NRC);
+  } else if (prec == KRR_MIXED) {
     NF = std::min(kNF[variant], mixed_max_nf(T.ka / 32));
     rows = 64 * NF;
     gz = 1;
@@ -335,16 +399,21 @@ void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
   }
   const int64_t gx = T.npad / rows;
   const int64_t nsrc = S.npad;
+  const int RpK = block ? Rpart : Rp;                  // row width of the K part in `part`
+  const int RoutK = (DV == 2 ? 2 : 1) * RpK;
   int64_t split = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, gx * gz), nsrc / 256));
   const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
   split = ceil_div(nsrc, src_len);
   DevBuf<double> own;
   DevBuf<double>& part = ws ? *ws : own;
-  const size_t need = (size_t)split * T.npad * Rout;
+  const size_t need = (size_t)split * T.npad * RoutK;
   if (part.n < need) part.alloc(need, s);
-  KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, Rp, Rout};
+  KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   bool ok = true;
-  if (prec == KRR_FP64) {
+  if (block) {
+    ok = launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
+                          prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
+  } else if (prec == KRR_FP64) {
     ok = launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, 1.0 / T.eps, part.p, s);
   } else if (prec == KRR_FP32) {
     ok = launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
@@ -363,7 +432,7 @@ void kmv_launch(const Staged& T, const Staged& S, const StagedVec& V, int deriv,
   const int Rcols = deriv == 2 ? 2 * R : R;
   const int64_t tot = T.n * Rcols;
   hipLaunchKernelGGL(k_kmv_finish, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, part.p, (int)split,
-                     T.npad, Rp, Rout, deriv, T.n, R, has_shift, sh, Vraw, U, ldu);
+                     T.npad, RpK, RoutK, deriv, T.n, R, has_shift, sh, Vraw, U, ldu);
   KRR_LAUNCH_CHECK();
 }
 

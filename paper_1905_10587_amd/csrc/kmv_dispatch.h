@@ -22,5 +22,8 @@ bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float
 bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                       const float* v, int col, double* part, hipStream_t s);
 int mixed_max_nf(int nch);
+// Block MVM (many right-hand sides): NCH in {1,2,3,4}, (NT, NRC) with NT * NRC <= 8, NS in {3, 6}.
+bool launch_kmv_block(int NCH, int NT, int NRC, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+                      const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
 
 }  // namespace krr

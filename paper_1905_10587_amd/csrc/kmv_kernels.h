@@ -240,10 +240,16 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
       for (int o = 0; o < NO; ++o) acc[f][e][o] = 0.0;
   constexpr float kNegLn2f = -0.69314718055994531f;
 
+  // per-lane pointers, advanced by 16 sources per step; the fragment for the next step is loaded one
+  // step ahead (the staged source arrays carry 16 padding rows, so the last prefetch stays in bounds)
+  const uint4* bp = B + (jb + r16) * KV + kq;
+  const float* vp = v + (jb + r16) * Rp + col;
+  const int64_t bstep = 16 * KV;
+  const int64_t vstep = 16 * (int64_t)Rp;
   bf16x8 bn[NCH];
 #pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, B[(jb + r16) * KV + ch * 4 + kq]);
-  float vn = v[(jb + r16) * Rp + col];
+  for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, bp[ch * 4]);
+  float vn = *vp;
   for (int64_t j0 = jb; j0 < je; j0 += 256) {
     float a32[NF][4][NO];
 #pragma unroll
@@ -252,31 +258,42 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int o = 0; o < NO; ++o) a32[f][e][o] = 0.0f;
-    for (int64_t j = j0; j < j0 + 256; j += 16) {
-      // the fragment for j was loaded one step ahead; issue the load for j + 16 now
+    for (int step = 0; step < 16; ++step) {
       bf16x8 b[NCH];
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) b[ch] = bn[ch];
       const float vj = vn;
-      const int64_t jn = j + 16 < je ? j + 16 : j;
+      bp += bstep;
+      vp += vstep;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, B[(jn + r16) * KV + ch * 4 + kq]);
-      vn = v[(jn + r16) * Rp + col];
-      f32x4 q[NF];
+      for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, bp[ch * 4]);
+      vn = *vp;
+      // software pipeline, two fragments deep: the MFMA of fragment f+2 is issued before the exps of
+      // fragment f, so the result of an MFMA is read 16 VALU instructions after its issue
+      f32x4 q0 = f32x4{0.f, 0.f, 0.f, 0.f}, q1 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        q[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int ch = 0; ch < NCH; ++ch) q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ch], b[ch], q0, 0, 0, 0);
+      if (NF > 1) {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) q[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f][ch], b[ch], q[f], 0, 0, 0);
+        for (int ch = 0; ch < NCH; ++ch)
+          q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[NF > 1 ? 1 : 0][ch], b[ch], q1, 0, 0, 0);
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
+        f32x4 q2 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (f + 2 < NF) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 < NF ? f + 2 : 0][ch], b[ch], q2, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float ex = __builtin_amdgcn_exp2f(q[f][e]);
+          const float ex = __builtin_amdgcn_exp2f(q0[e]);
           if (DV == 0 || DV == 2) a32[f][e][0] = __builtin_fmaf(ex, vj, a32[f][e][0]);
-          if (DV >= 1) a32[f][e][NO - 1] = __builtin_fmaf(q[f][e] * ex, kNegLn2f * vj, a32[f][e][NO - 1]);
+          if (DV >= 1) a32[f][e][NO - 1] = __builtin_fmaf(q0[e] * ex, kNegLn2f * vj, a32[f][e][NO - 1]);
         }
+        q0 = q1;
+        q1 = q2;
       }
     }
 #pragma unroll
@@ -313,5 +330,128 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
   }
 }
 
+
+}  // namespace krr
+
+namespace krr {
+
+// ------------------------------------------------------------------ block MVM (many right-hand sides)
+// U[i, r] = sum_j P_ij V[j, r] with P_ij = exp2(q_ij) computed on the fly.  The cross term is issued with
+// the sources as MFMA rows, so the 16 x 16 q tile lands in the lane layout of the A operand of
+// v_mfma_f32_16x16x16_bf16 (lane l: target l%16, sources (l/16)*4 + e): the exp'd tile feeds the second
+// contraction straight from registers.  P and V are split into BF16 parts (NS = 3: hi/lo with
+// hi*hi + hi*lo + lo*hi; NS = 6: hi/mid/lo with the six products down to 2^-24).  Each wave owns NT
+// target fragments of 16 and the block covers 16 * NRC right-hand sides (grid.z walks the rest).
+// V is staged as BF16 parts in groups of four sources: V4[((j/4) * Rp + r) * 4 + j%4].
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_bits_rn(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <int NCH, int NT, int NRC, int NS>
+__global__ __launch_bounds__(256) void k_kmv_block(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                   const uint2* __restrict__ Vh, const uint2* __restrict__ Vm,
+                                                   const uint2* __restrict__ Vl, int Rp, int64_t src_len,
+                                                   int64_t n_src, double* __restrict__ part, int64_t mpad,
+                                                   int Rout) {
+  constexpr int KV = NCH * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * NT);
+  const int rbase = blockIdx.z * 16 * NRC;
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+
+  bf16x8 tg[NT][NCH];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) tg[t][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * t + r16) * KV + ch * 4 + kq]);
+
+  double acc[NT][NRC][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < NRC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][c][e] = 0.0;
+
+  for (int64_t j0 = jb; j0 < je; j0 += 256) {
+    f32x4 a32[NT][NRC];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) a32[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t j = j0; j < j0 + 256; j += 16) {
+      bf16x8 sf[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) sf[ch] = __builtin_bit_cast(bf16x8, B[(j + r16) * KV + ch * 4 + kq]);
+      // exp'd tiles, split into BF16 parts, in the A-operand layout of the 16x16x16 MFMA
+      bf16x4 ph[NT], pm[NT], pl[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        f32x4 q = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sf[ch], tg[t][ch], q, 0, 0, 0);
+        uint16_t hb[4], mb[4], lb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float p = __builtin_amdgcn_exp2f(q[e]);
+          hb[e] = bf16_bits_rn(p);
+          const float r1 = p - bf16_bits_to_f(hb[e]);
+          mb[e] = bf16_bits_rn(r1);
+          if (NS == 6) lb[e] = bf16_bits_rn(r1 - bf16_bits_to_f(mb[e]));
+        }
+        ph[t] = __builtin_bit_cast(bf16x4, make_ushort4(hb[0], hb[1], hb[2], hb[3]));
+        pm[t] = __builtin_bit_cast(bf16x4, make_ushort4(mb[0], mb[1], mb[2], mb[3]));
+        if (NS == 6) pl[t] = __builtin_bit_cast(bf16x4, make_ushort4(lb[0], lb[1], lb[2], lb[3]));
+      }
+      const int64_t vg = (j >> 2) + kq;   // group of four sources
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) {
+        const int64_t vi = vg * Rp + rbase + 16 * c + r16;
+        const bf16x4 vh = __builtin_bit_cast(bf16x4, Vh[vi]);
+        const bf16x4 vm = __builtin_bit_cast(bf16x4, Vm[vi]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ph[t], vh, a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ph[t], vm, a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pm[t], vh, a32[t][c], 0, 0, 0);
+        }
+        if (NS == 6) {
+          const bf16x4 vl = __builtin_bit_cast(bf16x4, Vl[vi]);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ph[t], vl, a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pl[t], vh, a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pm[t], vm, a32[t][c], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[t][c][e] += (double)a32[t][c][e];
+  }
+  // lane l holds targets (l/16)*4 + e of each fragment for right-hand side l%16 of each chunk
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * t + kq * 4 + e;
+      double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout;
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) prow[rbase + 16 * c + r16] = acc[t][c][e];
+    }
+}
 
 }  // namespace krr

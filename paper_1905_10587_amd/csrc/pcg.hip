@@ -8,6 +8,9 @@
 // residual is recomputed as y - (K + beta I) x with the FP64 MVM (residual replacement).
 // Convergence is decided on the host from the R residual norms read back once per iteration.
 #include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -297,10 +300,28 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   red.dot(r.p, z.p, n, rho, s);
 
   std::vector<double> lanczos_g, lanczos_b;
+  // Safeguards: the best iterate by true residual is kept per column; a column whose true residual
+  // grows 1e3-fold over its best, or fails to improve in 8 consecutive true-residual evaluations, is
+  // stopped (KRR_ENOCONV) and returned at its best iterate.  After a failed convergence check a column
+  // is not checked again for max(replace_every, 5) iterations.
+  DevBuf<double> xbest(nR, s);
+  DevBuf<int> mask(R, s);
+  std::vector<double> best_rel(R, HUGE_VAL);
+  std::vector<int> stall(R, 0), next_check(R, 0), gave_up(R, 0);
+  const int recheck = std::max(replace_every, 5);
+  auto copy_columns = [&](double* dst, const double* src, const std::vector<int>& m) {
+    KRR_CHECK_HIP(hipMemcpyAsync(mask.p, m.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_copy_active, dim3(nb(nR)), dim3(256), 0, s, dst, src, mask.p, n, R);
+    KRR_LAUNCH_CHECK();
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+  };
   bool any_active = false;
   for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
   int it = 0;
   bool breakdown = false;
+  // KRR_PROGRESS=k prints the iteration count and the largest recursive relative residual every k iterations
+  const char* prog_env = std::getenv("KRR_PROGRESS");
+  const int progress = prog_env ? std::atoi(prog_env) : 0;
   while (any_active && it < maxit) {
     ++it;
     // q = (K + beta I) p in the working precision
@@ -324,7 +345,15 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     for (int c = 0; c < R; ++c) {
       if (!act[c]) continue;
       res.iters[c] = it;
-      if (std::sqrt(h[c]) / ynorm[c] <= tol) candidate = true;
+      if (it >= next_check[c] && std::sqrt(h[c]) / ynorm[c] <= tol) candidate = true;
+    }
+    if (progress > 0 && it % progress == 0) {
+      double worst = 0;
+      for (int c = 0; c < R; ++c)
+        if (act[c]) worst = std::max(worst, std::sqrt(h[c]) / ynorm[c]);
+      std::fprintf(stderr, "krr pcg: iteration %d, max recursive relres %.3e, %.1f ms\n", it, worst,
+                   std::chrono::duration<double, std::milli>(clk::now() - t_start).count());
+      std::fflush(stderr);
     }
     const bool scheduled = replace_every > 0 && it % replace_every == 0;
     if (candidate || scheduled) {
@@ -339,7 +368,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
       KRR_CHECK_HIP(hipStreamSynchronize(s));
       tm.collect();
-      bool changed = false;
+      bool changed = false, improved = false;
+      std::vector<int> imp(R, 0);
       for (int c = 0; c < R; ++c) {
         if (!act[c]) continue;
         const double rel = std::sqrt(h[c]) / ynorm[c];
@@ -347,8 +377,21 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
         if (rel <= tol) {
           act[c] = 0;
           changed = true;
+          continue;
+        }
+        next_check[c] = it + recheck;
+        if (rel < best_rel[c]) {
+          best_rel[c] = rel;
+          stall[c] = 0;
+          imp[c] = 1;
+          improved = true;
+        } else if (++stall[c] >= 8 || rel > 1e3 * best_rel[c] || !std::isfinite(rel)) {
+          act[c] = 0;
+          gave_up[c] = 1;
+          changed = true;
         }
       }
+      if (improved) copy_columns(xbest.p, x, imp);
       if (changed) KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
     }
     any_active = false;
@@ -366,7 +409,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       lanczos_b.push_back(b0);
     }
   }
-  // final true residuals for columns still active (maxit or breakdown)
+  // final true residuals for columns still active (maxit or breakdown); stopped columns return their
+  // best iterate
   bool unfinished = false;
   for (int c = 0; c < R; ++c) unfinished |= act[c] != 0;
   if (unfinished) {
@@ -377,8 +421,29 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
     KRR_CHECK_HIP(hipStreamSynchronize(s));
     for (int c = 0; c < R; ++c)
-      if (act[c]) res.relres[c] = std::sqrt(h[c]) / ynorm[c];
-    res.status = breakdown ? KRR_EBREAKDOWN : KRR_ENOCONV;
+      if (act[c]) {
+        res.relres[c] = std::sqrt(h[c]) / ynorm[c];
+        if (!(res.relres[c] <= best_rel[c])) gave_up[c] = 1;
+      }
+  }
+  bool restore = false;
+  std::vector<int> rest(R, 0);
+  for (int c = 0; c < R; ++c)
+    if (gave_up[c] && best_rel[c] < HUGE_VAL) {
+      rest[c] = 1;
+      res.relres[c] = best_rel[c];
+      restore = true;
+    }
+  if (restore) copy_columns(x, xbest.p, rest);
+  bool any_gave_up = false;
+  for (int c = 0; c < R; ++c) any_gave_up |= gave_up[c] != 0;
+  if (breakdown) {
+    res.status = KRR_EBREAKDOWN;
+    set_error("PCG breakdown at iteration " + std::to_string(it) + ": p^T A p <= 0 or not finite");
+  } else if (unfinished || any_gave_up) {
+    res.status = KRR_ENOCONV;
+    set_error(any_gave_up ? "PCG stopped: true residual stagnated or diverged; best iterate returned"
+                          : "PCG reached maxit; last iterate returned");
   }
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   tm.collect();

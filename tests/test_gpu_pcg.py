@@ -80,8 +80,11 @@ def test_block_pcg_equals_single_solves(gpu_lib, small):
     for c in range(3):
         a1, i1, r1, _, _ = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(Y[:, c].copy()), wl.eps,
                                              betas[c], P, tol=1e-9, maxit=5000, prec="fp64")
-        assert i1[0] == its[c]
-        np.testing.assert_allclose(A[:, c], a1.cpu().numpy(), rtol=1e-9, atol=1e-9 * np.abs(A[:, c]).max())
+        # block and single solves round differently (GEMM vs GEMV Woodbury apply), so iterates differ at
+        # round-off level and the counts by a few; the solutions agree within kappa * tol
+        assert abs(i1[0] - its[c]) <= 0.03 * i1[0] + 3
+        a1 = a1.cpu().numpy()
+        assert np.linalg.norm(A[:, c] - a1) / np.linalg.norm(a1) <= 1e-5
         assert _true_relres(wl.X, wl.eps, betas[c], Y[:, c], A[:, c]) <= 2e-9
 
 
@@ -111,3 +114,21 @@ def test_pcg_rejects_unknown_beta(gpu_lib, small):
     wl, om, P, ref = small
     with pytest.raises(gpu_lib.KRRError):
         gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(wl.y), wl.eps, 0.123, P, tol=1e-6)
+
+
+@pytest.mark.gpu
+def test_unattainable_tolerance_returns_best_iterate(gpu_lib):
+    """A tolerance below CG's attainable accuracy ends in KRR_ENOCONV with the best iterate, not garbage."""
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal(3)
+    X = 0.5 * rng.standard_normal((600, 3))
+    y = np.tanh(X @ w) + 0.1 * rng.standard_normal(600)
+    eps, beta = 0.5, 1e-2
+    ref = oc.solve_dense(X, y, eps, beta)
+    a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y), eps, beta, None,
+                                                tol=1e-15, maxit=5000, prec="fp64")
+    a = a.cpu().numpy()
+    assert status == 1
+    assert rel[0] < 1e-9
+    assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-5
+    assert _true_relres(X, eps, beta, y, a) < 1e-9
