@@ -6,12 +6,16 @@ sparse sketch, pivoted QR, anchor EVD, Nystrom factor, per-beta core Cholesky) a
 with FP64 residual replacement.  Inputs (points, labels, sketch draws) are resident in HBM before
 the timed region starts.
 
-Default workload "mixed": n = 1,000,000, d = 4, x ~ U[0,1]^4, eps = 0.01, beta = 1e-3, k = 2000,
-l = 2020, r = 32, tol 1e-6, split-BF16 MFMA cross term / FP32 exp / FP64 scalars, replacement every
-10 iterations.
+Default workload "fp32" (the second configuration): n = 100,000, d = 8, points from a mixture of 20
+Gaussians, eps = 0.2, beta = 1e-2, k = 1000, l = 1020, r = 32, tol 1e-8.  The timed step runs the
+mixed precision form (split-BF16 MFMA cross term, FP32 exp/accumulate, FP64 scalars, FP64 residual
+replacement every 10 iterations).  After the timed region the same system is solved with the FP64
+and the FP32 kernels on the same GPU and the same preconditioner, for the mixed-vs-FP64 comparison.
+`--workload mixed` runs n = 1,000,000, d = 4 (eps = 0.01, beta = 1e-3, k = 2000, tol 1e-6); its FP64
+solve (about 50 minutes) is only run with --fp64-solve.
 
 value = kernel pairs evaluated by the step's MVMs (working-precision and FP64) / step wall time,
-in Gpairs/s.  Also reported: solve seconds, iterations, the kernel-MVM rates of the mixed and the
+in Gpairs/s.  Also reported: solve seconds, iterations, the kernel-MVM rates of the mixed, FP32 and
 FP64 kernels on the same GPU, the roofline of the dominant kernel (the mixed MVM) and the CPU oracle.
 """
 from __future__ import annotations
@@ -57,16 +61,46 @@ def oracle_baseline(X, eps, seconds=12.0):
     return pairs / t_used, rows_done, t_used
 
 
+def kernels_only(a, wl, Xg, krr, torch):
+    """Plain copy of known size, then the workload's kernel MVMs (for rocprofv3 traces and counters)."""
+    dev = Xg.device
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out = {"copy_bytes": nbytes}
+    v = torch.randn(wl.n, dtype=torch.float64, device=dev)
+    for prec, reps in (("mixed", a.reps), ("fp64", 1)):
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            krr.kernel_mv(Xg, None, wl.eps, v, shift=wl.betas[0], prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        out[f"{prec}_ms"] = times
+        out[f"{prec}_gpairs_s"] = round(float(wl.n) * wl.n / min(times) / 1e6, 1)
+        log(f"bench: {prec} MVM n={wl.n}: {min(times):.2f} ms")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "fp32", "small", "block", "adjoint"])
+    ap.add_argument("--workload", default="fp32", choices=["mixed", "fp32", "small", "block", "adjoint"])
     ap.add_argument("--prec", default=None, help="working precision (default: the workload's)")
     ap.add_argument("--fp64-solve", action="store_true", help="also run the full FP64 solve (minutes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling mode: a 512 MiB device copy (counter calibration), then the workload's "
+                         "mixed and FP64 kernel MVMs; prints their HIP-event times")
+    ap.add_argument("--reps", type=int, default=3, help="MVM launches per precision in --kernels-only")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU row sharding of the "
@@ -83,7 +117,7 @@ def main(argv=None):
     krr.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
     wl = datagen.make_workload(a.workload)
-    prec = a.prec or {"mixed": "mixed", "fp32": "fp32", "small": "fp64", "block": "mixed", "adjoint": "mixed"}[a.workload]
+    prec = a.prec or {"mixed": "mixed", "fp32": "mixed", "small": "fp64", "block": "mixed", "adjoint": "mixed"}[a.workload]
     replace_every = 0 if prec == "fp64" else 10
     log(f"bench: workload {wl.name} n={wl.n} d={wl.d} eps={wl.eps} betas={wl.betas} k={wl.k} l={wl.l} "
         f"r={wl.r} tol={wl.tol} prec={prec}")
@@ -112,6 +146,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         return P, alpha, its, rel, st, status, tb, time.perf_counter() - t0
 
+    if a.kernels_only:
+        return kernels_only(a, wl, Xg, krr, torch)
     os.environ.setdefault("KRR_PROGRESS", "100")
     for w in range(a.warmup):
         log(f"bench: warmup step {w + 1}/{a.warmup}")
@@ -150,8 +186,9 @@ def main(argv=None):
         "config": {"workload": f"{wl.name}: n={n} d={wl.d} eps={wl.eps} beta={list(wl.betas)} k={wl.k} "
                                f"l={wl.l} r={wl.r} tol={wl.tol} rhs={R}",
                    "precision": prec, "replace_every": replace_every},
-        "solve_s": round(t_step, 3),
+        "step_s": round(t_step, 3),
         "build_s": round(t_build, 3),
+        "solve_s": round(t_step - t_build, 3),
         "iterations": max(its),
         "relres_true": max(rel),
         "status": status,
@@ -166,31 +203,38 @@ def main(argv=None):
                      "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_PAIRS / 1e12, 2),
                      "unit": "Tpairs/s", "frac": round(achieved / PEAK_PAIRS, 3), "traffic": None},
     }
-    # the FP64 kernel on the same GPU (one timed MVM of the same size)
+    # kernel rates of the other precisions on the same GPU (one timed MVM each, same size)
     if R == 1:
         v = torch.randn(n, dtype=torch.float64, device=dev)
-        krr.kernel_mv(Xg[:4096], Xg[:4096], wl.eps, v[:4096], prec="fp64")
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        krr.kernel_mv(Xg, None, wl.eps, v, prec="fp64")
-        e1.record()
-        torch.cuda.synchronize()
-        fp64_ms = e0.elapsed_time(e1)
-        out["mvm_gpairs_s_fp64"] = round(float(n) * n / fp64_ms / 1e6, 1)
-        out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
-        if a.fp64_solve and prec != "fp64":
-            log("bench: FP64 solve for comparison")
-            P64 = krr.Preconditioner(Xg, wl.eps, list(wl.betas), wl.k, wl.l, prec="fp64", **sk)
-            t0 = time.perf_counter()
-            a64, its64, rel64, st64, _ = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P64, tol=wl.tol, maxit=a.maxit,
-                                                       prec="fp64")
+        for p2 in ("fp64", "fp32"):
+            krr.kernel_mv(Xg[:4096], None, wl.eps, v[:4096], prec=p2)
             torch.cuda.synchronize()
-            out["fp64_solve_s"] = round(time.perf_counter() - t0, 2)
-            out["fp64_iterations"] = max(its64)
-            out["alpha_rel_err_vs_fp64"] = float(torch.linalg.norm(alpha - a64) / torch.linalg.norm(a64))
-        else:
-            out["fp64_solve_s_projected"] = round(max(its) * fp64_ms / 1e3, 1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            krr.kernel_mv(Xg, None, wl.eps, v, prec=p2)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"mvm_gpairs_s_{p2}"] = round(float(n) * n / e0.elapsed_time(e1) / 1e6, 1)
+        out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
+        # the same system solved with the FP64 and the FP32 kernels (same preconditioner), after the timed
+        # region; skipped by default where the FP64 solve takes tens of minutes
+        run_fp64 = a.fp64_solve or n <= 200_000
+        if prec != "fp64" and run_fp64:
+            for p2, rep in (("fp64", 0), ("fp32", 10)):
+                log(f"bench: {p2} solve on the same GPU for comparison")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a2, its2, rel2, st2, status2 = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol,
+                                                             maxit=a.maxit, replace_every=rep, prec=p2)
+                torch.cuda.synchronize()
+                out[f"{p2}_solve_s"] = round(time.perf_counter() - t0, 3)
+                out[f"{p2}_iterations"] = max(its2)
+                out[f"{p2}_relres_true"] = max(rel2)
+                if p2 == "fp64":
+                    out["alpha_rel_err_vs_fp64"] = float(torch.linalg.norm(alpha - a2) / torch.linalg.norm(a2))
+            out["solve_speedup_vs_fp64"] = round(out["fp64_solve_s"] / (t_step - t_build), 2)
+        elif prec != "fp64":
+            out["fp64_solve_s_projected"] = round(max(its) * float(n) * n / (out["mvm_gpairs_s_fp64"] * 1e9), 1)
     if not a.no_cpu:
         log("bench: CPU oracle baseline")
         rate, rows, secs = oracle_baseline(wl.X, wl.eps)

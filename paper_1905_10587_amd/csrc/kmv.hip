@@ -291,12 +291,13 @@ std::string vkey(int d, int R, int prec) {
 }
 const int kTM[3] = {1, 2, 4};
 const int kNF[4] = {1, 2, 4, 8};
+// block variants 0..5 contract with 16x16x16 MFMAs, 6..11 with 16x16x32 (same tile shapes)
 const int kBlockNT[6] = {2, 4, 1, 2, 4, 1};
 const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 }  // namespace
 
 int kmv_num_variants(int prec, int R) {
-  if (rclass(prec, R) == 3) return 6;
+  if (rclass(prec, R) == 3) return 12;
   return prec == KRR_MIXED ? 4 : 3;
 }
 
@@ -378,8 +379,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int D = T.dpad;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
+  bool k32 = false;
   if (block) {
-    const int vb = variant < 6 ? variant : 0;
+    const int vb = variant % 6;
+    k32 = variant >= 6 && variant < 12;
     int nrc_max = 1;
     while (nrc_max * 2 <= ceil_div(R, 16)) nrc_max *= 2;
     NT = kBlockNT[vb];
@@ -401,7 +404,12 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int64_t nsrc = S.npad;
   const int RpK = block ? Rpart : Rp;                  // row width of the K part in `part`
   const int RoutK = (DV == 2 ? 2 : 1) * RpK;
-  int64_t split = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, gx * gz), nsrc / 256));
+  // Source split: enough blocks to fill the chip (>= 2048) and chunks of at most ~64K sources, so the
+  // grid is many rounds of resident blocks and the last, partly filled round costs little.  The block
+  // path caps its FP64 partial buffer near 2 GB.
+  int64_t split = std::max<int64_t>(ceil_div(2048, gx * gz), ceil_div(nsrc, 65536));
+  if (block) split = std::min<int64_t>(split, std::max<int64_t>(1, ((int64_t)1 << 28) / (T.npad * (int64_t)RoutK)));
+  split = std::max<int64_t>(1, std::min<int64_t>(split, nsrc / 256));
   const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
   split = ceil_div(nsrc, src_len);
   DevBuf<double> own;
@@ -411,10 +419,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   bool ok = true;
   if (block) {
-    ok = launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
+    ok = launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
                           prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
   } else if (prec == KRR_FP64) {
-    ok = launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, 1.0 / T.eps, part.p, s);
+    ok = launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
   } else if (prec == KRR_FP32) {
     ok = launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
   } else {

@@ -5,6 +5,15 @@
 namespace krr {
 
 template <int NCH, int NT, int NRC, int NS>
+static void gob32(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm,
+                  const uint16_t* Vl, double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_kmv_block32<NCH, NT, NRC, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint2*>(Vh),
+                     reinterpret_cast<const uint2*>(Vm), reinterpret_cast<const uint2*>(Vl), g.Rp, g.src_len, g.n_src,
+                     part, g.mpad, g.Rout);
+}
+
+template <int NCH, int NT, int NRC, int NS>
 static void gob(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm,
                 const uint16_t* Vl, double* part, hipStream_t s) {
   hipLaunchKernelGGL((k_kmv_block<NCH, NT, NRC, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
@@ -14,8 +23,10 @@ static void gob(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const ui
 }
 
 #define KRR_BNS(NCH, NT, NRC) \
-  if (NS == 3) { gob<NCH, NT, NRC, 3>(g, A, B, Vh, Vm, Vl, part, s); return true; } \
-  if (NS == 6) { gob<NCH, NT, NRC, 6>(g, A, B, Vh, Vm, Vl, part, s); return true; }
+  if (NS == 3 && !k32) { gob<NCH, NT, NRC, 3>(g, A, B, Vh, Vm, Vl, part, s); return true; } \
+  if (NS == 6 && !k32) { gob<NCH, NT, NRC, 6>(g, A, B, Vh, Vm, Vl, part, s); return true; } \
+  if (NS == 3 && k32) { gob32<NCH, NT, NRC, 3>(g, A, B, Vh, Vm, Vl, part, s); return true; } \
+  if (NS == 6 && k32) { gob32<NCH, NT, NRC, 6>(g, A, B, Vh, Vm, Vl, part, s); return true; }
 #define KRR_BTR(NCH)                                                                    \
   if (NT == 1 && NRC == 1) { KRR_BNS(NCH, 1, 1) } if (NT == 1 && NRC == 2) { KRR_BNS(NCH, 1, 2) } \
   if (NT == 1 && NRC == 4) { KRR_BNS(NCH, 1, 4) } if (NT == 1 && NRC == 8) { KRR_BNS(NCH, 1, 8) } \
@@ -23,8 +34,9 @@ static void gob(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const ui
   if (NT == 2 && NRC == 4) { KRR_BNS(NCH, 2, 4) } if (NT == 4 && NRC == 1) { KRR_BNS(NCH, 4, 1) } \
   if (NT == 4 && NRC == 2) { KRR_BNS(NCH, 4, 2) }
 
-bool launch_kmv_block(int NCH, int NT, int NRC, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                      const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s) {
+bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,
+                      const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part,
+                      hipStream_t s) {
   switch (NCH) {
     case 1: KRR_BTR(1) break;
     case 2: KRR_BTR(2) break;

@@ -14,7 +14,7 @@ struct KmvGrid {
 // FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),
 // RC in {1,4,8}, DV in {0,2}.  Return false if the combination is not instantiated.
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
-                    const double* v, double inv_eps, double* part, hipStream_t s);
+                    const double* v, double neg_c, double* part, hipStream_t s);
 bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,
                     const float* v, double* part, hipStream_t s);
 // MFMA kernel (one column per launch): NCH in {1,2,3,4,6,8,13,25}, NF in {1,2,4,8} (limited by NCH),
@@ -23,7 +23,9 @@ bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t*
                       const float* v, int col, double* part, hipStream_t s);
 int mixed_max_nf(int nch);
 // Block MVM (many right-hand sides): NCH in {1,2,3,4}, (NT, NRC) with NT * NRC <= 8, NS in {3, 6}.
-bool launch_kmv_block(int NCH, int NT, int NRC, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                      const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
+// k32: the K.V contraction on v_mfma_f32_16x16x32_bf16 (32 sources per step) instead of 16x16x16.
+bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,
+                      const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part,
+                      hipStream_t s);
 
 }  // namespace krr

@@ -5,15 +5,15 @@
 namespace krr {
 
 template <int D, int TM, int RC, int DV>
-static void go64(const KmvGrid& g, const double* xt, const double* xs, const double* v, double inv_eps,
+static void go64(const KmvGrid& g, const double* xt, const double* xs, const double* v, double neg_c,
                  double* part, hipStream_t s) {
   hipLaunchKernelGGL((k_kmv_f64<D, TM, RC, DV>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
-                     inv_eps, part, g.mpad, g.Rout);
+                     neg_c, part, g.mpad, g.Rout);
 }
 
 #define KRR_DV(D, TM, RC)                                   \
-  if (DV == 0) { go64<D, TM, RC, 0>(g, xt, xs, v, inv_eps, part, s); return true; } \
-  if (DV == 2) { go64<D, TM, RC, 2>(g, xt, xs, v, inv_eps, part, s); return true; }
+  if (DV == 0) { go64<D, TM, RC, 0>(g, xt, xs, v, neg_c, part, s); return true; } \
+  if (DV == 2) { go64<D, TM, RC, 2>(g, xt, xs, v, neg_c, part, s); return true; }
 #define KRR_RC(D, TM) \
   if (RC == 1) { KRR_DV(D, TM, 1) } if (RC == 4) { KRR_DV(D, TM, 4) } if (RC == 8) { KRR_DV(D, TM, 8) }
 #define KRR_TM3(D) \
@@ -22,7 +22,7 @@ static void go64(const KmvGrid& g, const double* xt, const double* xs, const dou
   if (TM == 1) { KRR_RC(D, 1) }
 
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
-                    const double* v, double inv_eps, double* part, hipStream_t s) {
+                    const double* v, double neg_c, double* part, hipStream_t s) {
   switch (D) {
     case 2: KRR_TM3(2) break;
     case 3: KRR_TM3(3) break;

@@ -9,32 +9,31 @@ namespace krr {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// ------------------------------------------------------------------ FP64 exp(-t), t >= 0
-// exp(-t) = 2^{-n} exp(r), n = rint(t / ln 2), r = n ln2 - t in [-ln2/2, ln2/2] (Cody-Waite with a
-// two-part ln 2 whose high part has 42 significant bits, so n * LN2_HI is exact), exp(r) by its
-// Taylor series to degree 12 (truncation below 2e-16 relative on the reduced interval).
-__device__ __forceinline__ double exp_neg_f64(double t) {
-  constexpr double LN2_HI = 0x1.62e42fefa3800p-1;
-  constexpr double LN2_LO = 0x1.ef35793c76730p-45;
-  const double n = __builtin_rint(t * kLog2e);
-  double r = __builtin_fma(n, LN2_HI, -t);
-  r = __builtin_fma(n, LN2_LO, r);
-  double p = 2.08767569878681e-09;            // 1/12!
-  p = __builtin_fma(p, r, 2.505210838544172e-08);
-  p = __builtin_fma(p, r, 2.755731922398589e-07);
-  p = __builtin_fma(p, r, 2.7557319223985893e-06);
-  p = __builtin_fma(p, r, 2.48015873015873e-05);
-  p = __builtin_fma(p, r, 0.0001984126984126984);
-  p = __builtin_fma(p, r, 0.001388888888888889);
-  p = __builtin_fma(p, r, 0.008333333333333333);
-  p = __builtin_fma(p, r, 0.041666666666666664);
-  p = __builtin_fma(p, r, 0.16666666666666666);
-  p = __builtin_fma(p, r, 0.5);
-  p = __builtin_fma(p, r, 1.0);
-  p = __builtin_fma(p, r, 1.0);
-  const double res = __builtin_ldexp(p, -(int)n);
-  return t < 708.0 ? res : 0.0;
+// ------------------------------------------------------------------ FP64 2^q, q <= 0
+// 2^q = 2^n * 2^f with n = rint(q) and f = q - n (exact, |f| <= 1/2); 2^f by a degree-10
+// near-minimax polynomial (Chebyshev fit in 50-digit arithmetic, coefficients rounded to double;
+// worst relative error 3.1e-16 on [-1/2, 1/2]; derived by gen_exp2_poly.py).  q is clamped at
+// -1020 so ldexp stays in the normal range: values below 2^-1020 come out as ~1e-307 instead of 0.
+__device__ __forceinline__ double exp2_neg_f64(double q) {
+  q = q > -1020.0 ? q : -1020.0;
+  const double n = __builtin_rint(q);
+  const double f = q - n;
+  double p = 0x1.e6063f7217bc6p-28;
+  p = __builtin_fma(p, f, 0x1.b675bca4eeebbp-24);
+  p = __builtin_fma(p, f, 0x1.62bfd47773353p-20);
+  p = __builtin_fma(p, f, 0x1.ffcb54062e698p-17);
+  p = __builtin_fma(p, f, 0x1.430913096fd9fp-13);
+  p = __builtin_fma(p, f, 0x1.5d87fe9d7a584p-10);
+  p = __builtin_fma(p, f, 0x1.3b2ab6fba1ddap-7);
+  p = __builtin_fma(p, f, 0x1.c6b08d703ce49p-5);
+  p = __builtin_fma(p, f, 0x1.ebfbdff82c598p-3);
+  p = __builtin_fma(p, f, 0x1.62e42fefa3a19p-1);
+  p = __builtin_fma(p, f, 1.0);
+  return __builtin_ldexp(p, (int)n);
 }
+
+// exp(-t) for t >= 0
+__device__ __forceinline__ double exp_neg_f64(double t) { return exp2_neg_f64(-t * kLog2e); }
 
 // ------------------------------------------------------------------ direct kernels (FP64 / FP32)
 // Block: 256 threads, each owns TM targets (strided by 256) and RC columns.  Sources stream through
@@ -49,8 +48,9 @@ struct DirectTile {
 template <int D, int TM, int RC, int DV>
 __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, const double* __restrict__ xs,
                                                  const double* __restrict__ v, int Rp, int64_t src_len,
-                                                 int64_t n_src, double inv_eps, double* __restrict__ part,
+                                                 int64_t n_src, double neg_c, double* __restrict__ part,
                                                  int64_t mpad, int Rout) {
+  // neg_c = -log2(e) / eps: the exponent q = neg_c * D^2 is the base-2 exponent of the kernel value
   constexpr int NO = DV == 2 ? 2 : 1;
   constexpr int TS = DirectTile<D>::TS;
   __shared__ double sx[TS * D];
@@ -91,14 +91,14 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
           const double df = xi[t][k] - xj[k];
           d2 = __builtin_fma(df, df, d2);
         }
-        const double tt = d2 * inv_eps;
-        const double e = exp_neg_f64(tt);
+        const double q = d2 * neg_c;
+        const double e = exp2_neg_f64(q);
         if (DV == 0 || DV == 2) {
 #pragma unroll
           for (int c = 0; c < RC; ++c) acc[t][c][0] = __builtin_fma(e, vj[c], acc[t][c][0]);
         }
         if (DV >= 1) {
-          const double ed = tt * e;
+          const double ed = -kLn2 * q * e;   // (D^2/eps) K = -ln(2) q K
 #pragma unroll
           for (int c = 0; c < RC; ++c) acc[t][c][NO - 1] = __builtin_fma(ed, vj[c], acc[t][c][NO - 1]);
         }
@@ -443,6 +443,128 @@ __global__ __launch_bounds__(256) void k_kmv_block(const uint4* __restrict__ A, 
         for (int e = 0; e < 4; ++e) acc[t][c][e] += (double)a32[t][c][e];
   }
   // lane l holds targets (l/16)*4 + e of each fragment for right-hand side l%16 of each chunk
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * t + kq * 4 + e;
+      double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout;
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) prow[rbase + 16 * c + r16] = acc[t][c][e];
+    }
+}
+
+}  // namespace krr
+
+namespace krr {
+
+__device__ __forceinline__ uint4 pack8(const uint16_t* v) {
+  return uint4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+               (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
+}
+
+// Block MVM, K = 32 form: the K.V contraction uses v_mfma_f32_16x16x32_bf16 on 32 sources at a time.
+// Two 16-source cross-term tiles give each lane 8 exp'd values (sources j+4g+e and j+16+4g+e,
+// g = lane/16, e = 0..3); the K index of the second MFMA is relabelled so that lane l's eight A slots
+// are exactly those sources, and its B slots read the same two groups of four sources from V4.
+template <int NCH, int NT, int NRC, int NS>
+__global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                     const uint2* __restrict__ Vh, const uint2* __restrict__ Vm,
+                                                     const uint2* __restrict__ Vl, int Rp, int64_t src_len,
+                                                     int64_t n_src, double* __restrict__ part, int64_t mpad,
+                                                     int Rout) {
+  constexpr int KV = NCH * 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * NT);
+  const int rbase = blockIdx.z * 16 * NRC;
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+
+  bf16x8 tg[NT][NCH];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) tg[t][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * t + r16) * KV + ch * 4 + kq]);
+
+  double acc[NT][NRC][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < NRC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][c][e] = 0.0;
+
+  for (int64_t j0 = jb; j0 < je; j0 += 256) {
+    f32x4 a32[NT][NRC];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) a32[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t j = j0; j < j0 + 256; j += 32) {
+      bf16x8 sa[NCH], sb[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        sa[ch] = __builtin_bit_cast(bf16x8, B[(j + r16) * KV + ch * 4 + kq]);
+        sb[ch] = __builtin_bit_cast(bf16x8, B[(j + 16 + r16) * KV + ch * 4 + kq]);
+      }
+      bf16x8 ph[NT], pm[NT], pl[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[ch], tg[t][ch], qa, 0, 0, 0);
+          qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sb[ch], tg[t][ch], qb, 0, 0, 0);
+        }
+        uint16_t hb[8], mb[8], lb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float p = __builtin_amdgcn_exp2f(e < 4 ? qa[e] : qb[e - 4]);
+          hb[e] = bf16_bits_rn(p);
+          const float r1 = p - bf16_bits_to_f(hb[e]);
+          mb[e] = bf16_bits_rn(r1);
+          if (NS == 6) lb[e] = bf16_bits_rn(r1 - bf16_bits_to_f(mb[e]));
+        }
+        ph[t] = __builtin_bit_cast(bf16x8, pack8(hb));
+        pm[t] = __builtin_bit_cast(bf16x8, pack8(mb));
+        if (NS == 6) pl[t] = __builtin_bit_cast(bf16x8, pack8(lb));
+      }
+      const int64_t ga = (j >> 2) + kq, gb = ga + 4;   // the lane's two groups of four sources
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) {
+        const int col = rbase + 16 * c + r16;
+        const uint2 h0 = Vh[ga * Rp + col], h1 = Vh[gb * Rp + col];
+        const uint2 m0 = Vm[ga * Rp + col], m1 = Vm[gb * Rp + col];
+        const bf16x8 vh = __builtin_bit_cast(bf16x8, uint4{h0.x, h0.y, h1.x, h1.y});
+        const bf16x8 vm = __builtin_bit_cast(bf16x8, uint4{m0.x, m0.y, m1.x, m1.y});
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[t], vh, a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[t], vm, a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm[t], vh, a32[t][c], 0, 0, 0);
+        }
+        if (NS == 6) {
+          const uint2 l0 = Vl[ga * Rp + col], l1 = Vl[gb * Rp + col];
+          const bf16x8 vl = __builtin_bit_cast(bf16x8, uint4{l0.x, l0.y, l1.x, l1.y});
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[t], vl, a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl[t], vh, a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm[t], vm, a32[t][c], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[t][c][e] += (double)a32[t][c][e];
+  }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll

@@ -300,10 +300,12 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   red.dot(r.p, z.p, n, rho, s);
 
   std::vector<double> lanczos_g, lanczos_b;
-  // Safeguards: the best iterate by true residual is kept per column; a column whose true residual
-  // grows 1e3-fold over its best, or fails to improve in 8 consecutive true-residual evaluations, is
-  // stopped (KRR_ENOCONV) and returned at its best iterate.  After a failed convergence check a column
-  // is not checked again for max(replace_every, 5) iterations.
+  // Safeguards: the best iterate by true residual is kept per column.  The residual 2-norm of CG is
+  // not monotone (CG minimises the A-norm of the error), so a column is only stopped (KRR_ENOCONV, best
+  // iterate returned) when its true residual is not finite or exceeds 1e6 times its best, or when its
+  // recursive residual has claimed convergence 8 times without the true residual reaching tol (the
+  // attainable accuracy of the recurrence is reached).  After a failed convergence check a column is
+  // not checked again for max(replace_every, 5) iterations.
   DevBuf<double> xbest(nR, s);
   DevBuf<int> mask(R, s);
   std::vector<double> best_rel(R, HUGE_VAL);
@@ -340,6 +342,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     KRR_CHECK_HIP(hipStreamSynchronize(s));
     tm.collect();
     if (hflags[1]) { breakdown = true; break; }
+    std::vector<double> hrec(h.begin(), h.begin() + R);
     if (act[0]) lanczos_g.push_back(h[R]);
     bool candidate = false;
     for (int c = 0; c < R; ++c) {
@@ -379,13 +382,15 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
           changed = true;
           continue;
         }
+        const bool was_candidate = it >= next_check[c] && std::sqrt(hrec[c]) / ynorm[c] <= tol;
         next_check[c] = it + recheck;
+        if (was_candidate) ++stall[c];
         if (rel < best_rel[c]) {
           best_rel[c] = rel;
-          stall[c] = 0;
           imp[c] = 1;
           improved = true;
-        } else if (++stall[c] >= 8 || rel > 1e3 * best_rel[c] || !std::isfinite(rel)) {
+        }
+        if (stall[c] >= 8 || rel > 1e6 * best_rel[c] || !std::isfinite(rel)) {
           act[c] = 0;
           gave_up[c] = 1;
           changed = true;

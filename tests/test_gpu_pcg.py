@@ -132,3 +132,33 @@ def test_unattainable_tolerance_returns_best_iterate(gpu_lib):
     assert rel[0] < 1e-9
     assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-5
     assert _true_relres(X, eps, beta, y, a) < 1e-9
+
+
+@pytest.mark.gpu
+def test_block_pcg_mixed_many_columns(gpu_lib):
+    """16 systems (4 labels x 4 betas) in one lockstep solve through the block MVM, vs dense Cholesky."""
+    rng = np.random.default_rng(21)
+    n, d, eps = 2500, 6, 0.5
+    X = rng.random((n, d))
+    a = 2.0 * rng.standard_normal((4, d))
+    b = 2 * np.pi * rng.random(4)
+    labels = np.sin(X @ a.T + b) + 0.05 * rng.standard_normal((n, 4))
+    betas = [1e-4, 1e-3, 1e-2, 1e-1]
+    Y = np.repeat(labels, 4, axis=1)
+    col_beta = np.tile(np.array(betas), 4)
+    idx, sign = datagen.sketch_sparse_draws(n, 220, 16, seed=5)
+    P = gpu_lib.Preconditioner(torch.from_numpy(X), eps, betas, 200, 220, idx=torch.from_numpy(idx),
+                               sign=torch.from_numpy(sign), prec="mixed")
+    A, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(Y), eps, list(col_beta), P,
+                                                tol=1e-8, maxit=20000, replace_every=10, prec="mixed")
+    A = A.cpu().numpy()
+    print(f"block mixed PCG: iterations {its}, max relres {max(rel):.2e}, replacements {st['n_replace']}")
+    assert status == 0 and max(rel) <= 1e-8
+    K = ok.kernel_matrix(X, X, eps)
+    for c in range(16):
+        ref = np.linalg.solve(K + col_beta[c] * np.eye(n), Y[:, c])
+        kappa = np.linalg.cond(K + col_beta[c] * np.eye(n))
+        err = np.linalg.norm(A[:, c] - ref) / np.linalg.norm(ref)
+        assert err <= min(1e-2, 10 * kappa * 1e-8), (c, err)
+    # columns with larger beta converge in fewer iterations
+    assert its[3] <= its[0]

@@ -24,7 +24,8 @@ def _pts(n, d, seed):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("mixed", 2e-6)])
+# mixed: the l sketch columns go through the block MVM (two BF16 parts of K and Omega; measured 3e-6)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("mixed", 1e-5)])
 def test_sketch_dense_parity(gpu_lib, prec, tol):
     X = _pts(1300, 3, 1)
     om = datagen.sketch_dense_omega(1300, 37, seed=2)
@@ -97,9 +98,9 @@ def test_build_anchors_and_factor(gpu_lib, small_build):
     info = P.info()
     S = np.array(info["S"])
     ref = op.build_precond(wl.X, wl.eps, [wl.betas[0]], wl.k, omega=om)
-    # the sketch used by the build equals the oracle's
+    # the sketch used by the build equals the oracle's (mixed build: block MVM, two BF16 parts)
     Ysk = P.get(P.SKETCH).cpu().numpy()
-    np.testing.assert_allclose(Ysk, ref["Y"], rtol=0, atol=2e-6 * np.abs(ref["Y"]).max())
+    np.testing.assert_allclose(Ysk, ref["Y"], rtol=0, atol=5e-5 * np.abs(ref["Y"]).max())
     # anchors: valid greedy pivots of the oracle's sketch (the build's sketch ran in FP32 here)
     forced = op.qrcp(ref["Y"].T, wl.k, forced=S)
     assert np.all(forced["rdiag"] >= forced["maxnorm"] * (1 - 1e-4))
