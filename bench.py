@@ -188,6 +188,7 @@ def main(argv=None):
                    "precision": prec, "replace_every": replace_every},
         "step_s": round(t_step, 3),
         "build_s": round(t_build, 3),
+        "build_phases_ms": {k: round(v, 1) for k, v in P.timings().items()},
         "solve_s": round(t_step - t_build, 3),
         "iterations": max(its),
         "relres_true": max(rel),

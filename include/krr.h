@@ -55,6 +55,10 @@ typedef enum {
 /* Library version (major*10000 + minor*100 + patch). */
 int krr_version(void);
 
+/* Optional: initialise this thread's library state on `stream` (the rocBLAS handle and the GEMM code
+ * objects the preconditioner build uses) so that the first build does not pay for it. */
+int krr_init(void* stream);
+
 /* Message describing the last error on this thread ("" if none). */
 const char* krr_last_error(void);
 
@@ -135,6 +139,11 @@ int krr_build_precond(const double* X, int64_t n, int32_t d, double eps,
  *   lam_host [host] k eigenvalues of K_SS (ascending); rdiag_host [host] k QR diagonals. */
 int krr_precond_info(const krr_precond* P, int64_t* S_host, int32_t* kept,
                      double* lam_host, double* rdiag_host, int32_t* k, int32_t* nbeta);
+
+/* Wall-clock phases of the build in milliseconds (stream synchronised between phases):
+ *   ms[0] sketch, ms[1] pivoted QR, ms[2] anchor block + EVD, ms[3] C, W = C T and M = W^T W,
+ *   ms[4] core Cholesky factors and inverses, ms[5] total.  sweeps: Jacobi sweeps used (may be NULL). */
+int krr_precond_timings(const krr_precond* P, double* ms, int32_t* sweeps);
 
 /* Copy an internal device buffer into caller memory (testing and inspection).
  *   what: 0 = W FP64 (n x kept), 1 = W FP32 (n x kept, float), 2 = L FP64 (kept x kept,

@@ -60,6 +60,7 @@ class SolveStats(ctypes.Structure):
 _vp, _i64, _i32, _f64, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
     "krr_version": ([], _i32),
+    "krr_init": ([_vp], _i32),
     "krr_last_error": ([], ctypes.c_char_p),
     "krr_set_allocator": ([_vp, _vp, _vp], _i32),
     "krr_kernel_mv": ([_vp, _i64, _vp, _i64, _i32, _f64, _vp, _i32, _vp, _i32, _i32, _vp, _vp], _i32),
@@ -69,6 +70,7 @@ _SIGS = {
                            ctypes.POINTER(_vp), _vp], _i32),
     "krr_precond_info": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "krr_precond_get": ([_vp, _i32, _i32, _vp, _sz, _vp], _i32),
+    "krr_precond_timings": ([_vp, _vp, _vp], _i32),
     "krr_precond_apply": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
     "krr_precond_free": ([_vp], None),
     "krr_pcg_solve": ([_vp, _i64, _i32, _f64, _vp, _i32, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp, _vp, _vp,
@@ -114,6 +116,7 @@ def load():
         FREE = ctypes.CFUNCTYPE(None, _vp, _vp)
         _CALLBACKS = (ALLOC(_alloc_cb), FREE(_free_cb))
         _chk(lib, lib.krr_set_allocator(ctypes.cast(_CALLBACKS[0], _vp), ctypes.cast(_CALLBACKS[1], _vp), None))
+        _chk(lib, lib.krr_init(_stream()))
     _LIB = lib
     return lib
 
@@ -243,6 +246,14 @@ class Preconditioner:
         kept = ctypes.c_int32()
         _chk(self._lib, self._lib.krr_precond_info(self._h, S, ctypes.byref(kept), lam, rd, None, None))
         return {"S": list(S), "kept": kept.value, "lam": list(lam), "rdiag": list(rd)}
+
+    def timings(self):
+        """Build phases in ms: sketch, qr, evd, factor, core, total (and the Jacobi sweep count)."""
+        ms = (ctypes.c_double * 6)()
+        sw = ctypes.c_int32()
+        _chk(self._lib, self._lib.krr_precond_timings(self._h, ms, ctypes.byref(sw)))
+        keys = ("sketch", "qr", "evd", "factor", "core", "total")
+        return {**{k: ms[i] for i, k in enumerate(keys)}, "jacobi_sweeps": sw.value}
 
     def get(self, what: int, bidx: int = 0):
         info = self.info()

@@ -52,12 +52,18 @@ __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, co
   if (rl == 0 && c < R) part[(int64_t)blockIdx.y * R + c] = red[threadIdx.x];
 }
 
-__global__ void k_colsum_final(const double* __restrict__ part, int nby, int R, double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= R) return;
-  double s = 0;
-  for (int b = 0; b < nby; ++b) s += part[(int64_t)b * R + c];
-  out[c] = s;
+// out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256).
+__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nby, int R,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  red[threadIdx.x] = (int)threadIdx.x < nby ? part[(int64_t)threadIdx.x * R + c] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 struct ColReducer {
@@ -74,7 +80,7 @@ struct ColReducer {
     dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
     if (b) hipLaunchKernelGGL(k_coldot<0>, grid, dim3(256), 0, s, a, b, n, R, CB, part.p);
     else hipLaunchKernelGGL(k_coldot<1>, grid, dim3(256), 0, s, a, a, n, R, CB, part.p);
-    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, part.p, kRedBlocks, R, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out);
     KRR_LAUNCH_CHECK();
   }
 };

@@ -90,32 +90,42 @@ __global__ void k_add_diag(const double* __restrict__ M, int k, double beta, dou
 static unsigned nblk(int64_t n, int b = 256) { return (unsigned)ceil_div(n, b); }
 
 // ------------------------------------------------------------------ Woodbury apply kernels (one column)
-constexpr int kWRows = 1024;   // rows per block in the W^T x pass
+constexpr int kWRows = 256;   // rows per block in the W^T x pass
 
-// partial[b, c] = sum_{i in block b} W[i, c] x[i]  (products and sums in FP64; W read once)
+// partial[b, c] = sum_{i in row block b} W[i, c] x[i]  (products and sums in FP64; W read once).
+// Grid: row blocks x column chunks of 256, so that the pass has several blocks per CU at n ~ 1e5.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_wt_partial(const TW* __restrict__ W, int64_t n, int kept,
                                                     const double* __restrict__ x, int ldx,
                                                     double* __restrict__ partial) {
   const int64_t i0 = (int64_t)blockIdx.x * kWRows;
   const int64_t i1 = i0 + kWRows < n ? i0 + kWRows : n;
-  for (int cb = 0; cb < kept; cb += 256) {
-    const int c = cb + threadIdx.x;
-    double acc = 0.0;
-    if (c < kept) {
-#pragma unroll 4
-      for (int64_t i = i0; i < i1; ++i) acc = __builtin_fma((double)W[i * kept + c], x[i * ldx], acc);
-      partial[(int64_t)blockIdx.x * kept + c] = acc;
-    }
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  if (c >= kept) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = i0;
+  for (; i + 4 <= i1; i += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = __builtin_fma((double)W[(i + u) * kept + c], x[(i + u) * ldx], acc[u]);
   }
+  for (; i < i1; ++i) acc[0] = __builtin_fma((double)W[i * kept + c], x[i * ldx], acc[0]);
+  partial[(int64_t)blockIdx.x * kept + c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nb, int kept, double* __restrict__ t) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= kept) return;
+// t[c] = sum_b partial[b, c]: one block per column, strided partial sums then a fixed-order LDS tree.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int nb, int kept,
+                                                         double* __restrict__ t) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
   double s = 0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * kept + c];
-  t[c] = s;
+  for (int b = threadIdx.x; b < nb; b += 256) s += partial[(int64_t)b * kept + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t[c] = red[0];
 }
 
 // z[i] = sum_c G[i, c] t[c]; G symmetric, one wave per row reading row i of G contiguously.
@@ -198,11 +208,12 @@ void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bid
     const double* G = use32 ? P.G32[b].p : P.G64[b].p;
     const int nb = (int)ceil_div(n, kWRows);
     DevBuf<double> partial((size_t)nb * kept, s), t(kept, s), z(kept, s);
+    const dim3 gw((unsigned)nb, nblk(kept));
     if (use32)
-      hipLaunchKernelGGL(k_wt_partial<float>, dim3(nb), dim3(256), 0, s, P.W32.p, n, kept, x, 1, partial.p);
+      hipLaunchKernelGGL(k_wt_partial<float>, gw, dim3(256), 0, s, P.W32.p, n, kept, x, 1, partial.p);
     else
-      hipLaunchKernelGGL(k_wt_partial<double>, dim3(nb), dim3(256), 0, s, P.W64.p, n, kept, x, 1, partial.p);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(kept)), dim3(256), 0, s, partial.p, nb, kept, t.p);
+      hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, 1, partial.p);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)kept), dim3(256), 0, s, partial.p, nb, kept, t.p);
     hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t.p, z.p);
     const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 4), 8192);
     const size_t lds = (size_t)kept * sizeof(double);
@@ -406,6 +417,24 @@ void build_precond(krr_precond& P, const double* X, const double* omega, const i
 }  // namespace krr
 
 // ================================================================== C ABI
+extern "C" int krr_init(void* stream) {
+  return krr::guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    // one tiny call of each GEMM form the build and the block Woodbury apply use
+    krr::DevBuf<double> a(64, s), b(64, s), c(64, s);
+    krr::DevBuf<float> af(64, s), bf(64, s), cf(64, s);
+    KRR_CHECK_HIP(hipMemsetAsync(a.p, 0, 64 * sizeof(double), s));
+    KRR_CHECK_HIP(hipMemsetAsync(af.p, 0, 64 * sizeof(float), s));
+    krr::dgemm(s, true, false, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
+    krr::dgemm(s, false, true, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
+    krr::dgemm(s, false, false, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
+    krr::sgemm(s, false, true, 8, 8, 8, af.p, 8, af.p, 8, cf.p, 8);
+    krr::sgemm(s, true, false, 8, 8, 8, af.p, 8, af.p, 8, cf.p, 8);
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    return (int)KRR_OK;
+  });
+}
+
 extern "C" int krr_sketch(const double* X, int64_t n, int32_t d, double eps, const double* omega, const int64_t* idx,
                           const double* sign, int32_t l, int32_t r, int32_t prec, double* Y, void* stream) {
   return krr::guarded([&] {
@@ -482,6 +511,15 @@ extern "C" int krr_precond_info(const krr_precond* P, int64_t* S_host, int32_t* 
     if (rdiag_host) std::copy(P->rdiag_host.begin(), P->rdiag_host.end(), rdiag_host);
     if (k) *k = P->k;
     if (nbeta) *nbeta = (int32_t)P->betas.size();
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_precond_timings(const krr_precond* P, double* ms, int32_t* sweeps) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(P != nullptr && ms != nullptr, "null argument");
+    for (int i = 0; i < 6; ++i) ms[i] = P->t_build_ms[i];
+    if (sweeps) *sweeps = P->jacobi_sweeps;
     return (int)KRR_OK;
   });
 }

@@ -163,33 +163,57 @@ __device__ __forceinline__ ArgMax amax(ArgMax a, ArgMax b) {
 }
 
 constexpr int kQrBlock = 256;
-constexpr int kQrCols = 4;   // columns per thread in the pass over Yt
 
-// Initial squared column norms and per-block argmax.
-template <typename T>
-__global__ __launch_bounds__(kQrBlock) void k_qr_norms(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
-                                                       double* __restrict__ nrm2, ArgMax* __restrict__ part) {
-  __shared__ ArgMax red[kQrBlock];
-  ArgMax best{-2.0, INT64_MAX};
-  const int64_t c0 = ((int64_t)blockIdx.x * kQrBlock) * kQrCols + threadIdx.x;
-  double acc[kQrCols] = {};
-  for (int i = 0; i < l; ++i) {
-    const T* row = Yt + (int64_t)i * ldy;
+// Partial column sums over one slab of rows [i0, i0 + slab): part[slab, c] = sum_i q_i Yt[i, c] (MODE 0)
+// or sum_i Yt[i, c]^2 (MODE 1).  2-D grid (column blocks x row slabs) so that a pass over Yt fills the
+// chip even when n / 256 is small; one column per thread, rows unrolled by 4 for memory-level parallelism.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kQrBlock) void k_qr_slab(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
+                                                      int slab, const double* __restrict__ q,
+                                                      double* __restrict__ part) {
+  const int64_t c = (int64_t)blockIdx.x * kQrBlock + threadIdx.x;
+  const int i0 = blockIdx.y * slab;
+  const int i1 = i0 + slab < l ? i0 + slab : l;
+  if (c >= N) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = i0;
+  for (; i + 4 <= i1; i += 4) {
 #pragma unroll
-    for (int u = 0; u < kQrCols; ++u) {
-      const int64_t c = c0 + u * kQrBlock;
-      if (c < N) {
-        const double y = (double)row[c];
-        acc[u] = __builtin_fma(y, y, acc[u]);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const double y = (double)Yt[(int64_t)(i + u) * ldy + c];
+      acc[u] = MODE == 1 ? __builtin_fma(y, y, acc[u]) : __builtin_fma(q[i + u], y, acc[u]);
     }
   }
-#pragma unroll
-  for (int u = 0; u < kQrCols; ++u) {
-    const int64_t c = c0 + u * kQrBlock;
-    if (c < N) {
-      nrm2[c] = acc[u];
-      best = amax(best, ArgMax{acc[u], c});
+  for (; i < i1; ++i) {
+    const double y = (double)Yt[(int64_t)i * ldy + c];
+    acc[0] = MODE == 1 ? __builtin_fma(y, y, acc[0]) : __builtin_fma(q[i], y, acc[0]);
+  }
+  part[(int64_t)blockIdx.y * N + c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Column update after a pass, summing the slab partials in slab order: mode 1 sets nrm2[c] to the sum
+// (initial squared norms); mode 0 downdates nrm2[c] -= r_c^2 for unselected columns (clamped at 0).
+// Writes the per-block argmax of the updated norms.
+__global__ __launch_bounds__(kQrBlock) void k_qr_update(const double* __restrict__ part, int nslab, int64_t N,
+                                                        int mode, double* __restrict__ nrm2,
+                                                        ArgMax* __restrict__ amax_part) {
+  __shared__ ArgMax red[kQrBlock];
+  const int64_t c = (int64_t)blockIdx.x * kQrBlock + threadIdx.x;
+  ArgMax best{-2.0, INT64_MAX};
+  if (c < N) {
+    double r = 0.0;
+    for (int sl = 0; sl < nslab; ++sl) r += part[(int64_t)sl * N + c];
+    if (mode == 1) {
+      nrm2[c] = r;
+      best = ArgMax{r, c};
+    } else {
+      double v = nrm2[c];
+      if (v >= 0.0) {
+        v -= r * r;
+        v = v > 0.0 ? v : 0.0;
+        nrm2[c] = v;
+        best = ArgMax{v, c};
+      }
     }
   }
   red[threadIdx.x] = best;
@@ -198,7 +222,7 @@ __global__ __launch_bounds__(kQrBlock) void k_qr_norms(const T* __restrict__ Yt,
     if ((int)threadIdx.x < w) red[threadIdx.x] = amax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) amax_part[blockIdx.x] = red[0];
 }
 
 // Final argmax over block partials -> pivot; gathers w = Yt[:, p] and records piv / rdiag.
@@ -245,14 +269,23 @@ __global__ __launch_bounds__(256) void k_qr_proj_dots(const double* __restrict__
   if (threadIdx.x == 0) t[c] = red[0];
 }
 
-// w[i] -= sum_c t[c] Q[c, i]
+// w[i] -= sum_c t[c] Q[c, i]: a block of 256 threads covers 32 rows, 8 threads per row splitting the
+// c range; partials combined in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_qr_proj_sub(const double* __restrict__ Q, int l, int j,
                                                      const double* __restrict__ t, double* __restrict__ w) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= l) return;
+  __shared__ double red[256];
+  const int rl = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + rl;
   double s = 0;
-  for (int c = 0; c < j; ++c) s = __builtin_fma(t[c], Q[(int64_t)c * l + i], s);
-  w[i] -= s;
+  if (i < l)
+    for (int c = sl; c < j; c += 8) s = __builtin_fma(t[c], Q[(int64_t)c * l + i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (sl == 0 && i < l) {
+    double tot = 0;
+    for (int u = 0; u < 8; ++u) tot += red[u * 32 + rl];
+    w[i] -= tot;
+  }
 }
 
 // q_j = w / ||w|| (single block)
@@ -272,68 +305,39 @@ __global__ __launch_bounds__(1024) void k_qr_normalize(const double* __restrict_
   for (int i = threadIdx.x; i < l; i += 1024) Q[(int64_t)j * l + i] = w[i] * inv;
 }
 
-// r[c] = q_j . Yt[:, c];  nrm2[c] -= r^2 (unselected only);  per-block argmax of the result.
-template <typename T>
-__global__ __launch_bounds__(kQrBlock) void k_qr_pass(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
-                                                      const double* __restrict__ q, double* __restrict__ nrm2,
-                                                      ArgMax* __restrict__ part) {
-  __shared__ ArgMax red[kQrBlock];
-  const int64_t c0 = ((int64_t)blockIdx.x * kQrBlock) * kQrCols + threadIdx.x;
-  double acc[kQrCols] = {};
-  for (int i = 0; i < l; ++i) {
-    const double qi = q[i];
-    const T* row = Yt + (int64_t)i * ldy;
-#pragma unroll
-    for (int u = 0; u < kQrCols; ++u) {
-      const int64_t c = c0 + u * kQrBlock;
-      if (c < N) acc[u] = __builtin_fma(qi, (double)row[c], acc[u]);
-    }
-  }
-  ArgMax best{-2.0, INT64_MAX};
-#pragma unroll
-  for (int u = 0; u < kQrCols; ++u) {
-    const int64_t c = c0 + u * kQrBlock;
-    if (c < N) {
-      double v = nrm2[c];
-      if (v >= 0.0) {
-        v -= acc[u] * acc[u];
-        v = v > 0.0 ? v : 0.0;
-        nrm2[c] = v;
-        best = amax(best, ArgMax{v, c});
-      }
-    }
-  }
-  red[threadIdx.x] = best;
-  __syncthreads();
-  for (int w = kQrBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = amax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
 template <typename T>
 static void qrcp_impl(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t* piv, double* rdiag,
                       hipStream_t s) {
-  const int64_t nblk = ceil_div(N, (int64_t)kQrBlock * kQrCols);
-  DevBuf<double> nrm2(N, s), Q((size_t)k * l, s), w(l, s), t(std::max(k, 1), s);
-  DevBuf<ArgMax> part(nblk, s);
+  const int64_t nblk = ceil_div(N, (int64_t)kQrBlock);
+  // Split the l rows into slabs so that a pass launches about 4096 blocks (at least 16 rows per slab).
+  const int want = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div((int64_t)4096, nblk)), ceil_div(l, 16));
+  const int slab = (int)ceil_div(l, want);
+  const int nslab = (int)ceil_div(l, slab);
+  DevBuf<double> nrm2(N, s), Q((size_t)k * l, s), w(l, s), t(std::max(k, 1), s), part((size_t)nslab * N, s);
+  DevBuf<ArgMax> am(nblk, s);
   DevBuf<int64_t> pcur(1, s);
-  hipLaunchKernelGGL(k_qr_norms<T>, dim3((unsigned)nblk), dim3(kQrBlock), 0, s, Yt, ldy, N, l, nrm2.p, part.p);
+  const dim3 g2((unsigned)nblk, (unsigned)nslab);
+  hipLaunchKernelGGL((k_qr_slab<T, 1>), g2, dim3(kQrBlock), 0, s, Yt, ldy, N, l, slab, (const double*)nullptr,
+                     part.p);
+  hipLaunchKernelGGL(k_qr_update, dim3((unsigned)nblk), dim3(kQrBlock), 0, s, (const double*)part.p, nslab, N, 1,
+                     nrm2.p, am.p);
   KRR_LAUNCH_CHECK();
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL(k_qr_pick<T>, dim3(1), dim3(1024), 0, s, part.p, (int)nblk, Yt, ldy, l, j, nrm2.p, piv, rdiag,
-                       w.p, pcur.p);
+    hipLaunchKernelGGL(k_qr_pick<T>, dim3(1), dim3(1024), 0, s, (const ArgMax*)am.p, (int)nblk, Yt, ldy, l, j,
+                       nrm2.p, piv, rdiag, w.p, pcur.p);
     if (j > 0) {
       for (int pass = 0; pass < 2; ++pass) {   // Gram-Schmidt twice
         hipLaunchKernelGGL(k_qr_proj_dots, dim3(j), dim3(256), 0, s, Q.p, l, j, w.p, t.p);
-        hipLaunchKernelGGL(k_qr_proj_sub, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0, s, Q.p, l, j, t.p, w.p);
+        hipLaunchKernelGGL(k_qr_proj_sub, dim3((unsigned)ceil_div(l, 32)), dim3(256), 0, s, Q.p, l, j, t.p, w.p);
       }
     }
     hipLaunchKernelGGL(k_qr_normalize, dim3(1), dim3(1024), 0, s, w.p, l, j, Q.p);
-    if (j + 1 < k)
-      hipLaunchKernelGGL(k_qr_pass<T>, dim3((unsigned)nblk), dim3(kQrBlock), 0, s, Yt, ldy, N, l,
-                         Q.p + (int64_t)j * l, nrm2.p, part.p);
+    if (j + 1 < k) {
+      hipLaunchKernelGGL((k_qr_slab<T, 0>), g2, dim3(kQrBlock), 0, s, Yt, ldy, N, l, slab,
+                         (const double*)(Q.p + (int64_t)j * l), part.p);
+      hipLaunchKernelGGL(k_qr_update, dim3((unsigned)nblk), dim3(kQrBlock), 0, s, (const double*)part.p, nslab, N,
+                         0, nrm2.p, am.p);
+    }
     KRR_LAUNCH_CHECK();
   }
 }
