@@ -174,6 +174,8 @@ typedef struct {
   double t_mvm_fp64_ms;   /* HIP-event time in FP64 MVMs */
   double t_precond_ms;    /* HIP-event time in Woodbury applies */
   double kappa_est;       /* Lanczos estimate of the preconditioned condition number, column 0 */
+  double t_mvm_kernel_ms; /* HIP-event time of the main MVM kernel alone (t_mvm_ms without operand
+                             staging and the FP64 finishing pass) */
 } krr_solve_stats;
 
 /*

@@ -51,7 +51,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iters_max", ctypes.c_int32), ("n_mvm", ctypes.c_int32), ("n_mvm_fp64", ctypes.c_int32),
                 ("n_replace", ctypes.c_int32), ("t_total_ms", ctypes.c_double), ("t_mvm_ms", ctypes.c_double),
                 ("t_mvm_fp64_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
-                ("kappa_est", ctypes.c_double)]
+                ("kappa_est", ctypes.c_double), ("t_mvm_kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -24,7 +24,7 @@ struct Staged {
 };
 
 constexpr int kRowPad = 1024;   // targets/sources are padded to multiples of this
-constexpr int kPrefetchRows = 16;   // extra allocated rows after the padded sources (prefetch reads)
+constexpr int kPrefetchRows = 32;   // extra allocated rows after the padded sources (prefetch reads)
 
 // Pads d up to the instantiated widths of the direct (FP64/FP32) kernels.
 int padded_dim(int d);
@@ -63,7 +63,8 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
 //   Vraw: the original FP64 V (n x R) for the shift term.
 void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv,
                 const double* shift_host, const double* Vraw, int prec, double* U, int64_t ldu,
-                hipStream_t s, int variant = -1, DevBuf<double>* ws = nullptr);
+                hipStream_t s, int variant = -1, DevBuf<double>* ws = nullptr,
+                const hipEvent_t* kev = nullptr);   // kev: two events recorded around the main kernel
 
 // Variant bookkeeping for the autotuner.
 int kmv_num_variants(int prec, int R);

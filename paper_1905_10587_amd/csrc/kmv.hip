@@ -298,7 +298,8 @@ const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 
 int kmv_num_variants(int prec, int R) {
   if (rclass(prec, R) == 3) return 12;
-  return prec == KRR_MIXED ? 4 : 3;
+  // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8)
+  return prec == KRR_MIXED ? 10 : 3;
 }
 
 bool kmv_uses_block(int prec, int d, int R, int deriv) {
@@ -307,7 +308,15 @@ bool kmv_uses_block(int prec, int d, int R, int deriv) {
 
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t) {
   if (rclass(prec, R) == 3) return 0;
-  if (prec == KRR_MIXED) return mixed_max_nf(mixed_chunks(d)) >= 8 ? 3 : 1;
+  if (prec == KRR_MIXED) {
+    // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
+    // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
+    const int nch = mixed_chunks(d);
+    if (nch == 1) return 3;
+    if (nch == 2) return 9;
+    if (nch <= 4) return 8;
+    return mixed_max_nf(nch) >= 2 ? 1 : 0;
+  }
   if (padded_dim(d) >= 32) return 0;
   return m >= 65536 ? 1 : 0;
 }
@@ -363,9 +372,30 @@ void kmv_table_from_json(const std::string& s) {
   for (auto& kv : parsed) g_override[kv.first] = kv.second;
 }
 
+// Resident blocks of a kernel configuration on the current device (blocks per CU x CUs), cached by key.
+template <typename Query>
+static int64_t resident_blocks(Query query, const std::string& key) {
+  int dev = 0;
+  KRR_CHECK_HIP(hipGetDevice(&dev));
+  const std::string k = std::to_string(dev) + "/" + key;
+  static std::map<std::string, int64_t> cache;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cache.find(k);
+    if (it != cache.end()) return it->second;
+  }
+  int per_cu = 0, cus = 0;
+  query(&per_cu);
+  KRR_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t cap = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
+  std::lock_guard<std::mutex> lk(g_mu);
+  cache[k] = cap;
+  return cap;
+}
+
 void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const double* shift_host,
                 const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant,
-                DevBuf<double>* ws) {
+                DevBuf<double>* ws, const hipEvent_t* kev) {
   KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
   const int R = V.Rreal, Rp = V.R;
   KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
@@ -376,6 +406,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   KRR_REQUIRE(variant < kmv_num_variants(prec, R), "unknown kernel variant");
   int64_t rows;
   int gz, TM = 1, NF = 1, RC = R == 1 ? 1 : R <= 4 ? 4 : 8;
+  int form = 0;   // mixed single-column kernel form
   const int D = T.dpad;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
@@ -392,7 +423,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     rows = 64 * NT;
     gz = V.Rb / (16 * NRC);
   } else if (prec == KRR_MIXED) {
-    NF = std::min(kNF[variant], mixed_max_nf(T.ka / 32));
+    form = variant >= 7 ? 2 : variant >= 4 ? 1 : 0;
+    NF = std::min(variant >= 7 ? kNF[variant - 6] : variant >= 4 ? kNF[variant - 3] : kNF[variant],
+                  mixed_max_nf(T.ka / 32));
+    if (!mixed_has_pp(T.ka / 32) || NF < 2) form = 0;   // no pipelined form: the plain kernel, same NF
     rows = 64 * NF;
     gz = 1;
   } else {
@@ -404,33 +438,53 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int64_t nsrc = S.npad;
   const int RpK = block ? Rpart : Rp;                  // row width of the K part in `part`
   const int RoutK = (DV == 2 ? 2 : 1) * RpK;
-  // Source split: enough blocks to fill the chip (>= 2048) and chunks of at most ~64K sources, so the
-  // grid is many rounds of resident blocks and the last, partly filled round costs little.  The block
-  // path caps its FP64 partial buffer near 2 GB.
-  int64_t split = std::max<int64_t>(ceil_div(2048, gx * gz), ceil_div(nsrc, 65536));
-  if (block) split = std::min<int64_t>(split, std::max<int64_t>(1, ((int64_t)1 << 28) / (T.npad * (int64_t)RoutK)));
-  split = std::max<int64_t>(1, std::min<int64_t>(split, nsrc / 256));
-  const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
-  split = ceil_div(nsrc, src_len);
   DevBuf<double> own;
   DevBuf<double>& part = ws ? *ws : own;
+  auto run = [&](const KmvGrid& g) -> bool {
+    if (block)
+      return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
+                              V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
+    if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
+    if (prec == KRR_FP32) return launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
+    bool ok = true;
+    for (int c = 0; c < R && ok; ++c) {
+      ok = launch_kmv_mixed(T.ka / 32, NF, DV, form, g, T.sa.p, S.sb.p, V.v32.p, c, part.p, s);
+      if (g.occ) break;
+      KRR_LAUNCH_CHECK();
+    }
+    return ok;
+  };
+  // Source split: the grid runs in rounds of `cap` resident blocks; choose the split that minimises
+  // rounds x (per-block source count + a fixed per-block cost), so the last round is not mostly idle.
+  // The block path caps its FP64 partial buffer near 2 GB.
+  KmvGrid q{dim3(1, 1, 1), 0, nsrc, T.npad, RpK, RoutK};
+  const int64_t cap = resident_blocks(
+      [&](int* occ) {
+        q.occ = occ;
+        KRR_REQUIRE(run(q), "kernel variant not instantiated for this shape");
+      },
+      vkey(T.d, R, prec) + ":" + std::to_string(variant) + ":" + std::to_string(DV));
+  int64_t smax = std::max<int64_t>(1, nsrc / 256);
+  if (block) smax = std::min<int64_t>(smax, std::max<int64_t>(1, ((int64_t)1 << 28) / (T.npad * (int64_t)RoutK)));
+  const int64_t per_split = gx * gz;
+  int64_t split = 1;
+  double best = 1e300;
+  // (source chunks of at most 64K points keep each block's run short against the kernel's total)
+  for (int64_t sp = std::min(smax, ceil_div(nsrc, 65536)); sp <= smax; ++sp) {
+    const int64_t len = round_up(ceil_div(nsrc, sp), 256);
+    const int64_t spl = ceil_div(nsrc, len);
+    if (spl != sp) continue;   // the same source length as a smaller split
+    const double rounds = (double)ceil_div(per_split * spl, cap);
+    const double cost = rounds * (double)(len + 512);
+    if (cost < best * (1 - 1e-9)) { best = cost; split = spl; }
+  }
+  const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
   const size_t need = (size_t)split * T.npad * RoutK;
   if (part.n < need) part.alloc(need, s);
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
-  bool ok = true;
-  if (block) {
-    ok = launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
-                          prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
-  } else if (prec == KRR_FP64) {
-    ok = launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
-  } else if (prec == KRR_FP32) {
-    ok = launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
-  } else {
-    for (int c = 0; c < R && ok; ++c) {
-      ok = launch_kmv_mixed(T.ka / 32, NF, DV, g, T.sa.p, S.sb.p, V.v32.p, c, part.p, s);
-      KRR_LAUNCH_CHECK();
-    }
-  }
+  if (kev) KRR_CHECK_HIP(hipEventRecord(kev[0], s));
+  const bool ok = run(g);
+  if (kev) KRR_CHECK_HIP(hipEventRecord(kev[1], s));
   KRR_REQUIRE(ok, "kernel variant not instantiated for this shape");
   KRR_LAUNCH_CHECK();
   ShiftArg sh{};

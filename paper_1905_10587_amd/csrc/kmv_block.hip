@@ -7,6 +7,10 @@ namespace krr {
 template <int NCH, int NT, int NRC, int NS>
 static void gob32(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm,
                   const uint16_t* Vl, double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32<NCH, NT, NRC, NS>, 256, 0));
+    return;
+  }
   hipLaunchKernelGGL((k_kmv_block32<NCH, NT, NRC, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
                      reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint2*>(Vh),
                      reinterpret_cast<const uint2*>(Vm), reinterpret_cast<const uint2*>(Vl), g.Rp, g.src_len, g.n_src,
@@ -16,6 +20,10 @@ static void gob32(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const 
 template <int NCH, int NT, int NRC, int NS>
 static void gob(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm,
                 const uint16_t* Vl, double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block<NCH, NT, NRC, NS>, 256, 0));
+    return;
+  }
   hipLaunchKernelGGL((k_kmv_block<NCH, NT, NRC, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
                      reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint2*>(Vh),
                      reinterpret_cast<const uint2*>(Vm), reinterpret_cast<const uint2*>(Vl), g.Rp, g.src_len, g.n_src,

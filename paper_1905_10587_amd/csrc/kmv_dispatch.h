@@ -9,6 +9,8 @@ struct KmvGrid {
   dim3 grid;
   int64_t src_len, n_src, mpad;
   int Rp, Rout;
+  // When set, the launcher writes the kernel's resident blocks per CU here instead of launching.
+  int* occ = nullptr;
 };
 
 // FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),
@@ -18,10 +20,12 @@ bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const doubl
 bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,
                     const float* v, double* part, hipStream_t s);
 // MFMA kernel (one column per launch): NCH in {1,2,3,4,6,8,13,25}, NF in {1,2,4,8} (limited by NCH),
-// DV in {0,2}.
-bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                      const float* v, int col, double* part, hipStream_t s);
+// DV in {0,2}.  form 0: plain; 1: software-pipelined; 2: pipelined with LDS-staged source tiles
+// (forms 1 and 2: NCH <= 4, NF >= 2; all forms give identical results).
+bool launch_kmv_mixed(int NCH, int NF, int DV, int form, const KmvGrid& g, const uint16_t* A,
+                      const uint16_t* B, const float* v, int col, double* part, hipStream_t s);
 int mixed_max_nf(int nch);
+bool mixed_has_pp(int nch);
 // Block MVM (many right-hand sides): NCH in {1,2,3,4}, (NT, NRC) with NT * NRC <= 8, NS in {3, 6}.
 // k32: the K.V contraction on v_mfma_f32_16x16x32_bf16 (32 sources per step) instead of 16x16x16.
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,

@@ -7,6 +7,10 @@ namespace krr {
 template <int D, int TM, int RC, int DV>
 static void go32(const KmvGrid& g, const float* xt, const float* xs, const float* v,
                  double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f32<D, TM, RC, DV>, 256, 0));
+    return;
+  }
   hipLaunchKernelGGL((k_kmv_f32<D, TM, RC, DV>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
                      part, g.mpad, g.Rout);
 }

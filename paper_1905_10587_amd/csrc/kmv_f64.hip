@@ -7,6 +7,10 @@ namespace krr {
 template <int D, int TM, int RC, int DV>
 static void go64(const KmvGrid& g, const double* xt, const double* xs, const double* v, double neg_c,
                  double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64<D, TM, RC, DV>, 256, 0));
+    return;
+  }
   hipLaunchKernelGGL((k_kmv_f64<D, TM, RC, DV>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
                      neg_c, part, g.mpad, g.Rout);
 }

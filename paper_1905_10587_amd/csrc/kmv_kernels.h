@@ -331,6 +331,343 @@ __global__ __launch_bounds__(256) void k_kmv_mixed(const uint4* __restrict__ A, 
 }
 
 
+// Pipelined form of k_kmv_mixed (same arithmetic, same per-lane summation order, so the results are
+// identical).  The MFMA stream runs two fragments ahead of the exp/FMA stream across step boundaries:
+// while a wave evaluates the exps of fragment f it issues the MFMAs of fragment f + 2, which for the last
+// two fragments of a step belong to the next step (source fragments are prefetched two steps ahead).
+// Scheduling barriers interleave one MFMA with a group of VALU instructions, so the matrix core works
+// under the wave's own exp/FMA work instead of in a separate burst.  NF >= 2.
+template <int NCH, int NF, int DV>
+__global__ __launch_bounds__(256) void k_kmv_mixed_pp(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                      const float* __restrict__ v, int Rp, int col,
+                                                      int64_t src_len, int64_t n_src, double* __restrict__ part,
+                                                      int64_t mpad, int Rout, int out_col) {
+  static_assert(NF >= 2, "the cross-step pipeline needs two fragments per step");
+  constexpr int NO = DV == 2 ? 2 : 1;
+  constexpr int KV = NCH * 4;
+  constexpr int VPER = (DV == 0 ? 8 : 14) / NCH;   // VALU instructions placed after each MFMA
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * NF);
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+
+  bf16x8 a[NF][NCH];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      a[f][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * f + r16) * KV + ch * 4 + kq]);
+
+  double acc[NF][4][NO];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) acc[f][e][o] = 0.0;
+  constexpr float kNegLn2f = -0.69314718055994531f;
+
+  // b: fragment of the current step, bn: next step, bn2: two steps ahead (loaded at the top of a step).
+  // The staged source arrays carry 32 padding rows, so the loads past the last step stay in bounds.
+  const uint4* bp = B + (jb + r16) * KV + kq;
+  const float* vp = v + (jb + r16) * Rp + col;
+  const int64_t bstep = 16 * KV;
+  const int64_t vstep = 16 * (int64_t)Rp;
+  bf16x8 b[NCH], bn[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    b[ch] = __builtin_bit_cast(bf16x8, bp[ch * 4]);
+    bn[ch] = __builtin_bit_cast(bf16x8, bp[bstep + ch * 4]);
+  }
+  float vj = vp[0], vn = vp[vstep];
+  bp += 2 * bstep;
+  vp += 2 * vstep;
+  f32x4 q0 = f32x4{0.f, 0.f, 0.f, 0.f}, q1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ch], b[ch], q0, 0, 0, 0);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][ch], b[ch], q1, 0, 0, 0);
+
+  for (int64_t j0 = jb; j0 < je; j0 += 256) {
+    float a32[NF][4][NO];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) a32[f][e][o] = 0.0f;
+    for (int step = 0; step < 16; ++step) {
+      bf16x8 bn2[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) bn2[ch] = __builtin_bit_cast(bf16x8, bp[ch * 4]);
+      const float vn2 = *vp;
+      bp += bstep;
+      vp += vstep;
+      __builtin_amdgcn_sched_group_barrier(0x020, NCH + 1, 0);   // the prefetch loads go first
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        f32x4 q2 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (f + 2 < NF) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 < NF ? f + 2 : 0][ch], b[ch], q2, 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 - NF >= 0 ? f + 2 - NF : 0][ch], bn[ch], q2, 0,
+                                                         0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float ex = __builtin_amdgcn_exp2f(q0[e]);
+          if (DV == 0 || DV == 2) a32[f][e][0] = __builtin_fmaf(ex, vj, a32[f][e][0]);
+          if (DV >= 1) a32[f][e][NO - 1] = __builtin_fmaf(q0[e] * ex, kNegLn2f * vj, a32[f][e][NO - 1]);
+        }
+        q0 = q1;
+        q1 = q2;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, VPER, 0);   // then VALU work
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep fragments in order (MFMA results are consumed 2 later)
+      }
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        b[ch] = bn[ch];
+        bn[ch] = bn2[ch];
+      }
+      vj = vn;
+      vn = vn2;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[f][e][o] += (double)a32[f][e][o];
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        double x = acc[f][e][o];
+        x += __shfl_xor(x, 8);
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 1);
+        acc[f][e][o] = x;
+      }
+  if (r16 == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = row0 + 16 * f + kq * 4 + e;
+        double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout;
+        prow[out_col] = acc[f][e][0];
+        if (DV == 2) prow[Rp + out_col] = acc[f][e][1];
+      }
+  }
+}
+
+// LDS-staged form of k_kmv_mixed_pp (same arithmetic and per-lane summation order: identical results).
+// The four waves of a block share one copy of each source tile: TS sources of split vectors are moved
+// from global memory into LDS by direct global->LDS loads (16 bytes per lane, fully coalesced), double
+// buffered so that tile t+1 streams in while tile t is evaluated.  Rows are stored with one pad unit
+// (stride KV + 1 units of 16 bytes, odd), so the per-step fragment reads (16 rows x 16 bytes per quarter
+// wave) fall in distinct banks.  The weights v of the next tile go through a register into LDS.
+template <int NCH, int NF, int DV>
+__global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                       const float* __restrict__ v, int Rp, int col,
+                                                       int64_t src_len, int64_t n_src, double* __restrict__ part,
+                                                       int64_t mpad, int Rout, int out_col) {
+  static_assert(NF >= 2, "the pipeline needs two fragments per step");
+  constexpr int NO = DV == 2 ? 2 : 1;
+  constexpr int KV = NCH * 4;
+  constexpr int RS = KV + 1;                 // LDS row stride in 16-byte units
+  constexpr int TS = NCH <= 2 ? 256 : 128;   // sources per tile
+  constexpr int SPT = TS / 16;               // steps per tile
+  constexpr int NI = (TS * RS + 63) / 64;    // direct loads of 64 units per tile
+  constexpr int SBU = NI * 64 + 16 * RS;     // + 16 rows read (and discarded) by the last step's look-ahead
+  constexpr int VPER = (DV == 0 ? 8 : 14) / NCH;
+  __shared__ uint4 sb0[SBU], sb1[SBU];
+  __shared__ float sv0[TS + 16], sv1[TS + 16];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * NF);
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+  const int64_t ntile = (je - jb) / TS;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+
+  bf16x8 a[NF][NCH];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      a[f][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * f + r16) * KV + ch * 4 + kq]);
+
+  double acc[NF][4][NO];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) acc[f][e][o] = 0.0;
+  float a32[NF][4][NO];
+  auto clear32 = [&]() {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) a32[f][e][o] = 0.0f;
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[f][e][o] += (double)a32[f][e][o];
+    clear32();
+  };
+  constexpr float kNegLn2f = -0.69314718055994531f;
+
+  // Tile j0 -> LDS: slot s of the tile holds unit u of source row r (s = r * RS + u); the pad unit and
+  // the slots past TS * RS load a valid unit of the tile that is never read.
+  auto issue = [&](uint4* dst, int64_t j0) {
+    for (int i = wave; i < NI; i += 4) {
+      const int slot = i * 64 + lane;
+      int r = slot / RS, u = slot - r * RS;
+      if (u == KV) u = 0;
+      if (r >= TS) { r = 0; u = 0; }
+      __builtin_amdgcn_global_load_lds(B + (j0 + r) * KV + u, dst + i * 64, 16, 0, 0);
+    }
+  };
+  auto vload = [&](int64_t j0) -> float { return tid < TS ? v[(j0 + tid) * Rp + col] : 0.0f; };
+
+  auto compute = [&](const uint4* sb, const float* sv) {
+    bf16x8 b[NCH], bn[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) b[ch] = __builtin_bit_cast(bf16x8, sb[r16 * RS + ch * 4 + kq]);
+    float vj = sv[r16];
+    f32x4 q0 = f32x4{0.f, 0.f, 0.f, 0.f}, q1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ch], b[ch], q0, 0, 0, 0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][ch], b[ch], q1, 0, 0, 0);
+#pragma unroll 1
+    for (int st = 0; st < SPT; ++st) {
+      // look-ahead fragment of the next step (for the last step: pad rows, results discarded)
+      const int rn = (st + 1) * 16 + r16;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, sb[rn * RS + ch * 4 + kq]);
+      const float vn = sv[rn];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        f32x4 q2 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (f + 2 < NF) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 < NF ? f + 2 : 0][ch], b[ch], q2, 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 - NF >= 0 ? f + 2 - NF : 0][ch], bn[ch], q2, 0,
+                                                         0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float ex = __builtin_amdgcn_exp2f(q0[e]);
+          if (DV == 0 || DV == 2) a32[f][e][0] = __builtin_fmaf(ex, vj, a32[f][e][0]);
+          if (DV >= 1) a32[f][e][NO - 1] = __builtin_fmaf(q0[e] * ex, kNegLn2f * vj, a32[f][e][NO - 1]);
+        }
+        q0 = q1;
+        q1 = q2;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, VPER, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) b[ch] = bn[ch];
+      vj = vn;
+    }
+  };
+
+  clear32();
+  if (ntile > 0) {
+    issue(sb0, jb);
+    const float v0 = vload(jb);
+    if (tid < TS) sv0[tid] = v0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  for (int64_t t = 0; t < ntile; t += 2) {
+    // tile t from buffer 0 while tile t + 1 streams into buffer 1
+    const bool has1 = t + 1 < ntile;
+    float vr = 0.0f;
+    if (has1) {
+      issue(sb1, jb + (t + 1) * TS);
+      vr = vload(jb + (t + 1) * TS);
+    }
+    compute(sb0, sv0);
+    if (TS == 256) fold();
+    if (has1 && tid < TS) sv1[tid] = vr;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (!has1) break;
+    // tile t + 1 from buffer 1 while tile t + 2 streams into buffer 0
+    const bool has2 = t + 2 < ntile;
+    if (has2) {
+      issue(sb0, jb + (t + 2) * TS);
+      vr = vload(jb + (t + 2) * TS);
+    }
+    compute(sb1, sv1);
+    fold();   // TS = 256: one tile; TS = 128: the pair of tiles, 256 sources
+    if (has2 && tid < TS) sv0[tid] = vr;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        double x = acc[f][e][o];
+        x += __shfl_xor(x, 8);
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 1);
+        acc[f][e][o] = x;
+      }
+  if (r16 == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = row0 + 16 * f + kq * 4 + e;
+        double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout;
+        prow[out_col] = acc[f][e][0];
+        if (DV == 2) prow[Rp + out_col] = acc[f][e][1];
+      }
+  }
+}
+
 }  // namespace krr
 
 namespace krr {

@@ -9,7 +9,35 @@ int mixed_max_nf(int nch) { return nch <= 2 ? 8 : nch <= 4 ? 4 : nch <= 8 ? 2 : 
 template <int NCH, int NF, int DV>
 static void gom(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const float* v, int col, double* part,
                 hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_mixed<NCH, NF, DV>, 256, 0));
+    return;
+  }
   hipLaunchKernelGGL((k_kmv_mixed<NCH, NF, DV>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), v, g.Rp, col, g.src_len, g.n_src, part, g.mpad, g.Rout,
+                     col);
+}
+
+template <int NCH, int NF, int DV>
+static void gop(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const float* v, int col, double* part,
+                hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_mixed_pp<NCH, NF, DV>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_mixed_pp<NCH, NF, DV>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), v, g.Rp, col, g.src_len, g.n_src, part, g.mpad, g.Rout,
+                     col);
+}
+
+template <int NCH, int NF, int DV>
+static void gol(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const float* v, int col, double* part,
+                hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_mixed_lds<NCH, NF, DV>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_mixed_lds<NCH, NF, DV>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
                      reinterpret_cast<const uint4*>(B), v, g.Rp, col, g.src_len, g.n_src, part, g.mpad, g.Rout,
                      col);
 }
@@ -17,6 +45,16 @@ static void gom(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const fl
 #define KRR_MDV(NCH, NF)                                                        \
   if (DV == 0) { gom<NCH, NF, 0>(g, A, B, v, col, part, s); return true; }   \
   if (DV == 2) { gom<NCH, NF, 2>(g, A, B, v, col, part, s); return true; }
+#define KRR_PDV(NCH, NF)                                                        \
+  if (DV == 0) { gop<NCH, NF, 0>(g, A, B, v, col, part, s); return true; }   \
+  if (DV == 2) { gop<NCH, NF, 2>(g, A, B, v, col, part, s); return true; }
+#define KRR_LDV(NCH, NF)                                                        \
+  if (DV == 0) { gol<NCH, NF, 0>(g, A, B, v, col, part, s); return true; }   \
+  if (DV == 2) { gol<NCH, NF, 2>(g, A, B, v, col, part, s); return true; }
+#define KRR_LNF8(NCH) \
+  if (NF == 2) { KRR_LDV(NCH, 2) } if (NF == 4) { KRR_LDV(NCH, 4) } if (NF == 8) { KRR_LDV(NCH, 8) }
+#define KRR_LNF4(NCH) \
+  if (NF == 2) { KRR_LDV(NCH, 2) } if (NF == 4) { KRR_LDV(NCH, 4) }
 #define KRR_NF8(NCH) \
   if (NF == 1) { KRR_MDV(NCH, 1) } if (NF == 2) { KRR_MDV(NCH, 2) } if (NF == 4) { KRR_MDV(NCH, 4) } if (NF == 8) { KRR_MDV(NCH, 8) }
 #define KRR_NF4(NCH) \
@@ -25,9 +63,33 @@ static void gom(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const fl
   if (NF == 1) { KRR_MDV(NCH, 1) } if (NF == 2) { KRR_MDV(NCH, 2) }
 #define KRR_NF1(NCH) \
   if (NF == 1) { KRR_MDV(NCH, 1) }
+#define KRR_PNF8(NCH) \
+  if (NF == 2) { KRR_PDV(NCH, 2) } if (NF == 4) { KRR_PDV(NCH, 4) } if (NF == 8) { KRR_PDV(NCH, 8) }
+#define KRR_PNF4(NCH) \
+  if (NF == 2) { KRR_PDV(NCH, 2) } if (NF == 4) { KRR_PDV(NCH, 4) }
 
-bool launch_kmv_mixed(int NCH, int NF, int DV, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                      const float* v, int col, double* part, hipStream_t s) {
+bool mixed_has_pp(int nch) { return nch <= 4; }
+
+bool launch_kmv_mixed(int NCH, int NF, int DV, int form, const KmvGrid& g, const uint16_t* A,
+                      const uint16_t* B, const float* v, int col, double* part, hipStream_t s) {
+  if (form == 2) {
+    switch (NCH) {
+      case 1: KRR_LNF8(1) break;
+      case 2: KRR_LNF8(2) break;
+      case 3: KRR_LNF4(3) break;
+      case 4: KRR_LNF4(4) break;
+    }
+    return false;
+  }
+  if (form == 1) {
+    switch (NCH) {
+      case 1: KRR_PNF8(1) break;
+      case 2: KRR_PNF8(2) break;
+      case 3: KRR_PNF4(3) break;
+      case 4: KRR_PNF4(4) break;
+    }
+    return false;
+  }
   switch (NCH) {
     case 1: KRR_NF8(1) break;
     case 2: KRR_NF8(2) break;

@@ -169,14 +169,29 @@ struct EventTimer {
     KRR_CHECK_HIP(hipEventCreate(&a));
     KRR_CHECK_HIP(hipEventCreate(&b));
     KRR_CHECK_HIP(hipEventRecord(a, s));
+    open = ev.size();
     ev.push_back({a, b});
     acc = where;
     pending.push_back(where);
   }
-  void stop() {
+  void stop() {   // ends the interval opened by the last start() (external pairs may follow it)
     if (!on) return;
-    KRR_CHECK_HIP(hipEventRecord(ev.back().second, s));
+    KRR_CHECK_HIP(hipEventRecord(ev[open].second, s));
   }
+  size_t open = 0;
+  // a pair of events that the callee records (around one kernel inside a library call); nullptr when off
+  const hipEvent_t* external(double* where) {
+    if (!on) return nullptr;
+    hipEvent_t a, b;
+    KRR_CHECK_HIP(hipEventCreate(&a));
+    KRR_CHECK_HIP(hipEventCreate(&b));
+    ev.push_back({a, b});
+    pending.push_back(where);
+    ext[0] = a;
+    ext[1] = b;
+    return ext;
+  }
+  hipEvent_t ext[2] = {nullptr, nullptr};
   // collect after a synchronise
   void collect() {
     for (size_t i = 0; i < ev.size(); ++i) {
@@ -215,9 +230,9 @@ struct Operator {
     stage_points(S, X, n, d, eps, prec, center, true, true, s);
   }
   // out = (K + diag(shift)) v   (shift may be null)
-  void apply(const double* v, const double* shift, double* out, hipStream_t s) {
+  void apply(const double* v, const double* shift, double* out, hipStream_t s, const hipEvent_t* kev = nullptr) {
     stage_vectors(V, v, n, S.npad, R, prec, s);
-    kmv_launch(S, S, V, 0, shift, v, prec, out, R, s, -1, &ws);
+    kmv_launch(S, S, V, 0, shift, v, prec, out, R, s, -1, &ws, kev);
   }
 };
 
@@ -334,7 +349,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     ++it;
     // q = (K + beta I) p in the working precision
     tm.start(&res.st.t_mvm_ms);
-    Aw.apply(p.p, betas, q.p, s);
+    Aw.apply(p.p, betas, q.p, s, tm.external(&res.st.t_mvm_kernel_ms));
     tm.stop();
     res.st.n_mvm++;
     red.dot(p.p, q.p, n, pq, s);

@@ -128,3 +128,52 @@ def test_block_mv_parity(gpu_lib, prec, tol, case):
         print(f"block {prec} m={m} n={n} d={d} R={R} variant={variant}: max scaled error {err:.2e}", flush=True)
         assert err <= tol
     gpu_lib.set_variant(d, R, prec, -1)
+
+
+MIXED_VARIANT_CASES = [
+    # (m, n, d, deriv): d = 3, 8, 13, 20 give 1, 2, 3, 4 K chunks of the split cross term; d = 30 has none
+    # of the pipelined forms (it falls back to the plain kernel)
+    (1100, 2500, 3, 0),
+    (2100, 1300, 8, 0),
+    (1030, 1700, 13, 0),
+    (1500, 1100, 20, 0),
+    (600, 1500, 30, 0),
+    (1100, 1900, 8, 1),
+    (900, 1200, 3, 2),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", MIXED_VARIANT_CASES, ids=[f"m{c[0]}_n{c[1]}_d{c[2]}_deriv{c[3]}"
+                                                           for c in MIXED_VARIANT_CASES])
+def test_mixed_single_column_variants(gpu_lib, case):
+    """Every single-column MFMA variant (plain NF 1, 2, 4, 8; pipelined NF 2, 4, 8; pipelined with LDS-staged
+    source tiles NF 2, 4, 8), incl. K' and (K, K')."""
+    m, n, d, deriv = case
+    rng = np.random.default_rng(m * 7 + d)
+    Xs = rng.random((n, d))
+    Xt = rng.random((m, d))
+    v = rng.standard_normal(n)
+    eps = 0.05 * d
+    refs = ok.kernel_mv(Xt, Xs, eps, v, deriv=deriv)
+    scales = ok.kernel_mv(Xt, Xs, eps, np.abs(v), deriv=deriv)
+    if deriv != 2:
+        refs, scales = [refs], [scales]
+    outs = {}
+    for variant in range(gpu_lib.num_variants("mixed", 1)):
+        gpu_lib.set_variant(d, 1, "mixed", variant)
+        U = gpu_lib.kernel_mv(torch.from_numpy(Xt), torch.from_numpy(Xs), eps, torch.from_numpy(v), deriv=deriv,
+                              prec="mixed").cpu().numpy()
+        cols = [U[:, c] for c in range(2)] if deriv == 2 else [U.reshape(-1)]
+        for c, (ref, scale) in enumerate(zip(refs, scales)):
+            err = _scaled_err(cols[c], ref, scale)
+            print(f"mixed m={m} n={n} d={d} deriv={deriv} variant={variant} part={c}: max scaled error {err:.2e}",
+                  flush=True)
+            assert err <= TOL["mixed"]
+        outs[variant] = U
+    gpu_lib.set_variant(d, 1, "mixed", -1)
+    # the pipelined kernels keep the plain kernels' per-lane summation order, and at these sizes every
+    # variant runs in one round of resident blocks with the same source split: identical results
+    for plain, piped, staged in ((1, 4, 7), (2, 5, 8), (3, 6, 9)):
+        assert np.array_equal(outs[plain], outs[piped]), (plain, piped)
+        assert np.array_equal(outs[plain], outs[staged]), (plain, staged)

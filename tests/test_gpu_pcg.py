@@ -58,11 +58,14 @@ def test_pcg_reduced_precision_with_replacement(gpu_lib, small, prec):
     wl, om, P, ref = small
     beta = wl.betas[0]
     a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(wl.X), torch.from_numpy(wl.y), wl.eps, beta, P,
-                                                tol=1e-9, maxit=5000, replace_every=10, prec=prec)
+                                                tol=1e-9, maxit=5000, replace_every=10, prec=prec, timing=True)
     a = a.cpu().numpy()
     err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
-    print(f"{prec} PCG: {its[0]} its, relres {rel[0]:.2e}, replacements {st['n_replace']}, alpha err {err:.2e}")
+    print(f"{prec} PCG: {its[0]} its, relres {rel[0]:.2e}, replacements {st['n_replace']}, alpha err {err:.2e}, "
+          f"MVM {st['t_mvm_ms']:.2f} ms (kernel {st['t_mvm_kernel_ms']:.2f} ms), FP64 {st['t_mvm_fp64_ms']:.2f} ms")
     assert status == 0 and rel[0] <= 1e-9
+    # phase timers: the main kernel's time is part of the whole working-precision MVM's time
+    assert 0 < st["t_mvm_kernel_ms"] <= st["t_mvm_ms"] and st["t_mvm_fp64_ms"] > 0 and st["t_precond_ms"] > 0
     assert _true_relres(wl.X, wl.eps, beta, wl.y, a) <= 2e-9
     assert err <= 1e-4
 
