@@ -298,20 +298,22 @@ const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 
 int kmv_num_variants(int prec, int R) {
   if (rclass(prec, R) == 3) return 12;
-  // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8)
-  return prec == KRR_MIXED ? 10 : 3;
+  // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
+  // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9)
+  return prec == KRR_MIXED ? 12 : 3;
 }
 
 bool kmv_uses_block(int prec, int d, int R, int deriv) {
   return deriv == 0 && rclass(prec, R) == 3 && mixed_chunks(d) <= 4;
 }
 
-int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t) {
+int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square) {
   if (rclass(prec, R) == 3) return 0;
   if (prec == KRR_MIXED) {
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
     const int nch = mixed_chunks(d);
+    if (square && R == 1 && nch <= 4) return 10;   // symmetric square product
     if (nch == 1) return 3;
     if (nch == 2) return 9;
     if (nch <= 4) return 8;
@@ -372,6 +374,19 @@ void kmv_table_from_json(const std::string& s) {
   for (auto& kv : parsed) g_override[kv.first] = kv.second;
 }
 
+// Compute units of the current device (cached per device).
+static int64_t device_cus() {
+  int dev = 0;
+  KRR_CHECK_HIP(hipGetDevice(&dev));
+  static std::map<int, int64_t> cache;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  KRR_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cache[dev] = std::max(cus, 1);
+}
+
 // Resident blocks of a kernel configuration on the current device (blocks per CU x CUs), cached by key.
 template <typename Query>
 static int64_t resident_blocks(Query query, const std::string& key) {
@@ -402,11 +417,12 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int DV = deriv == 0 ? 0 : 2;
   const int Rout = (DV == 2 ? 2 : 1) * Rp;
   if (variant < 0) variant = kmv_get_override(T.d, R, prec);
-  if (variant < 0) variant = kmv_default_variant(prec, T.d, R, T.n, S.n);
+  if (variant < 0) variant = kmv_default_variant(prec, T.d, R, T.n, S.n, &T == &S && deriv == 0);
   KRR_REQUIRE(variant < kmv_num_variants(prec, R), "unknown kernel variant");
   int64_t rows;
   int gz, TM = 1, NF = 1, RC = R == 1 ? 1 : R <= 4 ? 4 : 8;
   int form = 0;   // mixed single-column kernel form
+  bool sym = false;   // symmetric square product (mixed, one column)
   const int D = T.dpad;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
@@ -423,10 +439,20 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     rows = 64 * NT;
     gz = V.Rb / (16 * NRC);
   } else if (prec == KRR_MIXED) {
-    form = variant >= 7 ? 2 : variant >= 4 ? 1 : 0;
-    NF = std::min(variant >= 7 ? kNF[variant - 6] : variant >= 4 ? kNF[variant - 3] : kNF[variant],
-                  mixed_max_nf(T.ka / 32));
-    if (!mixed_has_pp(T.ka / 32) || NF < 2) form = 0;   // no pipelined form: the plain kernel, same NF
+    const int nch = T.ka / 32;
+    int var = variant;
+    if (var >= 10) {
+      // the symmetric form needs the square product of one column without the derivative kernel
+      sym = &T == &S && DV == 0 && R == 1 && nch <= 4;
+      if (!sym) var -= 2;
+    }
+    if (sym) {
+      NF = nch <= 2 && var == 11 ? 8 : 4;
+    } else {
+      form = var >= 7 ? 2 : var >= 4 ? 1 : 0;
+      NF = std::min(var >= 7 ? kNF[var - 6] : var >= 4 ? kNF[var - 3] : kNF[var], mixed_max_nf(nch));
+      if (!mixed_has_pp(nch) || NF < 2) form = 0;   // no pipelined form: the plain kernel, same NF
+    }
     rows = 64 * NF;
     gz = 1;
   } else {
@@ -437,7 +463,8 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int64_t gx = T.npad / rows;
   const int64_t nsrc = S.npad;
   const int RpK = block ? Rpart : Rp;                  // row width of the K part in `part`
-  const int RoutK = (DV == 2 ? 2 : 1) * RpK;
+  // one column without the derivative kernel: partials are stored densely (one value per row and split)
+  const int RoutK = !block && DV == 0 && R == 1 ? 1 : (DV == 2 ? 2 : 1) * RpK;
   DevBuf<double> own;
   DevBuf<double>& part = ws ? *ws : own;
   auto run = [&](const KmvGrid& g) -> bool {
@@ -446,6 +473,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP32) return launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
+    if (sym) return launch_kmv_mixed_sym(T.ka / 32, NF, g, T.sa.p, S.sb.p, V.v32.p, part.p, s);
     bool ok = true;
     for (int c = 0; c < R && ok; ++c) {
       ok = launch_kmv_mixed(T.ka / 32, NF, DV, form, g, T.sa.p, S.sb.p, V.v32.p, c, part.p, s);
@@ -478,10 +506,32 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     const double cost = rounds * (double)(len + 512);
     if (cost < best * (1 - 1e-9)) { best = cost; split = spl; }
   }
-  const int64_t src_len = round_up(ceil_div(nsrc, split), 256);
+  int64_t src_len = round_up(ceil_div(nsrc, split), 256);
+  KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
+  if (sym) {
+    // super-tile edge E: the per-CU work ceil(items / CUs) x E^2 (at least two blocks per CU to hide
+    // latency) is minimised, with the partial buffer (NS x npad doubles) kept near 2 GB
+    const int64_t cus = device_cus();
+    int64_t bestE = 0;
+    double bestc = 1e300;
+    for (int64_t E : {1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384}) {
+      if (E % rows) continue;
+      const int64_t ns = ceil_div(T.npad, E);
+      if ((double)ns * T.npad * 8.0 > 2.2e9 && E != 16384) continue;
+      const int64_t items = ns * (ns + 1) / 2;
+      const double cost = (double)std::max<int64_t>(ceil_div(items, cus), 2) * (double)E * (double)E;
+      if (cost < bestc * (1 - 1e-9)) { bestc = cost; bestE = E; }
+    }
+    const int64_t ns = ceil_div(T.npad, bestE);
+    const int64_t items = ns * (ns + 1) / 2;
+    split = ns;
+    src_len = bestE;
+    g = KmvGrid{dim3((unsigned)(8 * ceil_div(items, 8))), src_len, nsrc, T.npad, RpK, RoutK};
+    g.E = (int)bestE;
+    g.NS = (int)ns;
+  }
   const size_t need = (size_t)split * T.npad * RoutK;
   if (part.n < need) part.alloc(need, s);
-  KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[0], s));
   const bool ok = run(g);
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[1], s));

@@ -11,6 +11,8 @@ struct KmvGrid {
   int Rp, Rout;
   // When set, the launcher writes the kernel's resident blocks per CU here instead of launching.
   int* occ = nullptr;
+  // symmetric form: super-tile edge and super-tiles per side (grid.x = 8 * ceil(NS (NS + 1) / 16))
+  int E = 0, NS = 0;
 };
 
 // FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),
@@ -26,6 +28,9 @@ bool launch_kmv_mixed(int NCH, int NF, int DV, int form, const KmvGrid& g, const
                       const uint16_t* B, const float* v, int col, double* part, hipStream_t s);
 int mixed_max_nf(int nch);
 bool mixed_has_pp(int nch);
+// Symmetric square product K(X, X) v, one column (NCH <= 4, NF in {4, 8}; NCH > 2: NF 4 only).
+bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+                          const float* v, double* part, hipStream_t s);
 // Block MVM (many right-hand sides): NCH in {1,2,3,4}, (NT, NRC) with NT * NRC <= 8, NS in {3, 6}.
 // k32: the K.V contraction on v_mfma_f32_16x16x32_bf16 (32 sources per step) instead of 16x16x16.
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,

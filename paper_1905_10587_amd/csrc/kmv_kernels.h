@@ -4,6 +4,8 @@
 
 #include "kmv.h"
 
+#include <type_traits>
+
 namespace krr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -666,6 +668,212 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__
         if (DV == 2) prow[Rp + out_col] = acc[f][e][1];
       }
   }
+}
+
+// Symmetric form for the square product u = K(X, X) v (one column), using K_ij = K_ji.  The index range is
+// cut into super-tiles of E points; block b owns one pair (r, c), r <= c, of the upper triangle and
+// evaluates the E x E tile once:
+//   row sums  sum_{j in c} K_ij v_j  for i in r  -> part[c][i],
+//   col sums  sum_{i in r} K_ij v_i  for j in c  -> part[r][j]   (off-diagonal pairs only).
+// Every slot part[s][i] (s < NS) receives exactly one contribution, so the FP64 finishing pass sums NS
+// partials per row in a fixed order.  Inside a block the pipelined LDS-staged tile loop of
+// k_kmv_mixed_lds runs once per target tile of 64 NF points; each lane's column partial for one step (its
+// source, over its 4 NF targets: FP32 over NF x 4 products) goes to LDS, and at the end of each source
+// tile the 16 partials of a source (4 waves x 4 lane groups) are added in FP64 in a fixed order.
+// Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle.
+template <int NCH, int NF>
+__global__ __launch_bounds__(256) void k_kmv_mixed_sym(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                       const float* __restrict__ v, int Rp, int E, int NS,
+                                                       int64_t npad, double* __restrict__ part, int Rout) {
+  static_assert(NF >= 2, "the pipeline needs two fragments per step");
+  constexpr int KV = NCH * 4;
+  constexpr int RS = KV + 1;
+  constexpr int TS = NCH <= 2 ? 128 : 64;    // sources per LDS tile
+  constexpr int SPT = TS / 16;
+  constexpr int TPF = 256 / TS;              // tiles per FP64 fold of the row sums (every 256 sources)
+  constexpr int NI = (TS * RS + 63) / 64;
+  constexpr int SBU = NI * 64 + 16 * RS;
+  constexpr int TM = 64 * NF;                // targets per target tile (4 waves x 16 NF)
+  constexpr int VPER = 8 / NCH;
+  __shared__ uint4 sb0[SBU], sb1[SBU];
+  __shared__ float sv0[TS + 16], sv1[TS + 16];
+  __shared__ float cb0[16][TS], cb1[16][TS];   // column partials per (wave, lane group) and source
+
+  // triangle item of this block (XCD-contiguous order), row-major over r with c = r .. NS-1
+  const int64_t nitems = (int64_t)NS * (NS + 1) / 2;
+  const int64_t per = (nitems + 7) / 8;
+  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= nitems) return;
+  int r = (int)((2.0 * NS + 1 - sqrt((2.0 * NS + 1) * (2.0 * NS + 1) - 8.0 * (double)item)) / 2);
+  if (r < 0) r = 0;
+  if (r > NS - 1) r = NS - 1;
+  auto row_start = [&](int64_t rr) { return rr * NS - rr * (rr - 1) / 2; };
+  while (r > 0 && row_start(r) > item) --r;
+  while (r + 1 < NS && row_start(r + 1) <= item) ++r;
+  const int c = r + (int)(item - row_start(r));
+  const bool diag = r == c;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t t0 = (int64_t)r * E, t1 = t0 + E < npad ? t0 + E : npad;
+  const int64_t s0 = (int64_t)c * E, s1 = s0 + E < npad ? s0 + E : npad;
+  const int ntile = (int)((s1 - s0) / TS);
+  constexpr float kZero = 0.0f;
+
+  bf16x8 a[NF][NCH];
+  float vt[NF][4];
+  double acc[NF][4];
+  float a32[NF][4];
+
+  auto issue = [&](uint4* dst, int64_t j0) {
+    for (int i = wave; i < NI; i += 4) {
+      const int slot = i * 64 + lane;
+      int rr = slot / RS, u = slot - rr * RS;
+      if (u == KV) u = 0;
+      if (rr >= TS) { rr = 0; u = 0; }
+      __builtin_amdgcn_global_load_lds(B + (j0 + rr) * KV + u, dst + i * 64, 16, 0, 0);
+    }
+  };
+  auto vload = [&](int64_t j0) -> float { return tid < TS ? v[(j0 + tid) * Rp] : kZero; };
+
+  // one LDS tile: row sums into a32; with COL, per-step column partials into cb[wave][step * 16 + r16]
+  auto compute = [&](const uint4* sb, const float* sv, float (*cb)[TS], auto colflag) {
+    constexpr bool COL = decltype(colflag)::value;
+    bf16x8 b[NCH], bn[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) b[ch] = __builtin_bit_cast(bf16x8, sb[r16 * RS + ch * 4 + kq]);
+    float vj = sv[r16];
+    f32x4 q0 = f32x4{0.f, 0.f, 0.f, 0.f}, q1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ch], b[ch], q0, 0, 0, 0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][ch], b[ch], q1, 0, 0, 0);
+#pragma unroll 1
+    for (int st = 0; st < SPT; ++st) {
+      const int rn = (st + 1) * 16 + r16;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, sb[rn * RS + ch * 4 + kq]);
+      const float vn = sv[rn];
+      float cs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        f32x4 q2 = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (f + 2 < NF) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 < NF ? f + 2 : 0][ch], b[ch], q2, 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 - NF >= 0 ? f + 2 - NF : 0][ch], bn[ch], q2, 0,
+                                                         0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float ex = __builtin_amdgcn_exp2f(q0[e]);
+          a32[f][e] = __builtin_fmaf(ex, vj, a32[f][e]);
+          if (COL) cs[e] = __builtin_fmaf(ex, vt[f][e], cs[e]);
+        }
+        q0 = q1;
+        q1 = q2;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, COL ? VPER + 4 / NCH : VPER, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (COL) cb[wave * 4 + kq][st * 16 + r16] = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) b[ch] = bn[ch];
+      vj = vn;
+    }
+  };
+
+  // (target tile, source tile) pairs in one sequence, so the first source tile of the next target tile is
+  // staged while the last one of the current target tile is evaluated
+  auto run = [&](auto colflag) {
+    constexpr bool COL = decltype(colflag)::value;
+    const int ntt = (int)((t1 - t0) / TM);
+    const int total = ntt * ntile;
+    issue(sb0, s0);
+    {
+      const float v0 = vload(s0);
+      if (tid < TS) sv0[tid] = v0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int64_t row0 = 0;
+    for (int k = 0; k < total; ++k) {
+      const int tt = k / ntile;
+      const int t = k - tt * ntile;
+      const bool odd = k & 1;
+      const bool more = k + 1 < total;
+      const int tn = t + 1 == ntile ? 0 : t + 1;
+      if (t == 0) {
+        row0 = t0 + (int64_t)tt * TM + (int64_t)wave * 16 * NF;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            a[f][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * f + r16) * KV + ch * 4 + kq]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (COL) vt[f][e] = v[(row0 + 16 * f + kq * 4 + e) * Rp];
+            acc[f][e] = 0.0;
+            a32[f][e] = 0.0f;
+          }
+        }
+      }
+      float vr = 0.0f;
+      if (more) {
+        issue(odd ? sb0 : sb1, s0 + (int64_t)tn * TS);
+        vr = vload(s0 + (int64_t)tn * TS);
+      }
+      // column partial of the earlier target tiles for this source tile, fetched under the tile's work
+      double* dst = part + ((int64_t)r * npad + s0 + (int64_t)t * TS + (tid < TS ? tid : 0)) * Rout;
+      double prev = 0.0;
+      if (COL && tid < TS && tt > 0) prev = *dst;
+      compute(odd ? sb1 : sb0, odd ? sv1 : sv0, odd ? cb1 : cb0, colflag);
+      if (t % TPF == TPF - 1 || t == ntile - 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[f][e] += (double)a32[f][e];
+            a32[f][e] = 0.0f;
+          }
+      }
+      if (more && tid < TS) (odd ? sv0 : sv1)[tid] = vr;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (COL && tid < TS) {
+        float (*cb)[TS] = odd ? cb1 : cb0;
+        double cs = 0.0;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) cs += (double)cb[g][tid];
+        *dst = prev + cs;
+      }
+      if (t == ntile - 1) {   // row sums of this target tile -> part[c][rows]
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            double x = acc[f][e];
+            x += __shfl_xor(x, 8);
+            x += __shfl_xor(x, 4);
+            x += __shfl_xor(x, 2);
+            x += __shfl_xor(x, 1);
+            if (r16 == 0) part[((int64_t)c * npad + row0 + 16 * f + kq * 4 + e) * Rout] = x;
+          }
+      }
+    }
+  };
+  if (diag) run(std::false_type{});
+  else run(std::true_type{});
 }
 
 }  // namespace krr

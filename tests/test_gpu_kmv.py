@@ -177,3 +177,39 @@ def test_mixed_single_column_variants(gpu_lib, case):
     for plain, piped, staged in ((1, 4, 7), (2, 5, 8), (3, 6, 9)):
         assert np.array_equal(outs[plain], outs[piped]), (plain, piped)
         assert np.array_equal(outs[plain], outs[staged]), (plain, staged)
+
+
+SYM_CASES = [
+    # (n, d): square products K(X, X) v; n spans several 1024-point super-tiles with a ragged tail
+    (2500, 3),
+    (3100, 8),
+    (2049, 13),
+    (4100, 20),
+    (700, 4),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", SYM_CASES, ids=[f"n{c[0]}_d{c[1]}" for c in SYM_CASES])
+def test_mixed_symmetric_square_product(gpu_lib, case):
+    """The symmetric form (each off-diagonal super-tile evaluated once, feeding row and column sums) against
+    the oracle, with and without the ridge shift, for both of its variants."""
+    n, d = case
+    rng = np.random.default_rng(n + 31 * d)
+    X = rng.random((n, d))
+    v = rng.standard_normal(n)
+    eps = 0.05 * d
+    beta = 1e-3
+    K = ok.kernel_matrix(X, X, eps)
+    ref, scale = K @ v, K @ np.abs(v)
+    for variant in (10, 11):
+        gpu_lib.set_variant(d, 1, "mixed", variant)
+        U = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), prec="mixed").cpu().numpy()
+        err = _scaled_err(U, ref, scale)
+        Us = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), shift=beta,
+                               prec="mixed").cpu().numpy()
+        err_s = _scaled_err(Us, ref + beta * v, scale + beta * np.abs(v))
+        print(f"symmetric n={n} d={d} variant={variant}: max scaled error {err:.2e} (with shift {err_s:.2e})",
+              flush=True)
+        assert err <= TOL["mixed"] and err_s <= TOL["mixed"]
+    gpu_lib.set_variant(d, 1, "mixed", -1)
