@@ -31,9 +31,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "PCG solve s to rel-res 1e-6 + kernel-MVM Gpairs/s; mixed vs FP64, same GPU"
-# VALU bound of the kernel MVM on MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s;
-# one pair needs one v_exp_f32 (half rate: 2 slots) and one FMA (1 slot) -> 13.1e12 pairs/s.
-PEAK_PAIRS = 256 * 4 * 16 * 2.4e9 / 3.0
+# VALU bound of the kernel MVM on MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s.
+# Direct form: one pair needs one v_exp_f32 (half rate: 2 slots) and one FMA (1 slot) -> 13.1e12 pairs/s.
+# Symmetric form (square products): one exp and two FMAs (row and column sums) serve two pairs of the
+# product -> 2 slots per pair -> 19.7e12 pairs/s.  Pairs are the product's n^2 (the algorithmic units).
+SLOTS = 256 * 4 * 16 * 2.4e9
+PEAK_PAIRS = SLOTS / 3.0
+PEAK_PAIRS_SYM = SLOTS / 2.0
+# Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
+# for roofline.traffic only while these hash to the value recorded with it.
+KERNEL_SOURCES = ("paper_1905_10587_amd/csrc/kmv_kernels.h", "paper_1905_10587_amd/csrc/kmv_mixed.hip",
+                  "paper_1905_10587_amd/csrc/kmv.hip", "paper_1905_10587_amd/csrc/kmv.h",
+                  "paper_1905_10587_amd/csrc/kmv_dispatch.h")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload):
+    """HBM bytes per launch of the mixed MVM kernel from the committed counter summary, or None when the
+    summary is missing, is for another workload, or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec
 
 
 def log(*a):
@@ -177,6 +209,9 @@ def main(argv=None):
     # roofline: the main MVM kernel alone (HIP events around its launch, on the solver's stream)
     avg_mvm_ms = st["t_mvm_kernel_ms"] / max(st["n_mvm"], 1)
     achieved = float(n) * n / (avg_mvm_ms * 1e-3)
+    variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec == "mixed" else (None, False)
+    peak = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
+    traffic = stored_traffic(wl.name) if prec == "mixed" and R == 1 else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -207,9 +242,13 @@ def main(argv=None):
         "t_precond_s": round(st["t_precond_ms"] / 1e3, 3),
         "kappa_est": round(st["kappa_est"], 1),
         "mvm_gpairs_s": round(achieved / 1e9, 1),
-        "roofline": {"bound": "alu", "kernel": f"{prec} MVM kernel (exp2 + FMA per pair, d={wl.d})",
-                     "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_PAIRS / 1e12, 2),
-                     "unit": "Tpairs/s", "frac": round(achieved / PEAK_PAIRS, 3), "traffic": None,
+        "roofline": {"bound": "alu",
+                     "kernel": (f"{prec} MVM, variant {variant}, " if variant is not None else f"{prec} MVM, ")
+                               + ("symmetric form (exp + 2 FMA per evaluated pair)" if sym
+                                  else "direct form (exp + FMA per pair)") + f", d={wl.d}",
+                     "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
+                     "unit": "Tpairs/s", "frac": round(achieved / peak, 3),
+                     "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
                      "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]},
     }
     # kernel rates of the other precisions on the same GPU (one timed MVM each, same size)

@@ -227,6 +227,15 @@ int krr_autotune_load(const char* path);
 /* Force a variant for (d, R, prec) (-1 clears the entry).  Number of variants: krr_num_variants. */
 int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t variant);
 int krr_num_variants(int32_t prec, int32_t R);
+/*
+ * The kernel variant a product would run (the forced or tuned entry, else the default) and whether
+ * that variant is the symmetric form (square product K(X, X) V of one column without the derivative
+ * kernel, mixed precision, d <= 20: each off-diagonal pair of point tiles is evaluated once).
+ *   square != 0: targets and sources are the same point set.  variant, symmetric [host] out.
+ * Host only; no GPU call.  KRR_EINVAL on bad arguments.
+ */
+int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int32_t* variant,
+                    int32_t* symmetric);
 
 #ifdef __cplusplus
 }

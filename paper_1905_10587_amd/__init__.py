@@ -82,6 +82,7 @@ _SIGS = {
     "krr_autotune_load": ([ctypes.c_char_p], _i32),
     "krr_set_variant": ([_i32, _i32, _i32, _i32], _i32),
     "krr_num_variants": ([_i32, _i32], _i32),
+    "krr_kmv_variant": ([_i32, _i32, _i32, _i32, _i32, _vp, _vp], _i32),
 }
 
 
@@ -366,3 +367,11 @@ def set_variant(d: int, R: int, prec, variant: int):
 def num_variants(prec, R: int = 1) -> int:
     lib = load()
     return lib.krr_num_variants(_prec(prec), R)
+
+
+def kmv_variant(d: int, R: int = 1, prec="mixed", *, deriv: int = 0, square: bool = True):
+    """(variant, symmetric): the kernel variant a product would run and whether it is the symmetric form."""
+    lib = load()
+    v, sym = ctypes.c_int32(), ctypes.c_int32()
+    _chk(lib, lib.krr_kmv_variant(d, R, deriv, _prec(prec), 1 if square else 0, ctypes.byref(v), ctypes.byref(sym)))
+    return v.value, bool(sym.value)

@@ -33,6 +33,22 @@ extern "C" int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t varia
 
 extern "C" int krr_num_variants(int32_t prec, int32_t R) { return krr::kmv_num_variants(prec, R); }
 
+extern "C" int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int32_t* variant,
+                               int32_t* symmetric) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(d >= 1 && d <= KRR_MAX_D, "d must be in [1, KRR_MAX_D]");
+    KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
+    KRR_REQUIRE(deriv >= 0 && deriv <= 2, "deriv must be 0, 1 or 2");
+    KRR_REQUIRE(prec >= KRR_FP64 && prec <= KRR_MIXED, "unknown precision");
+    KRR_REQUIRE(variant && symmetric, "null output pointer");
+    int v = krr::kmv_get_override(d, R, prec);
+    if (v < 0) v = krr::kmv_default_variant(prec, d, R, 0, 0, square != 0 && deriv == 0);
+    *variant = v;
+    *symmetric = krr::kmv_is_symmetric(prec, d, R, deriv, square != 0, v) ? 1 : 0;
+    return (int)KRR_OK;
+  });
+}
+
 extern "C" int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32_t* best_variant, void* stream) {
   using namespace krr;
   return guarded([&] {

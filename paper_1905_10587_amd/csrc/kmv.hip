@@ -323,6 +323,10 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
   return m >= 65536 ? 1 : 0;
 }
 
+bool kmv_is_symmetric(int prec, int d, int R, int deriv, bool square, int v) {
+  return prec == KRR_MIXED && R == 1 && deriv == 0 && square && v >= 10 && mixed_chunks(d) <= 4;
+}
+
 void kmv_set_override(int d, int R, int prec, int variant) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (variant < 0) g_override.erase(vkey(d, R, prec));
@@ -443,7 +447,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     int var = variant;
     if (var >= 10) {
       // the symmetric form needs the square product of one column without the derivative kernel
-      sym = &T == &S && DV == 0 && R == 1 && nch <= 4;
+      sym = kmv_is_symmetric(prec, T.d, R, deriv, &T == &S, var);
       if (!sym) var -= 2;
     }
     if (sym) {

@@ -680,7 +680,8 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__
 // k_kmv_mixed_lds runs once per target tile of 64 NF points; each lane's column partial for one step (its
 // source, over its 4 NF targets: FP32 over NF x 4 products) goes to LDS, and at the end of each source
 // tile the 16 partials of a source (4 waves x 4 lane groups) are added in FP64 in a fixed order.
-// Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle.
+// Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle in
+// column order.
 template <int NCH, int NF>
 __global__ __launch_bounds__(256) void k_kmv_mixed_sym(const uint4* __restrict__ A, const uint4* __restrict__ B,
                                                        const float* __restrict__ v, int Rp, int E, int NS,
@@ -699,18 +700,19 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_sym(const uint4* __restrict__
   __shared__ float sv0[TS + 16], sv1[TS + 16];
   __shared__ float cb0[16][TS], cb1[16][TS];   // column partials per (wave, lane group) and source
 
-  // triangle item of this block (XCD-contiguous order), row-major over r with c = r .. NS-1
+  // triangle item of this block (XCD-contiguous order), column-major: column c holds r = 0 .. c, so the
+  // blocks that run together on one XCD mostly share their source super-tile (L2 reuse)
   const int64_t nitems = (int64_t)NS * (NS + 1) / 2;
   const int64_t per = (nitems + 7) / 8;
   const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (item >= nitems) return;
-  int r = (int)((2.0 * NS + 1 - sqrt((2.0 * NS + 1) * (2.0 * NS + 1) - 8.0 * (double)item)) / 2);
-  if (r < 0) r = 0;
-  if (r > NS - 1) r = NS - 1;
-  auto row_start = [&](int64_t rr) { return rr * NS - rr * (rr - 1) / 2; };
-  while (r > 0 && row_start(r) > item) --r;
-  while (r + 1 < NS && row_start(r + 1) <= item) ++r;
-  const int c = r + (int)(item - row_start(r));
+  int c = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) / 2);
+  if (c < 0) c = 0;
+  if (c > NS - 1) c = NS - 1;
+  auto col_start = [&](int64_t cc) { return cc * (cc + 1) / 2; };
+  while (c > 0 && col_start(c) > item) --c;
+  while (c + 1 < NS && col_start(c + 1) <= item) ++c;
+  const int r = (int)(item - col_start(c));
   const bool diag = r == c;
 
   const int tid = threadIdx.x;

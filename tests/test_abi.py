@@ -69,3 +69,29 @@ def test_variant_table_roundtrip(lib, tmp_path):
     assert a.read_text() == b.read_text()
     assert '"2:4:1": 3' in a.read_text()
     assert L.krr_set_variant(4, 1, 2, 99) == -1          # out of range
+
+
+def test_kmv_variant_introspection(lib):
+    """krr_kmv_variant (host only): defaults per shape, the symmetric form only for square one-column mixed
+    products without the derivative kernel and d <= 20, forced entries win, bad arguments are rejected."""
+    import paper_1905_10587_amd as krr
+    L = krr.load()
+    for d in (3, 4, 8, 13, 20, 30):   # clear entries earlier tests may have forced
+        L.krr_set_variant(d, 1, 2, -1)
+    assert krr.kmv_variant(8, 1, "mixed", square=True) == (10, True)
+    assert krr.kmv_variant(4, 1, "mixed", square=True) == (10, True)
+    assert krr.kmv_variant(8, 1, "mixed", square=False) == (9, False)
+    assert krr.kmv_variant(4, 1, "mixed", square=False) == (3, False)
+    assert krr.kmv_variant(8, 1, "mixed", deriv=2, square=True) == (9, False)
+    assert krr.kmv_variant(30, 1, "mixed", square=True)[1] is False
+    assert krr.kmv_variant(8, 1, "fp64", square=True)[1] is False
+    krr.set_variant(8, 1, "mixed", 3)
+    assert krr.kmv_variant(8, 1, "mixed", square=True) == (3, False)
+    krr.set_variant(8, 1, "mixed", 11)
+    assert krr.kmv_variant(8, 1, "mixed", square=True) == (11, True)
+    assert krr.kmv_variant(8, 1, "mixed", square=False) == (11, False)
+    krr.set_variant(8, 1, "mixed", -1)
+    v, s = ctypes.c_int32(), ctypes.c_int32()
+    assert L.krr_kmv_variant(0, 1, 0, 2, 1, ctypes.byref(v), ctypes.byref(s)) == -1
+    assert L.krr_kmv_variant(8, 1, 3, 2, 1, ctypes.byref(v), ctypes.byref(s)) == -1
+    assert L.krr_kmv_variant(8, 1, 0, 2, 1, None, ctypes.byref(s)) == -1
