@@ -299,8 +299,10 @@ const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 int kmv_num_variants(int prec, int R) {
   if (rclass(prec, R) == 3) return 12;
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
-  // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9)
-  return prec == KRR_MIXED ? 12 : 3;
+  // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
+  // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2)
+  if (prec == KRR_MIXED) return 12;
+  return prec == KRR_FP64 && rclass(prec, R) == 1 ? 5 : 3;
 }
 
 bool kmv_uses_block(int prec, int d, int R, int deriv) {
@@ -313,18 +315,22 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
     const int nch = mixed_chunks(d);
-    if (square && R == 1 && nch <= 4) return 10;   // symmetric square product
+    if (kmv_is_symmetric(prec, d, R, 0, square, 10)) return 10;   // symmetric square product
     if (nch == 1) return 3;
     if (nch == 2) return 9;
     if (nch <= 4) return 8;
     return mixed_max_nf(nch) >= 2 ? 1 : 0;
   }
+  if (kmv_is_symmetric(prec, d, R, 0, square, 4)) return 4;   // FP64 symmetric square product, TM 4
   if (padded_dim(d) >= 32) return 0;
   return m >= 65536 ? 1 : 0;
 }
 
 bool kmv_is_symmetric(int prec, int d, int R, int deriv, bool square, int v) {
-  return prec == KRR_MIXED && R == 1 && deriv == 0 && square && v >= 10 && mixed_chunks(d) <= 4;
+  if (R != 1 || deriv != 0 || !square) return false;
+  if (prec == KRR_MIXED) return v >= 10 && mixed_chunks(d) <= 4;
+  if (prec == KRR_FP64) return v >= 3 && kmv_f64_has_sym(padded_dim(d));
+  return false;
 }
 
 void kmv_set_override(int d, int R, int prec, int variant) {
@@ -460,7 +466,12 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     rows = 64 * NF;
     gz = 1;
   } else {
-    TM = D >= 32 ? 1 : kTM[variant];
+    int var = variant;
+    if (prec == KRR_FP64 && var >= 3) {
+      sym = kmv_is_symmetric(prec, T.d, R, deriv, &T == &S, var);
+      if (!sym) var -= 2;
+    }
+    TM = sym ? (var == 3 ? 2 : 4) : D >= 32 ? 1 : kTM[var];
     rows = 256 * TM;
     gz = (int)ceil_div(R, RC);   // real columns only (Rp is padded to 8)
   }
@@ -475,6 +486,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     if (block)
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
+    if (prec == KRR_FP64 && sym) return launch_kmv_f64_sym(D, TM, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP32) return launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
     if (sym) return launch_kmv_mixed_sym(T.ka / 32, NF, g, T.sa.p, S.sb.p, V.v32.p, part.p, s);

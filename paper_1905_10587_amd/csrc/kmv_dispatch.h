@@ -19,6 +19,10 @@ struct KmvGrid {
 // RC in {1,4,8}, DV in {0,2}.  Return false if the combination is not instantiated.
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
                     const double* v, double neg_c, double* part, hipStream_t s);
+// Symmetric FP64 square product of one column (D in {2, 4, 6, 8, 16}, TM in {2, 4}).
+bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const double* v, double neg_c,
+                        double* part, hipStream_t s);
+bool kmv_f64_has_sym(int D);
 bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,
                     const float* v, double* part, hipStream_t s);
 // MFMA kernel (one column per launch): NCH in {1,2,3,4,6,8,13,25}, NF in {1,2,4,8} (limited by NCH),

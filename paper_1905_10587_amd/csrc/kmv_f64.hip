@@ -25,6 +25,30 @@ static void go64(const KmvGrid& g, const double* xt, const double* xs, const dou
 #define KRR_TM1(D) \
   if (TM == 1) { KRR_RC(D, 1) }
 
+template <int D, int TM>
+static void go64s(const KmvGrid& g, const double* x, const double* v, double neg_c, double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_sym<D, TM>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_f64_sym<D, TM>), g.grid, dim3(256), 0, s, x, v, g.Rp, neg_c, g.E, g.NS, g.mpad, part,
+                     g.Rout);
+}
+
+bool kmv_f64_has_sym(int D) { return D == 2 || D == 4 || D == 6 || D == 8 || D == 16; }
+
+bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const double* v, double neg_c,
+                        double* part, hipStream_t s) {
+#define KRR_S64(DD)                                                   \
+  if (D == DD) {                                                      \
+    if (TM == 2) { go64s<DD, 2>(g, x, v, neg_c, part, s); return true; } \
+    if (TM == 4) { go64s<DD, 4>(g, x, v, neg_c, part, s); return true; } \
+  }
+  KRR_S64(2) KRR_S64(4) KRR_S64(6) KRR_S64(8) KRR_S64(16)
+#undef KRR_S64
+  return false;
+}
+
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
                     const double* v, double neg_c, double* part, hipStream_t s) {
   switch (D) {

@@ -119,6 +119,113 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
   }
 }
 
+// Symmetric FP64 form for the square product u = K(X, X) v (one column), D even and <= 16.  Super-tiles
+// and partial slots as in k_kmv_mixed_sym: block b owns one pair (r, c <= ...) of the upper triangle,
+// evaluates the E x E tile once and writes its row sums to part[c][rows of r] and, off the diagonal, its
+// column sums to part[r][rows of c].  Each thread owns TM targets (strided by 256 in a target tile).
+// Sources stream through LDS in tiles of 256; a wave walks each 64-source sub-tile in rotated order
+// (lane l takes source (l + k) mod 64 at step k), so at every step the 64 lanes touch 64 distinct
+// sources: a lane's column contribution (its TM targets) is added to that source's per-wave LDS slot
+// with an LDS atomic, and the four waves' slots are added in a fixed order at the end of the tile.
+// Rows are stored with an odd number of 16-byte units so the rotated reads are bank-conflict free.
+template <int D, int TM>
+__global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ X, const double* __restrict__ v,
+                                                     int Rp, double neg_c, int E, int NS, int64_t npad,
+                                                     double* __restrict__ part, int Rout) {
+  static_assert(D % 2 == 0 && D <= 16, "even dimensions up to 16");
+  constexpr int SD = 2 * ((D / 2) | 1);   // LDS row stride in doubles (odd number of 16-byte units)
+  constexpr int TS = 256;
+  constexpr int TT = 256 * TM;
+  __shared__ double xs[TS * SD];
+  __shared__ double vs[TS];
+  __shared__ double cacc[4][TS];
+
+  const int64_t nitems = (int64_t)NS * (NS + 1) / 2;
+  const int64_t per = (nitems + 7) / 8;
+  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= nitems) return;
+  int c = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) / 2);
+  if (c < 0) c = 0;
+  if (c > NS - 1) c = NS - 1;
+  auto col_start = [&](int64_t cc) { return cc * (cc + 1) / 2; };
+  while (c > 0 && col_start(c) > item) --c;
+  while (c + 1 < NS && col_start(c + 1) <= item) ++c;
+  const int r = (int)(item - col_start(c));
+  const bool diag = r == c;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t t0 = (int64_t)r * E, t1 = t0 + E < npad ? t0 + E : npad;
+  const int64_t s0 = (int64_t)c * E, s1 = s0 + E < npad ? s0 + E : npad;
+  const int ntile = (int)((s1 - s0) / TS);
+  const int ntt = (int)((t1 - t0) / TT);
+
+  auto run = [&](auto colflag) {
+    constexpr bool COL = decltype(colflag)::value;
+    for (int tt = 0; tt < ntt; ++tt) {
+      const int64_t ib = t0 + (int64_t)tt * TT + tid;
+      double xi[TM][D], vt[TM], acc[TM];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[m][k] = X[(ib + m * 256) * D + k];
+        vt[m] = COL ? v[(ib + m * 256) * Rp] : 0.0;
+        acc[m] = 0.0;
+      }
+      for (int t = 0; t < ntile; ++t) {
+        const int64_t jt = s0 + (int64_t)t * TS;
+        double* dst = part + ((int64_t)r * npad + jt + tid) * Rout;
+        double prev = 0.0;
+        if (COL && tt > 0) prev = *dst;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < D; ++k) xs[tid * SD + k] = X[(jt + tid) * D + k];
+        vs[tid] = v[(jt + tid) * Rp];
+        if (COL) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cacc[wave][lane + 64 * u] = 0.0;
+        }
+        __syncthreads();
+        for (int sub = 0; sub < 4; ++sub) {
+#pragma unroll 2
+          for (int k = 0; k < 64; ++k) {
+            const int j = sub * 64 + ((lane + k) & 63);
+            double xj[D];
+#pragma unroll
+            for (int u = 0; u < D; u += 2) {
+              const double2 w = *reinterpret_cast<const double2*>(&xs[j * SD + u]);
+              xj[u] = w.x;
+              xj[u + 1] = w.y;
+            }
+            const double vj = vs[j];
+            double cs = 0.0;
+#pragma unroll
+            for (int m = 0; m < TM; ++m) {
+              double d2 = 0.0;
+#pragma unroll
+              for (int u = 0; u < D; ++u) {
+                const double df = xi[m][u] - xj[u];
+                d2 = __builtin_fma(df, df, d2);
+              }
+              const double e = exp2_neg_f64(d2 * neg_c);
+              acc[m] = __builtin_fma(e, vj, acc[m]);
+              if (COL) cs = __builtin_fma(e, vt[m], cs);
+            }
+            if (COL) __hip_atomic_fetch_add(&cacc[wave][j], cs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+        __syncthreads();
+        if (COL) *dst = prev + (((cacc[0][tid] + cacc[1][tid]) + cacc[2][tid]) + cacc[3][tid]);
+      }
+#pragma unroll
+      for (int m = 0; m < TM; ++m) part[((int64_t)c * npad + ib + m * 256) * Rout] = acc[m];
+    }
+  };
+  if (diag) run(std::false_type{});
+  else run(std::true_type{});
+}
+
 // FP32 form: coordinates pre-scaled so that q = -||t'-s'||^2 is the exp2 argument.  Per pair: D subs,
 // D FMAs, one v_exp_f32, RC FMAs.  FP32 partial sums are folded into FP64 once per 256 sources.
 template <int D, int TM, int RC, int DV>

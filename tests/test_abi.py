@@ -84,7 +84,10 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(4, 1, "mixed", square=False) == (3, False)
     assert krr.kmv_variant(8, 1, "mixed", deriv=2, square=True) == (9, False)
     assert krr.kmv_variant(30, 1, "mixed", square=True)[1] is False
-    assert krr.kmv_variant(8, 1, "fp64", square=True)[1] is False
+    assert krr.kmv_variant(8, 1, "fp64", square=True) == (4, True)
+    assert krr.kmv_variant(8, 1, "fp64", square=False)[1] is False
+    assert krr.kmv_variant(3, 1, "fp64", square=True)[1] is False   # odd padded width: direct kernel
+    assert krr.kmv_variant(8, 1, "fp32", square=True)[1] is False
     krr.set_variant(8, 1, "mixed", 3)
     assert krr.kmv_variant(8, 1, "mixed", square=True) == (3, False)
     krr.set_variant(8, 1, "mixed", 11)

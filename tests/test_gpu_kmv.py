@@ -186,14 +186,21 @@ SYM_CASES = [
     (2049, 13),
     (4100, 20),
     (700, 4),
+    (3000, 6),
+    (2600, 16),
 ]
 
 
+SYM_VARIANTS = {"mixed": (10, 11), "fp64": (3, 4)}
+
+
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("case", SYM_CASES, ids=[f"n{c[0]}_d{c[1]}" for c in SYM_CASES])
-def test_mixed_symmetric_square_product(gpu_lib, case):
+def test_symmetric_square_product(gpu_lib, case, prec):
     """The symmetric form (each off-diagonal super-tile evaluated once, feeding row and column sums) against
-    the oracle, with and without the ridge shift, for both of its variants."""
+    the oracle, with and without the ridge shift, for both of its variants (shapes without a symmetric
+    form run the direct kernel: FP64 at odd padded widths, mixed above 20 dimensions)."""
     n, d = case
     rng = np.random.default_rng(n + 31 * d)
     X = rng.random((n, d))
@@ -202,14 +209,15 @@ def test_mixed_symmetric_square_product(gpu_lib, case):
     beta = 1e-3
     K = ok.kernel_matrix(X, X, eps)
     ref, scale = K @ v, K @ np.abs(v)
-    for variant in (10, 11):
-        gpu_lib.set_variant(d, 1, "mixed", variant)
-        U = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), prec="mixed").cpu().numpy()
+    for variant in SYM_VARIANTS[prec]:
+        gpu_lib.set_variant(d, 1, prec, variant)
+        U = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), prec=prec).cpu().numpy()
         err = _scaled_err(U, ref, scale)
         Us = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), shift=beta,
-                               prec="mixed").cpu().numpy()
+                               prec=prec).cpu().numpy()
         err_s = _scaled_err(Us, ref + beta * v, scale + beta * np.abs(v))
-        print(f"symmetric n={n} d={d} variant={variant}: max scaled error {err:.2e} (with shift {err_s:.2e})",
-              flush=True)
-        assert err <= TOL["mixed"] and err_s <= TOL["mixed"]
-    gpu_lib.set_variant(d, 1, "mixed", -1)
+        form = gpu_lib.kmv_variant(d, 1, prec, square=True)
+        print(f"symmetric {prec} n={n} d={d} variant={variant} {form}: max scaled error {err:.2e} "
+              f"(with shift {err_s:.2e})", flush=True)
+        assert err <= TOL[prec] and err_s <= TOL[prec]
+    gpu_lib.set_variant(d, 1, prec, -1)
