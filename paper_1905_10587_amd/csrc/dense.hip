@@ -121,6 +121,200 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ A, do
   }
 }
 
+// Block form of the same tournament: the k columns are cut into blocks of W, and round r pairs the blocks
+// (P, Q) by the circle method.  A workgroup copies the 2W columns S of its pair into LDS, forms their Gram
+// matrix G = S^T S afresh, and runs `inner` sweeps of two-sided Jacobi rotations on G (rounds of W
+// disjoint rotations, G <- R^T G R in a column phase and a row phase, the rotated 2x2 block set by the
+// stable formulas G_pp - t G_pq, G_qq + t G_pq and 0), accumulating J = prod R.  It then writes S J back to A and V J to V.  The rotation of a pair (p, q) is the one the
+// scalar algorithm would take from the same a = G_pp, b = G_qq, g = G_pq.  The convergence measure is
+// taken from the fresh Gram (every pair of the 2W columns), so the outer loop stops on columns that are
+// orthogonal as stored.  Columns >= k (partial last block, bye block) are zero and never rotate.
+template <int W>
+__global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A, double* __restrict__ V, int k,
+                                                          int NB, int r, double rot_tol, int inner,
+                                                          unsigned long long* __restrict__ offmax) {
+  constexpr int C2 = 2 * W;
+  static_assert(C2 * C2 <= 256 && W * C2 <= 256, "one thread per Gram entry");
+  constexpr int NEB = (C2 / 4) * (C2 / 4);   // 4 x 4 blocks of the Gram matrix
+  constexpr int RGW = 64 / NEB;              // row groups per wave
+  extern __shared__ double sa[];   // C2 columns of length k, column stride ks (odd: conflict-free)
+  __shared__ double G[C2][C2 + 1];
+  __shared__ double gred[4][NEB][16];
+  __shared__ double J[C2][C2 + 1];
+  __shared__ double rc[W], rs[W], rt[W], rg[W], ra[W], rb[W];
+  __shared__ int rp[W], rq[W], ron[W];
+  __shared__ double offw[4];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x;
+  int P, Q;
+  if (i == 0) { P = r; Q = NB - 1; }
+  else { P = (r + i) % (NB - 1); Q = (r - i + NB - 1) % (NB - 1); }
+  if (P > Q) { const int t = P; P = Q; Q = t; }
+  // a pair with the bye block has nothing to rotate across, except in the first round of a sweep, where
+  // it is that block's only chance to rotate its own column pairs (the bye's columns read as zeros)
+  if ((int64_t)Q * W >= k && r != 0) return;
+  auto gcol = [&](int lc) { return lc < W ? P * W + lc : Q * W + (lc - W); };
+  const int ks = k | 1;
+  // a thread moves one row of the 2W columns at a time, so its 2W loads are in flight together
+  for (int t = tid; t < k; t += 256) {
+    double row[C2];
+#pragma unroll
+    for (int lc = 0; lc < C2; ++lc) {
+      const int g = gcol(lc);
+      row[lc] = g < k ? A[(int64_t)g * k + t] : 0.0;
+    }
+#pragma unroll
+    for (int lc = 0; lc < C2; ++lc) sa[lc * ks + t] = row[lc];
+  }
+  __syncthreads();
+  // fresh Gram G = S^T S: lane (row group, 4 x 4 block) accumulates its block over the rows of its group,
+  // the row groups of a wave are combined by butterflies, the four waves in a fixed order.  Block (bi, bj)
+  // and (bj, bi) use the same products in the same order, so G is exactly symmetric.
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int eb = lane % NEB, rgl = lane / NEB;
+    const int bi = eb / (C2 / 4), bj = eb % (C2 / 4);
+    const int rg = wave * RGW + rgl, nrg = 4 * RGW;
+    double acc[4][4];
+#pragma unroll
+    for (int e1 = 0; e1 < 4; ++e1)
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) acc[e1][e2] = 0.0;
+    for (int t = rg; t < k; t += nrg) {
+      double x[4], y[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        x[e] = sa[(4 * bi + e) * ks + t];
+        y[e] = sa[(4 * bj + e) * ks + t];
+      }
+#pragma unroll
+      for (int e1 = 0; e1 < 4; ++e1)
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) acc[e1][e2] = __builtin_fma(x[e1], y[e2], acc[e1][e2]);
+    }
+#pragma unroll
+    for (int e1 = 0; e1 < 4; ++e1)
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2)
+        for (int o = NEB; o < 64; o <<= 1) acc[e1][e2] += __shfl_xor(acc[e1][e2], o);
+    if (rgl == 0) {
+#pragma unroll
+      for (int e1 = 0; e1 < 4; ++e1)
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) gred[wave][eb][e1 * 4 + e2] = acc[e1][e2];
+    }
+  }
+  __syncthreads();
+  if (tid < C2 * C2) {
+    const int gi = tid / C2, gj = tid % C2;
+    const int eb = (gi / 4) * (C2 / 4) + gj / 4, e = (gi % 4) * 4 + gj % 4;
+    G[gi][gj] = ((gred[0][eb][e] + gred[1][eb][e]) + gred[2][eb][e]) + gred[3][eb][e];
+    J[gi][gj] = gi == gj ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double off_local = 0.0;
+  if (tid < C2 * C2) {
+    const int gi = tid / C2, gj = tid % C2;
+    if (gi < gj) {
+      const double den = sqrt(G[gi][gi] * G[gj][gj]);
+      off_local = den > 0 ? fabs(G[gi][gj]) / den : 0.0;
+    }
+  }
+  // The first round of an outer sweep meets every block once: it runs the full circle over the 2W columns
+  // (pairs inside P and inside Q included); later rounds run only the W x W cross pairs, in W rounds of W
+  // disjoint pairs (p, W + (p + ir) mod W), which every outer sweep meets exactly once.
+  const bool full = r == 0;
+  const int nround = full ? C2 - 1 : W;
+  for (int sw = 0; sw < inner; ++sw) {
+    for (int ir = 0; ir < nround; ++ir) {
+      if (tid < W) {   // rotation parameters of slot tid
+        int p, q;
+        if (!full) { p = tid; q = W + (tid + ir) % W; }
+        else if (tid == 0) { p = ir; q = C2 - 1; }
+        else { p = (ir + tid) % (C2 - 1); q = (ir - tid + C2 - 1) % (C2 - 1); }
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double a = G[p][p], b = G[q][q], g = G[p][q];
+        const double den = sqrt(a * b);
+        const double off = den > 0 ? fabs(g) / den : 0.0;
+        const int on = off > rot_tol;
+        double c = 1.0, sn = 0.0, tt = 0.0;
+        if (on) {
+          const double zeta = (b - a) / (2.0 * g);
+          tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          sn = c * tt;
+        }
+        rp[tid] = p; rq[tid] = q; ron[tid] = on;
+        rc[tid] = c; rs[tid] = sn; rt[tid] = tt; rg[tid] = g; ra[tid] = a; rb[tid] = b;
+      }
+      __syncthreads();
+      const int sl = tid / C2, e = tid % C2;   // W slots x C2 rows/columns
+      if (tid < W * C2 && ron[sl]) {         // column phase: G <- G R, J <- J R
+        const int p = rp[sl], q = rq[sl];
+        const double c = rc[sl], sn = rs[sl];
+        const double x = G[e][p], y = G[e][q];
+        G[e][p] = c * x - sn * y;
+        G[e][q] = sn * x + c * y;
+        const double u = J[e][p], w = J[e][q];
+        J[e][p] = c * u - sn * w;
+        J[e][q] = sn * u + c * w;
+      }
+      __syncthreads();
+      if (tid < W * C2 && ron[sl]) {         // row phase: G <- R^T G
+        const int p = rp[sl], q = rq[sl];
+        const double c = rc[sl], sn = rs[sl];
+        const double x = G[p][e], y = G[q][e];
+        G[p][e] = c * x - sn * y;
+        G[q][e] = sn * x + c * y;
+      }
+      __syncthreads();
+      if (tid < W && ron[tid]) {             // the rotated 2x2 block, stable formulas
+        const int p = rp[tid], q = rq[tid];
+        G[p][p] = ra[tid] - rt[tid] * rg[tid];
+        G[q][q] = rb[tid] + rt[tid] * rg[tid];
+        G[p][q] = 0.0;
+        G[q][p] = 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  // A <- S J, V <- V J on the 2W columns, one row per thread at a time
+  for (int t = tid; t < k; t += 256) {
+    double so[C2], vo[C2];
+#pragma unroll
+    for (int m = 0; m < C2; ++m) {
+      const int g = gcol(m);
+      so[m] = sa[m * ks + t];
+      vo[m] = g < k ? V[(int64_t)g * k + t] : 0.0;
+    }
+#pragma unroll 1
+    for (int lc = 0; lc < C2; ++lc) {   // J is read from LDS here (not hoisted into registers)
+      const int g = gcol(lc);
+      if (g >= k) continue;
+      double xa = 0.0, xv = 0.0;
+#pragma unroll
+      for (int m = 0; m < C2; ++m) {
+        xa = __builtin_fma(so[m], J[m][lc], xa);
+        xv = __builtin_fma(vo[m], J[m][lc], xv);
+      }
+      A[(int64_t)g * k + t] = xa;
+      V[(int64_t)g * k + t] = xv;
+    }
+  }
+  // block maximum of the off-diagonal measure -> one atomic
+  for (int o = 32; o > 0; o >>= 1) {
+    const double t = __shfl_xor(off_local, o);
+    off_local = t > off_local ? t : off_local;
+  }
+  if ((tid & 63) == 0) offw[tid >> 6] = off_local;
+  __syncthreads();
+  if (tid == 0) {
+    double m = offw[0];
+    for (int w = 1; w < 4; ++w) m = offw[w] > m ? offw[w] : m;
+    atomicMax(offmax, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 __global__ void k_identity(double* __restrict__ V, int k) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)k * k) return;
@@ -145,12 +339,36 @@ int jacobi_evd(double* A, double* V, double* lam, int k, hipStream_t s, int max_
     return 0;
   }
   const int K = k + (k & 1);
+  const int kInner = 1;   // sweeps over a block pair's Gram matrix per visit
+  // block form when a pair of column blocks fits in LDS (2W columns of k doubles <= 141 KB)
+  const int W = k >= 64 && k <= 1100 ? 8 : (k >= 64 && k <= 2200 ? 4 : 0);
+  const size_t lds = (size_t)2 * W * (k | 1) * sizeof(double);
+  int NB = 0;
+  if (W) {
+    NB = (int)ceil_div(k, W);
+    NB += NB & 1;
+    if (W == 8)
+      KRR_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_blockpair<8>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    else
+      KRR_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_blockpair<4>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
   DevBuf<unsigned long long> off(1, s);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     KRR_CHECK_HIP(hipMemsetAsync(off.p, 0, sizeof(unsigned long long), s));
-    for (int r = 0; r < K - 1; ++r) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(K / 2), dim3(256), 0, s, A, V, k, K, r, 1e-15, off.p);
+    if (W == 8) {
+      for (int r = 0; r < NB - 1; ++r)
+        hipLaunchKernelGGL(k_jacobi_blockpair<8>, dim3(NB / 2), dim3(256), lds, s, A, V, k, NB, r, 1e-15, kInner,
+                           off.p);
+    } else if (W == 4) {
+      for (int r = 0; r < NB - 1; ++r)
+        hipLaunchKernelGGL(k_jacobi_blockpair<4>, dim3(NB / 2), dim3(256), lds, s, A, V, k, NB, r, 1e-15, kInner,
+                           off.p);
+    } else {
+      for (int r = 0; r < K - 1; ++r)
+        hipLaunchKernelGGL(k_jacobi_round, dim3(K / 2), dim3(256), 0, s, A, V, k, K, r, 1e-15, off.p);
     }
     KRR_LAUNCH_CHECK();
     unsigned long long h = 0;
