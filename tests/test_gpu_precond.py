@@ -123,6 +123,31 @@ def test_build_anchors_and_factor(gpu_lib, small_build):
 
 
 @pytest.mark.gpu
+# k = 40: scalar Jacobi rounds; k = 700: blocks of 8 columns; k = 1500: blocks of 4 columns (the LDS
+# holds a pair of blocks); the partial last block and the bye block occur at 700 and 1500.  eps is set
+# so that K_SS stays well conditioned (no eigenvalue near the truncation threshold).
+@pytest.mark.parametrize("k,eps", [(40, 0.02), (700, 0.004), (1500, 0.003)])
+def test_anchor_evd_paths(gpu_lib, k, eps):
+    """The eigendecomposition of K_SS on every code path: eigenvalues and W W^T = C K_SS^+ C^T against the
+    oracle for the GPU's anchors."""
+    n, d = 3500, 3
+    X = _pts(n, d, 40 + k)
+    l = k + 20
+    idx, sign = datagen.sketch_sparse_draws(n, l, 8, seed=41 + k)
+    P = gpu_lib.Preconditioner(torch.from_numpy(X), eps, [1e-3], k, l, idx=torch.from_numpy(idx),
+                               sign=torch.from_numpy(sign), prec="fp64")
+    info = P.info()
+    S = np.array(info["S"])
+    nf = op.nystrom_factor(X, S, eps)
+    lam = np.array(info["lam"])
+    print(f"k={k}: {info['kept']} eigenvalues kept (oracle {nf['kept']}), sweeps {P.timings()['jacobi_sweeps']}")
+    np.testing.assert_allclose(lam, np.sort(nf["lam"]), rtol=1e-9, atol=1e-12 * lam.max())
+    assert info["kept"] == nf["kept"]
+    W = P.get(P.W64).cpu().numpy()
+    np.testing.assert_allclose(W @ W.T, nf["W"] @ nf["W"].T, rtol=0, atol=1e-9)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_woodbury_apply_parity(gpu_lib, small_build, prec):
     wl, om, P = small_build
