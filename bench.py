@@ -139,6 +139,7 @@ def main(argv=None):
                     help="profiling mode: a 1 GiB device copy (counter calibration), then the workload's "
                          "mixed and FP64 kernel MVMs; prints their HIP-event times")
     ap.add_argument("--reps", type=int, default=3, help="MVM launches per precision in --kernels-only")
+    ap.add_argument("--save-alpha", default=None, help="write the timed solve's alpha (.npy) after the run")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU row sharding of the "
@@ -174,11 +175,30 @@ def main(argv=None):
         sk = dict(omega=torch.from_numpy(datagen.sketch_dense_omega(wl.n, wl.l, datagen.sketch_seed(wl.name))).to(dev))
     torch.cuda.synchronize()
 
+    adjoint = wl.X_val is not None
+    if adjoint:
+        Xvg = torch.from_numpy(wl.X_val).to(dev)
+        yvg = torch.from_numpy(wl.y_val).to(dev)
+    grad_out = {}
+
     def step():
         t0 = time.perf_counter()
         P = krr.Preconditioner(Xg, wl.eps, list(wl.betas), wl.k, wl.l, prec=prec, **sk)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        if adjoint:
+            # the step of this workload is the validation-loss gradient: forward solve, adjoint solve and the
+            # FP64 products that assemble loss and gradient
+            loss, ge, gb, alpha, lam, sts = krr.grad(Xg, Yg, Xvg, yvg, wl.eps, wl.betas[0], P, tol=wl.tol,
+                                                     maxit=a.maxit, replace_every=replace_every, prec=prec,
+                                                     return_stats=True)
+            torch.cuda.synchronize()
+            grad_out.update(loss=loss, dloss_dlog_eps=ge, dloss_dlog_beta=gb, stats=sts)
+            st = {k: sts[0][k] + sts[1][k] for k in sts[0] if k not in ("kappa_est", "iters_max")}
+            st["kappa_est"] = sts[0]["kappa_est"]
+            st["iters_max"] = max(sts[0]["iters_max"], sts[1]["iters_max"])
+            its, rel, status = [sts[0]["iters_max"], sts[1]["iters_max"]], [0.0], 0
+            return P, alpha, its, rel, st, status, tb, time.perf_counter() - t0
         alpha, its, rel, st, status = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol, maxit=a.maxit,
                                                     replace_every=replace_every, prec=prec, timing=True)
         torch.cuda.synchronize()
@@ -201,9 +221,15 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     P, alpha, its, rel, st, status, t_build, t_step = results[-1]
+    if a.save_alpha:
+        import numpy as np
+        np.save(a.save_alpha, alpha.cpu().numpy())
     R = len(betas_col)
     n = wl.n
     pairs_step = (st["n_mvm"] + st["n_mvm_fp64"]) * float(n) * n
+    if adjoint:   # + fused (K, K') on validation x training, K^T r_v, K' alpha (FP64)
+        m = wl.X_val.shape[0]
+        pairs_step += 2.0 * m * n + float(n) * n
     ms_per_step = 1e3 * t_total / a.steps
     value = pairs_step / (t_total / a.steps) / 1e9
     # roofline: the main MVM kernel alone (HIP events around its launch, on the solver's stream)
@@ -233,7 +259,7 @@ def main(argv=None):
         "build_phases_ms": {k: round(v, 1) for k, v in P.timings().items()},
         "solve_s": round(t_step - t_build, 3),
         "iterations": max(its),
-        "relres_true": max(rel),
+        "relres_true": None if adjoint else max(rel),
         "status": status,
         "n_mvm": st["n_mvm"],
         "n_mvm_fp64": st["n_mvm_fp64"],
@@ -251,8 +277,16 @@ def main(argv=None):
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
                      "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]},
     }
+    if adjoint:
+        sts = grad_out.pop("stats")
+        out["gradient"] = {**{k: v for k, v in grad_out.items()},
+                           "forward": {"iterations": sts[0]["iters_max"], "n_mvm": sts[0]["n_mvm"],
+                                       "n_mvm_fp64": sts[0]["n_mvm_fp64"]},
+                           "adjoint": {"iterations": sts[1]["iters_max"], "n_mvm": sts[1]["n_mvm"],
+                                       "n_mvm_fp64": sts[1]["n_mvm_fp64"]},
+                           "validation_points": int(wl.X_val.shape[0])}
     # kernel rates of the other precisions on the same GPU (one timed MVM each, same size)
-    if R == 1:
+    if R == 1 and not adjoint:
         v = torch.randn(n, dtype=torch.float64, device=dev)
         for p2 in ("fp64", "fp32"):
             krr.kernel_mv(Xg[:4096], None, wl.eps, v[:4096], prec=p2)

@@ -206,14 +206,15 @@ int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps,
  * with K' = (D^2/eps) K.  One forward and one adjoint PCG (same preconditioner P, may be NULL) in the
  * working precision `prec`; the products that assemble the loss and gradient (K_vt alpha and K'_vt alpha
  * fused, K_vt^T r_v, K' alpha) run in FP64.  Host scalars out; alpha_out [dev] n (optional), lambda_out [dev] n
- * (optional).
+ * (optional); stats [host] optional: two entries, the forward and the adjoint solve (HIP-event times recorded
+ * when given).
  */
 int krr_grad(const double* Xtr, int64_t n, const double* ytr,
              const double* Xval, int64_t m, const double* yval, int32_t d,
              double eps, double beta, const krr_precond* P,
              double tol, int32_t maxit, int32_t replace_every, int32_t prec,
              double* loss, double* dloss_dlog_eps, double* dloss_dlog_beta,
-             double* alpha_out, double* lambda_out, void* stream);
+             double* alpha_out, double* lambda_out, krr_solve_stats* stats, void* stream);
 
 /*
  * Tile-shape autotuner for the kernel MVM (project-written; the paper has none).

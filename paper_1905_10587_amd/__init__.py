@@ -76,7 +76,7 @@ _SIGS = {
     "krr_pcg_solve": ([_vp, _i64, _i32, _f64, _vp, _i32, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp, _vp, _vp,
                        _i32, _vp], _i32),
     "krr_grad": ([_vp, _i64, _vp, _vp, _i64, _vp, _i32, _f64, _f64, _vp, _f64, _i32, _i32, _i32, _vp, _vp, _vp,
-                  _vp, _vp, _vp], _i32),
+                  _vp, _vp, _vp, _vp], _i32),
     "krr_autotune": ([_i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "krr_autotune_save": ([ctypes.c_char_p], _i32),
     "krr_autotune_load": ([ctypes.c_char_p], _i32),
@@ -314,8 +314,9 @@ def pcg_solve(X, Y, eps: float, betas, P: Optional[Preconditioner] = None, *, to
 
 
 def grad(Xtr, ytr, Xval, yval, eps: float, beta: float, P: Optional[Preconditioner] = None, *, tol=1e-8,
-         maxit=10000, replace_every=0, prec="fp64"):
-    """(loss, dL/dlog eps, dL/dlog beta, alpha, lambda) by the adjoint method."""
+         maxit=10000, replace_every=0, prec="fp64", return_stats=False):
+    """(loss, dL/dlog eps, dL/dlog beta, alpha, lambda) by the adjoint method; with return_stats, a sixth
+    element: the forward and adjoint solves' statistics (two dicts)."""
     lib = load()
     Xtr, ytr, Xval, yval = _dev(Xtr), _dev(ytr), _dev(Xval), _dev(yval)
     n, d = Xtr.shape
@@ -323,10 +324,13 @@ def grad(Xtr, ytr, Xval, yval, eps: float, beta: float, P: Optional[Precondition
     loss, ge, gb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     alpha = torch.empty(n, dtype=torch.float64, device=Xtr.device)
     lam = torch.empty(n, dtype=torch.float64, device=Xtr.device)
+    st = (SolveStats * 2)()
     _chk(lib, lib.krr_grad(_p(Xtr), n, _p(ytr), _p(Xval), m, _p(yval), d, float(eps), float(beta),
                            None if P is None else P.handle, float(tol), int(maxit), int(replace_every),
                            _prec(prec), ctypes.byref(loss), ctypes.byref(ge), ctypes.byref(gb), _p(alpha), _p(lam),
-                           _stream()))
+                           st if return_stats else None, _stream()))
+    if return_stats:
+        return loss.value, ge.value, gb.value, alpha, lam, [st[0].as_dict(), st[1].as_dict()]
     return loss.value, ge.value, gb.value, alpha, lam
 
 

@@ -57,7 +57,8 @@ static double dot_dev(const double* a, int sa, const double* b, int sb, int64_t 
 extern "C" int krr_grad(const double* Xtr, int64_t n, const double* ytr, const double* Xval, int64_t m,
                         const double* yval, int32_t d, double eps, double beta, const krr_precond* P, double tol,
                         int32_t maxit, int32_t replace_every, int32_t prec, double* loss, double* dloss_dlog_eps,
-                        double* dloss_dlog_beta, double* alpha_out, double* lambda_out, void* stream) {
+                        double* dloss_dlog_beta, double* alpha_out, double* lambda_out, krr_solve_stats* stats,
+                        void* stream) {
   using namespace krr;
   return guarded([&] {
     validate_common(m, n, d, eps);
@@ -74,7 +75,8 @@ extern "C" int krr_grad(const double* Xtr, int64_t n, const double* ytr, const d
     KRR_CHECK_HIP(hipMemsetAsync(alpha.p, 0, sizeof(double) * n, s));
     KRR_CHECK_HIP(hipMemsetAsync(lam.p, 0, sizeof(double) * n, s));
     // forward solve
-    PcgResult f = pcg_solve(Xtr, n, d, eps, ytr, 1, &beta, P, tol, maxit, replace_every, prec, alpha.p, false, s);
+    const bool timing = stats != nullptr;
+    PcgResult f = pcg_solve(Xtr, n, d, eps, ytr, 1, &beta, P, tol, maxit, replace_every, prec, alpha.p, timing, s);
     if (f.status < 0) return f.status;
     // [K_vt alpha, K'_vt alpha]
     kernel_mv_raw(Xval, m, Xtr, n, d, eps, alpha.p, 1, nullptr, 2, KRR_FP64, Uv.p, 2, s);
@@ -85,12 +87,16 @@ extern "C" int krr_grad(const double* Xtr, int64_t n, const double* ytr, const d
     // g = K_vt^T r_v = K(Xtr, Xval) r_v
     kernel_mv_raw(Xtr, n, Xval, m, d, eps, rv.p, 1, nullptr, 0, KRR_FP64, g.p, 1, s);
     // adjoint solve
-    PcgResult a = pcg_solve(Xtr, n, d, eps, g.p, 1, &beta, P, tol, maxit, replace_every, prec, lam.p, false, s);
+    PcgResult a = pcg_solve(Xtr, n, d, eps, g.p, 1, &beta, P, tol, maxit, replace_every, prec, lam.p, timing, s);
     if (a.status < 0) return a.status;
     // K' alpha on the training set
     kernel_mv_raw(Xtr, n, Xtr, n, d, eps, alpha.p, 1, nullptr, 1, KRR_FP64, Kpa.p, 1, s);
     const double t2 = dot_dev(lam.p, 1, Kpa.p, 1, n, tmp.p, s);      // lambda^T K' alpha
     const double t3 = dot_dev(lam.p, 1, alpha.p, 1, n, tmp.p, s);    // lambda^T alpha
+    if (stats) {
+      stats[0] = f.st;
+      stats[1] = a.st;
+    }
     *loss = L;
     *dloss_dlog_eps = t1 - t2;
     *dloss_dlog_beta = -beta * t3;
