@@ -310,12 +310,13 @@ bool kmv_uses_block(int prec, int d, int R, int deriv) {
 }
 
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square) {
-  if (rclass(prec, R) == 3) return 0;
+  // block MVM: K = 32 contraction, 4 target fragments x 2 column groups (fastest at n = 5e5, R = 128)
+  if (rclass(prec, R) == 3) return prec == KRR_MIXED ? 7 : 0;
   if (prec == KRR_MIXED) {
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
     const int nch = mixed_chunks(d);
-    if (kmv_is_symmetric(prec, d, R, 0, square, 10)) return 10;   // symmetric square product
+    if (kmv_is_symmetric(prec, d, R, 0, square, 11)) return 11;   // symmetric square product (NF 8; 4 above 2 chunks)
     if (nch == 1) return 3;
     if (nch == 2) return 9;
     if (nch <= 4) return 8;
@@ -472,8 +473,15 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
       if (!sym) var -= 2;
     }
     TM = sym ? (var == 3 ? 2 : 4) : D >= 32 ? 1 : kTM[var];
+    // many right-hand sides in FP64: wide column chunks (the exp of a pair is shared by RC columns)
+    // (a chunk must not run past the padded column count Rp: RC divides Rp)
+    if (prec == KRR_FP64 && !sym && DV == 0 && D <= 16 && R >= 16 && Rp % 16 == 0) {
+      RC = R >= 32 && Rp % 32 == 0 ? 32 : 16;
+      TM = 1;
+    }
     rows = 256 * TM;
     gz = (int)ceil_div(R, RC);   // real columns only (Rp is padded to 8)
+    KRR_REQUIRE(Rp % RC == 0, "internal: column chunk does not divide the padded column count");
   }
   const int64_t gx = T.npad / rows;
   const int64_t nsrc = S.npad;

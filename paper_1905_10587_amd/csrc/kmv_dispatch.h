@@ -16,7 +16,8 @@ struct KmvGrid {
 };
 
 // FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),
-// RC in {1,4,8}, DV in {0,2}.  Return false if the combination is not instantiated.
+// RC in {1,4,8}, DV in {0,2}; FP64 also RC in {16, 32} with TM 1, DV 0, D <= 16.  Return false if the
+// combination is not instantiated.
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
                     const double* v, double neg_c, double* part, hipStream_t s);
 // Symmetric FP64 square product of one column (D in {2, 4, 6, 8, 16}, TM in {2, 4}).

@@ -20,8 +20,13 @@ static void go64(const KmvGrid& g, const double* xt, const double* xs, const dou
   if (DV == 2) { go64<D, TM, RC, 2>(g, xt, xs, v, neg_c, part, s); return true; }
 #define KRR_RC(D, TM) \
   if (RC == 1) { KRR_DV(D, TM, 1) } if (RC == 4) { KRR_DV(D, TM, 4) } if (RC == 8) { KRR_DV(D, TM, 8) }
+// TM 1 also has wide column chunks (RC 16, 32; K only) for many right-hand sides
+#define KRR_RCW(D) \
+  KRR_RC(D, 1) \
+  if (RC == 16 && DV == 0) { go64<D, 1, 16, 0>(g, xt, xs, v, neg_c, part, s); return true; } \
+  if (RC == 32 && DV == 0) { go64<D, 1, 32, 0>(g, xt, xs, v, neg_c, part, s); return true; }
 #define KRR_TM3(D) \
-  if (TM == 1) { KRR_RC(D, 1) } if (TM == 2) { KRR_RC(D, 2) } if (TM == 4) { KRR_RC(D, 4) }
+  if (TM == 1) { KRR_RCW(D) } if (TM == 2) { KRR_RC(D, 2) } if (TM == 4) { KRR_RC(D, 4) }
 #define KRR_TM1(D) \
   if (TM == 1) { KRR_RC(D, 1) }
 

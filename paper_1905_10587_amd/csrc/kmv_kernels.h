@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
                                                  int64_t mpad, int Rout) {
   // neg_c = -log2(e) / eps: the exponent q = neg_c * D^2 is the base-2 exponent of the kernel value
   constexpr int NO = DV == 2 ? 2 : 1;
-  constexpr int TS = DirectTile<D>::TS;
+  constexpr int TS = DirectTile<D>::TS * 8 / (RC > 8 ? RC : 8);   // wide column chunks: shorter tiles
   __shared__ double sx[TS * D];
   __shared__ double sv[TS * RC];
   const int64_t ibase = (int64_t)blockIdx.x * (256 * TM) + threadIdx.x;
@@ -790,13 +790,15 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__
 // Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle in
 // column order.
 template <int NCH, int NF>
-__global__ __launch_bounds__(256) void k_kmv_mixed_sym(const uint4* __restrict__ A, const uint4* __restrict__ B,
+// (two resident blocks per CU: the register budget is held to 256 per lane; NF 8 spills a few values)
+__global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restrict__ A, const uint4* __restrict__ B,
                                                        const float* __restrict__ v, int Rp, int E, int NS,
                                                        int64_t npad, double* __restrict__ part, int Rout) {
   static_assert(NF >= 2, "the pipeline needs two fragments per step");
   constexpr int KV = NCH * 4;
   constexpr int RS = KV + 1;
-  constexpr int TS = NCH <= 2 ? 128 : 64;    // sources per LDS tile
+  // sources per LDS tile (two tiles, the column partials and the weights fit twice per CU)
+  constexpr int TS = NCH == 1 ? 256 : (NCH == 2 ? 128 : 64);
   constexpr int SPT = TS / 16;
   constexpr int TPF = 256 / TS;              // tiles per FP64 fold of the row sums (every 256 sources)
   constexpr int NI = (TS * RS + 63) / 64;

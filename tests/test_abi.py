@@ -78,8 +78,8 @@ def test_kmv_variant_introspection(lib):
     L = krr.load()
     for d in (3, 4, 8, 13, 20, 30):   # clear entries earlier tests may have forced
         L.krr_set_variant(d, 1, 2, -1)
-    assert krr.kmv_variant(8, 1, "mixed", square=True) == (10, True)
-    assert krr.kmv_variant(4, 1, "mixed", square=True) == (10, True)
+    assert krr.kmv_variant(8, 1, "mixed", square=True) == (11, True)
+    assert krr.kmv_variant(4, 1, "mixed", square=True) == (11, True)
     assert krr.kmv_variant(8, 1, "mixed", square=False) == (9, False)
     assert krr.kmv_variant(4, 1, "mixed", square=False) == (3, False)
     assert krr.kmv_variant(8, 1, "mixed", deriv=2, square=True) == (9, False)

@@ -221,3 +221,24 @@ def test_symmetric_square_product(gpu_lib, case, prec):
               f"(with shift {err_s:.2e})", flush=True)
         assert err <= TOL[prec] and err_s <= TOL[prec]
     gpu_lib.set_variant(d, 1, prec, -1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("R", [16, 40, 128])
+@pytest.mark.parametrize("d", [3, 8])
+def test_fp64_many_columns(gpu_lib, R, d):
+    """FP64 products with many right-hand sides (wide column chunks of 16 or 32: one exp per pair shared by
+    the chunk), a ragged last chunk at R = 40, square and cross-set."""
+    rng = np.random.default_rng(R + d)
+    Xs = rng.random((1300, d))
+    Xt = rng.random((700, d))
+    V = rng.standard_normal((1300, R))
+    eps = 0.05 * d
+    for targets, same in ((Xs, True), (Xt, False)):
+        K = ok.kernel_matrix(targets, Xs, eps)
+        ref, scale = K @ V, K @ np.abs(V)
+        U = gpu_lib.kernel_mv(torch.from_numpy(targets), None if same else torch.from_numpy(Xs), eps,
+                              torch.from_numpy(V), prec="fp64").cpu().numpy()
+        err = _scaled_err(U, ref, scale)
+        print(f"fp64 R={R} d={d} square={same}: max scaled error {err:.2e}", flush=True)
+        assert err <= TOL["fp64"]
