@@ -238,6 +238,16 @@ def main(argv=None):
     variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec == "mixed" else (None, False)
     peak = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
     traffic = stored_traffic(wl.name) if prec == "mixed" and R == 1 else None
+    block_mvm = prec == "mixed" and R > 1
+    if block_mvm:
+        # many right-hand sides: the exp'd tile is contracted with V on MFMA (three BF16 split products per
+        # column), plus the split cross term (NCH chunks of 32) -> MFMA bound; dense BF16 peak 2.5 PFLOP/s
+        nch = -(-(6 * wl.d + 6) // 32)
+        flop_pair = 2.0 * 3 * R + 2.0 * 32 * nch
+        roofline = {"bound": "mfma", "kernel": f"block MVM (variant {variant}), R={R}, d={wl.d}",
+                    "achieved": round(achieved * flop_pair / 1e12, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                    "frac": round(achieved * flop_pair / 2.5e15, 3), "traffic": None,
+                    "flop_per_pair": flop_pair, "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]}
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -268,7 +278,7 @@ def main(argv=None):
         "t_precond_s": round(st["t_precond_ms"] / 1e3, 3),
         "kappa_est": round(st["kappa_est"], 1),
         "mvm_gpairs_s": round(achieved / 1e9, 1),
-        "roofline": {"bound": "alu",
+        "roofline": roofline if block_mvm else {"bound": "alu",
                      "kernel": (f"{prec} MVM, variant {variant}, " if variant is not None else f"{prec} MVM, ")
                                + ("symmetric form (exp + 2 FMA per evaluated pair)" if sym
                                   else "direct form (exp + FMA per pair)") + f", d={wl.d}",
@@ -277,6 +287,17 @@ def main(argv=None):
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
                      "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]},
     }
+    if R > 1:   # per-beta summary of the block solve's columns
+        by_beta = {}
+        for c in range(R):
+            e = by_beta.setdefault(str(betas_col[c]), {"columns": 0, "converged": 0, "iterations_max": 0,
+                                                        "relres_max": 0.0})
+            e["columns"] += 1
+            e["converged"] += int(rel[c] <= wl.tol)
+            e["iterations_max"] = max(e["iterations_max"], int(its[c]))
+            e["relres_max"] = max(e["relres_max"], float(rel[c]))
+        out["columns_by_beta"] = by_beta
+        out["ms_per_iteration"] = round(1e3 * (t_step - t_build) / max(max(its), 1), 1)
     if adjoint:
         sts = grad_out.pop("stats")
         out["gradient"] = {**{k: v for k, v in grad_out.items()},
