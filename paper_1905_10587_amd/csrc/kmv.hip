@@ -533,6 +533,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   int64_t src_len = round_up(ceil_div(nsrc, split), 256);
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   if (sym) {
+    KRR_REQUIRE(RoutK == 1, "internal: the symmetric kernels write dense one-column partials");
     // super-tile edge E: the per-CU work ceil(items / CUs) x E^2 (at least two blocks per CU to hide
     // latency) is minimised, with the partial buffer (NS x npad doubles) kept near 2 GB
     const int64_t cus = device_cus();

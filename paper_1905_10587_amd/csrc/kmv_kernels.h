@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
       }
       for (int t = 0; t < ntile; ++t) {
         const int64_t jt = s0 + (int64_t)t * TS;
-        double* dst = part + ((int64_t)r * npad + jt + tid) * Rout;
+        double* dst = part + (int64_t)r * npad + jt + tid;   // one column: dense partials
         double prev = 0.0;
         if (COL && tt > 0) prev = *dst;
         __syncthreads();
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
         if (COL) *dst = prev + (((cacc[0][tid] + cacc[1][tid]) + cacc[2][tid]) + cacc[3][tid]);
       }
 #pragma unroll
-      for (int m = 0; m < TM; ++m) part[((int64_t)c * npad + ib + m * 256) * Rout] = acc[m];
+      for (int m = 0; m < TM; ++m) part[(int64_t)c * npad + ib + m * 256] = acc[m];
     }
   };
   if (diag) run(std::false_type{});
@@ -945,7 +945,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
         vr = vload(s0 + (int64_t)tn * TS);
       }
       // column partial of the earlier target tiles for this source tile, fetched under the tile's work
-      double* dst = part + ((int64_t)r * npad + s0 + (int64_t)t * TS + (tid < TS ? tid : 0)) * Rout;
+      double* dst = part + (int64_t)r * npad + s0 + (int64_t)t * TS + (tid < TS ? tid : 0);   // dense partials
       double prev = 0.0;
       if (COL && tid < TS && tt > 0) prev = *dst;
       compute(odd ? sb1 : sb0, odd ? sv1 : sv0, odd ? cb1 : cb0, colflag);
@@ -969,6 +969,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
         *dst = prev + cs;
       }
       if (t == ntile - 1) {   // row sums of this target tile -> part[c][rows]
+        double* prow = part + (int64_t)c * npad + row0 + kq * 4;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -978,7 +979,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
             x += __shfl_xor(x, 4);
             x += __shfl_xor(x, 2);
             x += __shfl_xor(x, 1);
-            if (r16 == 0) part[((int64_t)c * npad + row0 + 16 * f + kq * 4 + e) * Rout] = x;
+            if (r16 == 0) prow[16 * f + e] = x;
           }
       }
     }
