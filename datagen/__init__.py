@@ -160,6 +160,14 @@ def sketch_sparse_draws(n: int, l: int, r: int, seed: int):
     return np.ascontiguousarray(idx), _c(sign)
 
 
+def random_anchors(n: int, k: int, seed: int) -> np.ndarray:
+    """k distinct point indices drawn uniformly without replacement (random-sampling anchors)."""
+    if not 1 <= k <= n:
+        raise ValueError("need 1 <= k <= n")
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.choice(n, size=k, replace=False).astype(np.int64))
+
+
 def uniform_points(n: int, d: int, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return _c(lo + (hi - lo) * rng.random((n, d)))

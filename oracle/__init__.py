@@ -9,10 +9,12 @@ fed the same inputs by the separate ``datagen`` module.
 
 Modules
   kernel   Gaussian kernel matrix, matrix-free kernel MVM, derivative kernel (Sec. 1, Eq. 1-2, Eq. dscrt_gt)
-  precond  Algorithms 1-4: sketches, pivoted QR anchor selection, Nystrom factor, Woodbury apply (Sec. 3)
+  precond  Algorithms 1-4: sketches, pivoted QR anchor selection, Nystrom factor, Woodbury apply (Sec. 3);
+           farthest point sampling and caller-given anchors (remark in Sec. 3)
   pcg      Algorithm 5: preconditioned CG with residual replacement and Lanczos estimates (Sec. 3, 4.1)
   adjoint  validation-loss gradient w.r.t. log eps and log beta (adjoint method; not in the paper)
-  theory   Theorem maintheorem, the ID corollary, the SVD remark, Corollary tradeoff, CG rate (Sec. 4)
+  theory   Theorem maintheorem, the ID corollary, the SVD remark, Corollary tradeoff (also on a dataset's
+           bounding box), CG rate (Sec. 4)
 
 Parity status: every function is pinned by the CPU tests in tests/test_oracle_*.py
 except the FP32 / mixed-precision error levels of the GPU path, which have no

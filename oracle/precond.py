@@ -8,6 +8,8 @@ Steps, in the paper's order:
   Algorithm 3 (BuildCholesky): U^{-1} = K(X_S, X_S); a square root U^{1/2} from
       an EVD; Y = C U^{1/2}; Cholesky of beta I + U^{1/2} C^T C U^{1/2}
       (Eq. to_factor2 and Eq. chol_factor).
+  Remark in Sec. 3: the anchors may instead come from random sampling or farthest
+      point sampling; Algorithm 3 then runs unchanged on them.
   Algorithm 4 (ApplyPreconditioner): (K~ + beta I)^{-1} x through the Woodbury
       identity (Eq. woodbury) in the stabilised form.
 
@@ -26,6 +28,9 @@ Readings where the paper is loose (all stated in the design notes too):
     index.  The oracle recomputes every residual column norm at every step
     (no norm downdating).
   * Cholesky convention: lower L with L L^T (the paper writes L^T L).
+  * Other anchor choices (remark in Sec. 3): random sampling (the indices are an input,
+    drawn by the caller) and farthest point sampling, read as the greedy rule that adds the
+    point farthest from the chosen set, squared Euclidean distances, ties to the lowest index.
 """
 from __future__ import annotations
 
@@ -156,11 +161,56 @@ def build_precond(X, eps, betas, k, *, omega=None, idx=None, sign=None, tau=DEFA
     else:
         Y = sketch_sparse(X, eps, idx, sign)
     qr = qrcp(Y.T, k)
-    S = qr["piv"]
+    P = build_precond_from_anchors(X, eps, betas, qr["piv"], tau=tau)
+    P.update(Y=Y, rdiag=qr["rdiag"])
+    return P
+
+
+def build_precond_from_anchors(X, eps, betas, S, *, tau=DEFAULT_TAU):
+    """Algorithm 3 for anchors chosen some other way (remark in Sec. 3: random sampling or FPS
+    in place of the ID; the theoretical bounds then no longer apply)."""
+    S = np.asarray(S, np.int64)
     nf = nystrom_factor(X, S, eps, tau)
     Ls = {float(b): core_cholesky(nf["W"], float(b)) for b in np.atleast_1d(betas)}
-    return {"Y": Y, "S": S, "rdiag": qr["rdiag"], "W": nf["W"], "lam": nf["lam"],
-            "kept": nf["kept"], "L": Ls}
+    return {"S": S, "W": nf["W"], "lam": nf["lam"], "kept": nf["kept"], "L": Ls}
+
+
+# ---------------------------------------------------------------- farthest point sampling
+def sqdist_to_point(X, x):
+    """||X[i] - x||^2 for every row, accumulated coordinate by coordinate: each difference,
+    square and sum is rounded on its own (no fused multiply-add)."""
+    X = np.asarray(X, np.float64)
+    acc = np.zeros(X.shape[0])
+    for c in range(X.shape[1]):
+        t = X[:, c] - x[c]
+        acc = acc + t * t
+    return acc
+
+
+def fps(X, k, start=0):
+    """Farthest point sampling, the second alternative anchor choice named in the remark of Sec. 3.
+
+    S[0] = start.  Step j picks, among the points not yet chosen, the one whose squared distance
+    to the nearest chosen point is largest (ties to the lowest index).  Returns (S, dsel) with
+    dsel[j] that largest squared distance (dsel[0] = inf).
+    """
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    if not 1 <= k <= n or not 0 <= start < n:
+        raise ValueError("need 1 <= k <= n and 0 <= start < n")
+    S = np.empty(k, np.int64)
+    dsel = np.empty(k)
+    S[0], dsel[0] = start, np.inf
+    chosen = np.zeros(n, bool)
+    chosen[start] = True
+    dmin = np.full(n, np.inf)
+    for j in range(1, k):
+        dmin = np.minimum(dmin, sqdist_to_point(X, X[S[j - 1]]))
+        cand = np.where(chosen, -np.inf, dmin)
+        i = int(np.argmax(cand))             # first maximum = lowest index
+        S[j], dsel[j] = i, cand[i]
+        chosen[i] = True
+    return S, dsel
 
 
 def apply_precond(P, beta, x):

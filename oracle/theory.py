@@ -4,7 +4,8 @@
   * ID corollary: M = 2 sqrt(4k(n-k)+1), so cond <= 1 + 2 lam_{k+1} sqrt(4k(n-k)+1)/b <= 1 + 2 lam_{k+1}(n+1)/b
   * SVD remark: with K~ the best rank-k approximation, cond = 1 + lam_{k+1}/b exactly
   * Theorem gaussiankernelbound / Corollary tradeoff (Eq. condbound): rank needed for a target condition number
-    gamma = (2/pi) sqrt(h^{-2} ln(Mbar n / (b (xi - 1)))),  k >= prod_i (floor(gamma q_i) + 1)
+    gamma = (2/pi) sqrt(h^{-2} ln(Mbar n / (b (xi - 1)))),  k >= prod_i (floor(gamma q_i) + 1),
+    on a dataset with q_i its bounding-box side lengths and h = sqrt(eps)
   * Eq. cgrate: ||e_i||_A <= 2 ||e_0||_A ((sqrt(kappa)-1)/(sqrt(kappa)+1))^i
   * Eq. noprecond_rate and Eq. precond_rate2: iteration estimates
 """
@@ -44,6 +45,16 @@ def rank_bound(q, h, n, beta, xi, Mbar=None):
     for qi in q:
         out *= int(math.floor(g * qi)) + 1
     return out
+
+
+def rank_for_cond(X, eps, beta, xi, Mbar=None):
+    """Corollary tradeoff applied to a dataset: q_i are the side lengths of the bounding box of X,
+    h = sqrt(eps), n the number of points.  Returns (gamma, k) of Eq. condbound_gamma / Eq. condbound."""
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    q = X.max(axis=0) - X.min(axis=0)
+    h = math.sqrt(eps)
+    return rank_gamma(h, n, beta, xi, Mbar), rank_bound(q, h, n, beta, xi, Mbar)
 
 
 def cg_error_bound(kappa, i):

@@ -90,6 +90,22 @@ def test_rank_bound_worked_examples():
             assert 1e46 < k < 1e47
 
 
+def test_rank_for_cond_on_a_box():
+    # 8 corners of a 2 x 1 x 0.5 box plus two interior points (n = 10), h = 1, Mbar = n, and
+    # beta (xi - 1) = n^2 exp(-(1.05 pi)^2): then gamma = 2.1 exactly in real arithmetic, so the
+    # factors of Eq. condbound are floor(4.2)+1, floor(2.1)+1, floor(1.05)+1 = 5, 3, 2
+    corners = np.array([[a, b, c] for a in (0.0, 2.0) for b in (-1.0, 0.0) for c in (3.0, 3.5)])
+    X = np.vstack([corners, [[1.0, -0.5, 3.2], [0.3, -0.1, 3.4]]])
+    beta = 0.5
+    xi = 1.0 + 100.0 * math.exp(-(1.05 * math.pi) ** 2) / beta
+    g, k = th.rank_for_cond(X, 1.0, beta, xi)
+    assert abs(g - 2.1) < 1e-12
+    assert k == 5 * 3 * 2
+    # eps = h^2: halving h doubles gamma
+    g2, _ = th.rank_for_cond(X, 0.25, beta, xi)
+    assert abs(g2 - 4.2) < 1e-12
+
+
 def test_cg_rate_formulas():
     assert th.cg_error_bound(1.0, 3) == 0.0
     # Eq. precond_rate2 equals Eq. cgrate solved for i with kappa = 1 + M lam/beta (without the factor 2)

@@ -159,3 +159,80 @@ def test_full_rank_preconditioner_is_exact():
     K = ok.kernel_matrix(X, X, eps)
     x = rng.standard_normal(40)
     np.testing.assert_allclose(op.apply_precond(P, beta, (K + beta * np.eye(40)) @ x), x, rtol=1e-6)
+
+
+# ---------------------------------------------------------------- other anchor choices (remark in Sec. 3)
+def test_fps_on_a_line_bisects():
+    # 17 points at 0, 1, ..., 16 starting from 0: the far end, then the midpoint, then the
+    # quarter points, eighth points and the odd points, each level left to right (ties -> lowest index)
+    X = np.arange(17, dtype=np.float64)[:, None]
+    S, dsel = op.fps(X, 17, start=0)
+    np.testing.assert_array_equal(S, [0, 16, 8, 4, 12, 2, 6, 10, 14, 1, 3, 5, 7, 9, 11, 13, 15])
+    np.testing.assert_array_equal(dsel[1:], [256, 64, 16, 16, 4, 4, 4, 4] + [1] * 8)
+    assert np.isinf(dsel[0])
+
+
+def test_fps_k_center_two_approximation():
+    # FPS is Gonzalez's greedy k-center rule: its covering radius is at most twice the optimum,
+    # found here by brute force over every k-subset
+    import itertools
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        X = rng.random((11, 2))
+        D = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1))
+        for k in (2, 3, 4):
+            S, _ = op.fps(X, k, start=trial)
+            r_fps = D[:, S].min(axis=1).max()
+            r_opt = min(D[:, list(c)].min(axis=1).max() for c in itertools.combinations(range(11), k))
+            assert r_opt <= r_fps + 1e-15 and r_fps <= 2 * r_opt + 1e-12
+
+
+def test_fps_separation_and_monotone():
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((300, 3))
+    S, dsel = op.fps(X, 40, start=7)
+    assert len(set(S.tolist())) == 40 and S[0] == 7
+    assert np.all(np.diff(dsel[1:]) <= 0)                     # the pick distance never grows
+    for j in range(1, 40):
+        # pick j is exactly dsel[j] away from its nearest earlier pick, and no point is farther
+        d2 = ((X[S[:j]] - X[S[j]]) ** 2).sum(-1)
+        np.testing.assert_allclose(d2.min(), dsel[j], rtol=1e-14)
+        dall = ((X[:, None, :] - X[None, S[:j], :]) ** 2).sum(-1).min(axis=1)
+        assert dall.max() <= dsel[j] * (1 + 1e-14)
+
+
+def test_fps_duplicates_give_distinct_indices():
+    X = np.ones((6, 2))
+    S, dsel = op.fps(X, 6, start=3)
+    np.testing.assert_array_equal(S, [3, 0, 1, 2, 4, 5])
+    np.testing.assert_array_equal(dsel[1:], 0.0)
+
+
+def test_anchors_given_all_points_reproduce_K():
+    # every point an anchor: the Nystrom approximation is K itself, so the preconditioner inverts K + bI
+    rng = np.random.default_rng(13)
+    X = rng.random((50, 2))
+    eps, beta = 0.02, 1e-2
+    S = datagen.random_anchors(50, 50, seed=14)
+    assert sorted(S.tolist()) == list(range(50))
+    P = op.build_precond_from_anchors(X, eps, [beta], S, tau=0.0)
+    K = ok.kernel_matrix(X, X, eps)
+    np.testing.assert_allclose(P["W"] @ P["W"].T, K, atol=1e-10)
+    x = rng.standard_normal(50)
+    np.testing.assert_allclose(op.apply_precond(P, beta, (K + beta * np.eye(50)) @ x), x, rtol=1e-6)
+
+
+@pytest.mark.parametrize("how", ["random", "fps"])
+def test_anchors_given_nystrom_properties(how):
+    # any anchor set: K~ interpolates the anchor block, K - K~ is PSD (Lemma schur) and the
+    # preconditioned spectrum stays at or above 1
+    rng = np.random.default_rng(15)
+    X = rng.random((200, 3))
+    eps, beta = 0.05, 1e-3
+    S = datagen.random_anchors(200, 25, seed=16) if how == "random" else op.fps(X, 25, start=0)[0]
+    P = op.build_precond_from_anchors(X, eps, [beta], S)
+    K = ok.kernel_matrix(X, X, eps)
+    Kt = P["W"] @ P["W"].T
+    np.testing.assert_allclose(Kt[np.ix_(S, S)], K[np.ix_(S, S)], atol=1e-9)
+    assert np.linalg.eigvalsh(K - Kt).min() > -1e-9
+    assert op.preconditioned_spectrum(K, P["W"], beta).min() >= 1 - 1e-8
