@@ -125,6 +125,98 @@ def kernels_only(a, wl, Xg, krr, torch):
     return 0
 
 
+def study_anchors(a, wl, Xg, Yg, krr, torch, datagen, prec, replace_every):
+    """Anchor-selection variants on one workload (remark in Sec. 3; the l-versus-iterations tradeoff):
+    Algorithm 1 (dense sketch), Algorithm 2 over r, random sampling, farthest point sampling and no
+    preconditioner.  Build time, iterations and solve time for each."""
+    import numpy as np
+    dev = Xg.device
+    n, k, l = wl.n, wl.k, wl.l
+    beta = float(wl.betas[0])
+    seed = datagen.sketch_seed(wl.name)
+    rows = []
+    # warm-up: first use of the build's kernels and BLAS handles, not timed
+    krr.Preconditioner(Xg, wl.eps, [beta], 64, 84, omega=torch.from_numpy(datagen.sketch_dense_omega(n, 84, 1)).to(dev),
+                       prec=prec)
+    torch.cuda.synchronize()
+    cases = [("alg1_dense", {}), *[(f"alg2_sparse_r{r}", {"r": r}) for r in (8, 32, 128)],
+             ("random", {}), ("fps", {}), ("none", {})]
+    for name, opt in cases:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "alg1_dense":
+            om = torch.from_numpy(datagen.sketch_dense_omega(n, l, seed)).to(dev)
+            P = krr.Preconditioner(Xg, wl.eps, [beta], k, l, omega=om, prec=prec)
+        elif name.startswith("alg2"):
+            idx, sign = datagen.sketch_sparse_draws(n, l, opt["r"], seed)
+            P = krr.Preconditioner(Xg, wl.eps, [beta], k, l, idx=torch.from_numpy(idx).to(dev),
+                                   sign=torch.from_numpy(sign).to(dev), prec=prec)
+        elif name == "random":
+            S = torch.from_numpy(datagen.random_anchors(n, k, seed)).to(dev)
+            P = krr.Preconditioner(Xg, wl.eps, [beta], k, anchors=S, prec=prec)
+        elif name == "fps":
+            P = krr.Preconditioner(Xg, wl.eps, [beta], k, anchors="fps", fps_start=0, prec=prec)
+        else:
+            P = None
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        alpha, its, rel, st, status = krr.pcg_solve(Xg, Yg, wl.eps, [beta], P, tol=wl.tol, maxit=a.maxit,
+                                                    replace_every=replace_every, prec=prec)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0 - tb
+        row = {"anchors": name, "build_s": round(tb, 3), "solve_s": round(ts, 3), "iterations": max(its),
+               "relres_true": max(rel), "status": status, "kappa_est": round(st["kappa_est"], 1)}
+        if P is not None:
+            row["build_phases_ms"] = {kk: round(v, 1) for kk, v in P.timings().items()}
+            row["kept"] = P.info()["kept"]
+        log(f"bench: anchors {name}: build {tb:.3f} s, {max(its)} iterations, solve {ts:.3f} s")
+        rows.append(row)
+        del P
+    print(json.dumps({"study": "anchors", "workload": f"{wl.name}: n={n} d={wl.d} eps={wl.eps} beta={beta} "
+                                                      f"k={k} l={l} tol={wl.tol}",
+                      "precision": prec, "replace_every": replace_every, "data": "synthetic", "rows": rows}))
+    return 0
+
+
+def study_cond(a, krr, torch, datagen):
+    """Condition numbers with and without the preconditioner on 10,000-point draws of each workload's
+    distribution (the setting of Sec. 5.1: k = 100, 500, 1000, Algorithm 2 anchors with l = k + 5), measured
+    as the extreme Ritz
+    values of FP64 CG/PCG on a Gaussian right-hand side run to 1e-10; beside them the rank that
+    Corollary tradeoff asks for."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    out = []
+    for name in ("fp32", "mixed", "adjoint", "block"):
+        wl = datagen.make_workload(name, **({"n": 10_000, "m": 1000} if name == "adjoint" else {"n": 10_000}))
+        X = torch.from_numpy(wl.X).to(dev)
+        # a Gaussian right-hand side excites every eigenvector, so the Ritz values reach both ends of
+        # the spectrum (a label vector may have almost nothing at the bottom)
+        yg = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n)).to(dev)
+        beta = float(wl.betas[0])
+        seed = datagen.sketch_seed(name)
+        entry = {"workload": name, "n": wl.n, "d": wl.d, "eps": wl.eps, "beta": beta, "rows": []}
+        for k in (0, 100, 500, 1000):
+            P = None
+            t0 = time.perf_counter()
+            if k:
+                idx, sign = datagen.sketch_sparse_draws(wl.n, k + 5, min(32, wl.n), seed)
+                P = krr.Preconditioner(X, wl.eps, [beta], k, k + 5, idx=torch.from_numpy(idx).to(dev),
+                                       sign=torch.from_numpy(sign).to(dev), prec="fp64")
+            _, its, rel, st, status = krr.pcg_solve(X, yg, wl.eps, [beta], P, tol=1e-10, maxit=20_000,
+                                                    prec="fp64")
+            torch.cuda.synchronize()
+            entry["rows"].append({"k": k, "cond": st["kappa_est"], "lam_min": st["lam_min_est"],
+                                  "lam_max": st["lam_max_est"], "iterations": max(its), "relres_true": max(rel),
+                                  "s": round(time.perf_counter() - t0, 3)})
+            log(f"bench: cond {name} k={k}: {st['kappa_est']:.4g} ({max(its)} iterations)")
+        g, kb, q = krr.rank_for_cond(X, wl.eps, beta, 2.0)
+        entry["corollary_tradeoff_xi2"] = {"gamma": g, "k_bound": kb, "q": q}
+        out.append(entry)
+    print(json.dumps({"study": "cond", "data": "synthetic", "subsets": out}))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +232,9 @@ def main(argv=None):
                          "mixed and FP64 kernel MVMs; prints their HIP-event times")
     ap.add_argument("--reps", type=int, default=3, help="MVM launches per precision in --kernels-only")
     ap.add_argument("--save-alpha", default=None, help="write the timed solve's alpha (.npy) after the run")
+    ap.add_argument("--study", default=None, choices=["anchors", "cond"],
+                    help="instead of the benchmark step: anchor-selection variants on the workload, or "
+                         "condition numbers with/without the preconditioner on 10,000-point subsets")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU row sharding of the "
@@ -155,6 +250,8 @@ def main(argv=None):
 
     krr.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if a.study == "cond":
+        return study_cond(a, krr, torch, datagen)
     wl = datagen.make_workload(a.workload)
     prec = a.prec or {"mixed": "mixed", "fp32": "mixed", "small": "fp64", "block": "mixed", "adjoint": "mixed"}[a.workload]
     replace_every = 0 if prec == "fp64" else 10
@@ -206,6 +303,8 @@ def main(argv=None):
 
     if a.kernels_only:
         return kernels_only(a, wl, Xg, krr, torch)
+    if a.study == "anchors":
+        return study_anchors(a, wl, Xg, Yg, krr, torch, datagen, prec, replace_every)
     os.environ.setdefault("KRR_PROGRESS", "100")
     for w in range(a.warmup):
         log(f"bench: warmup step {w + 1}/{a.warmup}")

@@ -134,6 +134,47 @@ int krr_build_precond(const double* X, int64_t n, int32_t d, double eps,
                       double tau, int32_t prec, int32_t flags,
                       krr_precond** out, void* stream);
 
+/*
+ * Setup stage on anchors chosen another way (remark in Sec. 3: random sampling or farthest point
+ * sampling in place of the ID; the bounds of Sec. 4 then no longer hold).  Algorithm 3 and the
+ * core factors run exactly as in krr_build_precond.
+ *   S [dev] int64 k distinct indices in [0, n) chosen by the caller (random sampling draws them);
+ *   S == NULL: farthest point sampling from point fps_start (as krr_fps).  The handle keeps its
+ *   own copy of the anchors.  Other arguments as in krr_build_precond (no sketch, so no l, r,
+ *   random inputs or flags).  Timings: ms[0] = 0, ms[1] = anchor selection (FPS, or the check of S);
+ *   krr_precond_info reports rdiag as zeros.  KRR_EINVAL for out-of-range or repeated anchors.
+ */
+int krr_build_precond_anchors(const double* X, int64_t n, int32_t d, double eps,
+                              const double* betas, int32_t nbeta, const int64_t* S, int32_t k,
+                              int64_t fps_start, double tau, int32_t prec,
+                              krr_precond** out, void* stream);
+
+/*
+ * Farthest point sampling (remark in Sec. 3): S[0] = start; each next anchor is the point, not yet
+ * chosen, with the largest squared Euclidean distance to its nearest chosen point (ties to the
+ * lowest index).  Distances are summed over coordinates in order, each operation rounded on its
+ * own, so the picks are reproducible bit for bit.
+ *   X [dev] n x d FP64; 1 <= k <= n; 0 <= start < n.
+ *   S [dev] int64 k output (distinct indices); dsel [dev] k output or NULL: the squared distance of
+ *   each pick when chosen (dsel[0] = +inf, then non-increasing).  Uses k - 1 kernel launches.
+ */
+int krr_fps(const double* X, int64_t n, int32_t d, int32_t k, int64_t start, int64_t* S, double* dsel,
+            void* stream);
+
+/*
+ * Rank for a target condition number on the data (Corollary tradeoff, Eq. condbound_gamma and
+ * Eq. condbound): q_i are the side lengths of the bounding box of X (device reduction), h = sqrt(eps),
+ *   gamma = (2/pi) sqrt(h^{-2} ln(Mbar n / (beta (xi - 1)))),   k = prod_i (floor(gamma q_i) + 1).
+ *   X [dev] n x d FP64; beta > 0; xi > 1 (the target condition number); Mbar > 0, or <= 0 for
+ *   Mbar = n (the ID value of the remark after the corollary).  KRR_EINVAL unless
+ *   Mbar n > beta (xi - 1).
+ *   Outputs [host]: gamma; k_bound as a double (exact below 2^53, may overflow to inf);
+ *   q_host d values or NULL.  Synchronises the stream.  The bound is stated for ID-built
+ *   preconditioners.
+ */
+int krr_rank_for_cond(const double* X, int64_t n, int32_t d, double eps, double beta, double xi,
+                      double Mbar, double* gamma, double* k_bound, double* q_host, void* stream);
+
 /* Sizes and host copies of small results.  Any output pointer may be NULL.
  *   S_host [host] int64 k anchors; kept: rank kept after the EVD truncation;
  *   lam_host [host] k eigenvalues of K_SS (ascending); rdiag_host [host] k QR diagonals. */
@@ -176,6 +217,9 @@ typedef struct {
   double kappa_est;       /* Lanczos estimate of the preconditioned condition number, column 0 */
   double t_mvm_kernel_ms; /* HIP-event time of the main MVM kernel alone (t_mvm_ms without operand
                              staging and the FP64 finishing pass) */
+  double lam_min_est;     /* smallest and largest eigenvalue of column 0's Lanczos tridiagonal (Ritz values */
+  double lam_max_est;     /* of the preconditioned operator; kappa_est is their ratio; 0 if none), built from
+                             the CG coefficients up to the first claim of convergence of column 0 */
 } krr_solve_stats;
 
 /*

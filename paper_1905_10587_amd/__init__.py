@@ -51,7 +51,8 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iters_max", ctypes.c_int32), ("n_mvm", ctypes.c_int32), ("n_mvm_fp64", ctypes.c_int32),
                 ("n_replace", ctypes.c_int32), ("t_total_ms", ctypes.c_double), ("t_mvm_ms", ctypes.c_double),
                 ("t_mvm_fp64_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
-                ("kappa_est", ctypes.c_double), ("t_mvm_kernel_ms", ctypes.c_double)]
+                ("kappa_est", ctypes.c_double), ("t_mvm_kernel_ms", ctypes.c_double),
+                ("lam_min_est", ctypes.c_double), ("lam_max_est", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,6 +69,10 @@ _SIGS = {
     "krr_qrcp": ([_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
     "krr_build_precond": ([_vp, _i64, _i32, _f64, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _f64, _i32, _i32,
                            ctypes.POINTER(_vp), _vp], _i32),
+    "krr_build_precond_anchors": ([_vp, _i64, _i32, _f64, _vp, _i32, _vp, _i32, _i64, _f64, _i32,
+                                   ctypes.POINTER(_vp), _vp], _i32),
+    "krr_fps": ([_vp, _i64, _i32, _i32, _i64, _vp, _vp, _vp], _i32),
+    "krr_rank_for_cond": ([_vp, _i64, _i32, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp], _i32),
     "krr_precond_info": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "krr_precond_get": ([_vp, _i32, _i32, _vp, _sz, _vp], _i32),
     "krr_precond_timings": ([_vp, _vp, _vp], _i32),
@@ -207,29 +212,70 @@ def qrcp(Y, k: int, prec="fp64"):
     return piv, rdiag
 
 
+def fps(X, k: int, start: int = 0):
+    """Farthest point sampling on the device: (S int64 k, dsel float64 k), dsel[0] = inf."""
+    lib = load()
+    X = _dev(X)
+    n, d = X.shape
+    S = torch.empty(int(k), dtype=torch.int64, device="cuda")
+    dsel = torch.empty(int(k), dtype=torch.float64, device="cuda")
+    _chk(lib, lib.krr_fps(_p(X), n, d, int(k), int(start), _p(S), _p(dsel), _stream()))
+    return S, dsel
+
+
+def rank_for_cond(X, eps: float, beta: float, xi: float, Mbar: Optional[float] = None):
+    """Corollary tradeoff on the data: (gamma, k bound as a float, bounding-box side lengths q)."""
+    lib = load()
+    X = _dev(X)
+    n, d = X.shape
+    g, kb = ctypes.c_double(), ctypes.c_double()
+    q = (ctypes.c_double * d)()
+    _chk(lib, lib.krr_rank_for_cond(_p(X), n, d, float(eps), float(beta), float(xi),
+                                    0.0 if Mbar is None else float(Mbar), ctypes.byref(g), ctypes.byref(kb), q,
+                                    _stream()))
+    return g.value, kb.value, list(q)
+
+
 class Preconditioner:
     """ID / Nystrom / Woodbury preconditioner (Algorithms 1-4) owned by the library."""
 
     W64, W32, LCORE, SKETCH, MCORE = 0, 1, 2, 3, 4
 
-    def __init__(self, X, eps: float, betas: Sequence[float], k: int, l: int, *, omega=None, idx=None,
-                 sign=None, tau: float = 0.0, prec="fp64", keep_sketch: bool = False):
+    def __init__(self, X, eps: float, betas: Sequence[float], k: int, l: Optional[int] = None, *, omega=None,
+                 idx=None, sign=None, anchors=None, fps_start: int = 0, tau: float = 0.0, prec="fp64",
+                 keep_sketch: bool = False):
+        """anchors=None: Algorithm 1 (omega) or 2 (idx, sign) with l sketch columns and the pivoted QR;
+        anchors="fps": farthest point sampling from fps_start; anchors=<k indices>: those points
+        (random sampling: the caller draws them)."""
         lib = load()
         self._lib = lib
         X = _dev(X)
         self.n, self.d = X.shape
         self.eps = float(eps)
         self.betas = [float(b) for b in betas]
-        self.k, self.l = int(k), int(l)
+        self.k = int(k)
         self.prec = _prec(prec)
+        bh, nb = _host_f64(self.betas)
+        h = ctypes.c_void_p()
+        self._h = None
+        if anchors is not None:
+            self.l = 0
+            S = None if isinstance(anchors, str) and anchors == "fps" else _dev(anchors, torch.int64)
+            if S is not None and S.numel() != self.k:
+                raise ValueError("anchors must hold k indices")
+            _chk(lib, lib.krr_build_precond_anchors(_p(X), self.n, self.d, self.eps, bh, nb, _p(S), self.k,
+                                                    int(fps_start), float(tau), self.prec, ctypes.byref(h),
+                                                    _stream()))
+            self._h = h
+            return
+        if l is None:
+            raise ValueError("l (sketch columns) is required unless anchors are given")
+        self.l = int(l)
         if omega is not None:
             omega, r = _dev(omega), 0
         else:
             idx, sign = _dev(idx, torch.int64), _dev(sign)
             r = idx.shape[1]
-        bh, nb = _host_f64(self.betas)
-        h = ctypes.c_void_p()
-        self._h = None
         _chk(lib, lib.krr_build_precond(_p(X), self.n, self.d, self.eps, bh, nb, self.k, self.l, _p(omega),
                                         _p(idx), _p(sign), r, float(tau), self.prec, 1 if keep_sketch else 0,
                                         ctypes.byref(h), _stream()))

@@ -320,7 +320,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   KRR_CHECK_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
   red.dot(r.p, z.p, n, rho, s);
 
+  // Lanczos coefficients of column 0, recorded until its recursive residual first claims convergence:
+  // the true-residual check that follows replaces r by a vector of rounding-error size relative to the
+  // recurrence, after which the coefficients no longer describe a Lanczos process of the operator.
   std::vector<double> lanczos_g, lanczos_b;
+  bool lanczos_open = true;
   // Safeguards: the best iterate by true residual is kept per column.  The residual 2-norm of CG is
   // not monotone (CG minimises the A-norm of the error), so a column is only stopped (KRR_ENOCONV, best
   // iterate returned) when its true residual is not finite or exceeds 1e6 times its best, or when its
@@ -364,12 +368,15 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     tm.collect();
     if (hflags[1]) { breakdown = true; break; }
     std::vector<double> hrec(h.begin(), h.begin() + R);
-    if (act[0]) lanczos_g.push_back(h[R]);
+    if (act[0] && lanczos_open) lanczos_g.push_back(h[R]);
     bool candidate = false;
     for (int c = 0; c < R; ++c) {
       if (!act[c]) continue;
       res.iters[c] = it;
-      if (it >= next_check[c] && std::sqrt(h[c]) / ynorm[c] <= tol) candidate = true;
+      if (it >= next_check[c] && std::sqrt(h[c]) / ynorm[c] <= tol) {
+        candidate = true;
+        if (c == 0) lanczos_open = false;
+      }
     }
     if (progress > 0 && it % progress == 0) {
       double worst = 0;
@@ -428,7 +435,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
     hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, p.p, z.p, beta, active.p, n, R);
     KRR_LAUNCH_CHECK();
-    if (R == 1 || act[0]) {
+    if (act[0] && lanczos_open) {
       double b0;
       KRR_CHECK_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, s));
       KRR_CHECK_HIP(hipStreamSynchronize(s));
@@ -473,9 +480,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   }
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   tm.collect();
-  // Lanczos tridiagonal of column 0 -> extreme eigenvalues (kappa estimate) by bisection-free power:
-  // the tridiagonal is small; use a symmetric QR-free estimate from its Gershgorin-refined bounds
-  // computed with the Sturm-sequence bisection below.
+  // Lanczos tridiagonal of column 0 (rebuilt from the CG step lengths and ratios) -> its smallest and
+  // largest eigenvalues by Sturm-sequence bisection inside the Gershgorin interval.
   {
     const int m = (int)std::min(lanczos_g.size(), lanczos_b.size() + 1);
     if (m >= 2) {
@@ -512,6 +518,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       };
       const double emin = kth(0), emax = kth(m - 1);
       res.st.kappa_est = emin > 0 ? emax / emin : 0.0;
+      res.st.lam_min_est = emin;
+      res.st.lam_max_est = emax;
     }
   }
   int mx = 0;

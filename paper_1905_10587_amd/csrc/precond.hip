@@ -18,6 +18,7 @@
 #include <memory>
 #include <numeric>
 
+#include "anchors.h"
 #include "dense.h"
 #include "kmv.h"
 #include "precond.h"
@@ -296,12 +297,30 @@ static void validate_sketch_inputs(const double* omega, const int64_t* idx, cons
 }
 
 // Sketch into Yt (l x ldy) in the working precision wprec (FP64 or FP32).
+// Algorithm 1 sketch Y = K Omega^T (omega and Y n x l row-major), in column chunks of at most 256
+// (the widest block product).
+void sketch_dense(const double* X, int64_t n, int d, double eps, const double* omega, int l, int prec, double* Y,
+                  hipStream_t s) {
+  constexpr int kChunk = 256;
+  DevBuf<double> Oc(l > kChunk ? (size_t)n * kChunk : 0, s);
+  for (int c0 = 0; c0 < l; c0 += kChunk) {
+    const int rc = std::min(kChunk, l - c0);
+    const double* V = omega;
+    if (l > kChunk) {
+      KRR_CHECK_HIP(hipMemcpy2DAsync(Oc.p, sizeof(double) * rc, omega + c0, sizeof(double) * l, sizeof(double) * rc,
+                                     (size_t)n, hipMemcpyDeviceToDevice, s));
+      V = Oc.p;
+    }
+    kernel_mv_raw(X, n, X, n, d, eps, V, rc, nullptr, 0, prec, Y + c0, l, s);
+  }
+}
+
 static void make_sketch_t(const double* X, int64_t n, int d, double eps, const double* omega, const int64_t* idx,
                           const double* sign, int l, int r, int prec, int wprec, void* Yt, int64_t ldy,
                           double* keepY, hipStream_t s) {
   if (omega) {
     DevBuf<double> Y(n * l, s);
-    kernel_mv_raw(X, n, X, n, d, eps, omega, l, nullptr, 0, prec, Y.p, l, s);
+    sketch_dense(X, n, d, eps, omega, l, prec, Y.p, s);
     transpose_to_t(Y.p, n, l, wprec, Yt, ldy, s);
     if (keepY) KRR_CHECK_HIP(hipMemcpyAsync(keepY, Y.p, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
   } else {
@@ -328,6 +347,8 @@ static void build_core(krr_precond& P, const double* M, std::vector<DevBuf<doubl
     if (Ls) Ls->push_back(std::move(L));
   }
 }
+
+void build_from_anchors(krr_precond& P, const double* X, hipStream_t s);
 
 void build_precond(krr_precond& P, const double* X, const double* omega, const int64_t* idx, const double* sign,
                    int flags, hipStream_t s) {
@@ -358,8 +379,17 @@ void build_precond(krr_precond& P, const double* X, const double* omega, const i
   KRR_CHECK_HIP(hipMemcpyAsync(P.rdiag_host.data(), rdiag.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   P.t_build_ms[1] = ms_since(t0);
+  build_from_anchors(P, X, s);
+  P.t_build_ms[5] = ms_since(t_all);
+}
+
+// Algorithm 3 and the core factors for the anchors in P.S (device) / P.S_host: fills phases 2-4.
+void build_from_anchors(krr_precond& P, const double* X, hipStream_t s) {
+  using clk = std::chrono::steady_clock;
+  const int64_t n = P.n;
+  const int d = P.d, k = P.k;
   // 3. K_SS = U^{-1}, EVD, truncation
-  t0 = clk::now();
+  auto t0 = clk::now();
   DevBuf<double> XS((size_t)k * d, s), Kss((size_t)k * k, s), V((size_t)k * k, s), lam(k, s);
   gather_rows(X, n, d, P.S.p, k, XS.p, s);
   kernel_block_colmajor(XS.p, k, XS.p, k, d, P.eps, Kss.p, k, s);
@@ -411,7 +441,6 @@ void build_precond(krr_precond& P, const double* X, const double* omega, const i
   if (P.prec != KRR_FP64) build_core(P, P.M32.p, P.G32, nullptr, s);
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   P.t_build_ms[4] = ms_since(t0);
-  P.t_build_ms[5] = ms_since(t_all);
 }
 
 }  // namespace krr
@@ -445,7 +474,7 @@ extern "C" int krr_sketch(const double* X, int64_t n, int32_t d, double eps, con
     hipStream_t s = (hipStream_t)stream;
     krr::validate_sketch_inputs(omega, idx, sign, n, l, r, s);
     if (omega) {
-      krr::kernel_mv_raw(X, n, X, n, d, eps, omega, l, nullptr, 0, prec, Y, l, s);
+      krr::sketch_dense(X, n, d, eps, omega, l, prec, Y, s);
     } else {
       const int wprec = prec == KRR_FP64 ? KRR_FP64 : KRR_FP32;
       const int64_t ldy = krr::round_up(n, 256);
@@ -496,6 +525,53 @@ extern "C" int krr_build_precond(const double* X, int64_t n, int32_t d, double e
     P->tau = tau > 0 ? tau : 1e-12;
     P->betas.assign(betas, betas + nbeta);
     krr::build_precond(*P, X, omega, idx, sign, flags, s);
+    *out = P.release();
+    return (int)KRR_OK;
+  });
+}
+
+extern "C" int krr_build_precond_anchors(const double* X, int64_t n, int32_t d, double eps, const double* betas,
+                                         int32_t nbeta, const int64_t* S, int32_t k, int64_t fps_start, double tau,
+                                         int32_t prec, krr_precond** out, void* stream) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(out != nullptr, "out must not be NULL");
+    *out = nullptr;
+    krr::validate_common(n, n, d, eps);
+    krr::validate_prec(prec);
+    KRR_REQUIRE(X && betas, "null pointer argument");
+    KRR_REQUIRE(nbeta >= 1 && nbeta <= 64, "nbeta must be in [1, 64]");
+    for (int i = 0; i < nbeta; ++i) KRR_REQUIRE(betas[i] > 0 && std::isfinite(betas[i]), "beta must be positive and finite");
+    KRR_REQUIRE(k >= 1 && k <= n, "need 1 <= k <= n");
+    KRR_REQUIRE((size_t)k * sizeof(double) <= 160 * 1024, "k too large (at most 20480)");
+    KRR_REQUIRE(S != nullptr || (fps_start >= 0 && fps_start < n), "fps_start must be in [0, n)");
+    hipStream_t s = (hipStream_t)stream;
+    krr::check_finite_device(X, n * (int64_t)d, "X", s);
+    using clk = std::chrono::steady_clock;
+    const auto t_all = clk::now();
+    auto P = std::make_unique<krr_precond>();
+    P->n = n; P->d = d; P->k = k; P->l = 0; P->r = 0; P->eps = eps; P->prec = prec;
+    P->tau = tau > 0 ? tau : 1e-12;
+    P->betas.assign(betas, betas + nbeta);
+    P->S.alloc(k, s);
+    P->S_host.resize(k);
+    P->rdiag_host.assign(k, 0.0);
+    const auto t0 = clk::now();
+    if (S) {
+      KRR_CHECK_HIP(hipMemcpyAsync(P->S_host.data(), S, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+      KRR_CHECK_HIP(hipStreamSynchronize(s));
+      std::vector<int64_t> srt(P->S_host);
+      std::sort(srt.begin(), srt.end());
+      KRR_REQUIRE(srt.front() >= 0 && srt.back() < n, "anchor index out of range");
+      KRR_REQUIRE(std::adjacent_find(srt.begin(), srt.end()) == srt.end(), "anchor indices must be distinct");
+      KRR_CHECK_HIP(hipMemcpyAsync(P->S.p, S, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, s));
+    } else {
+      krr::fps_select(X, n, d, k, fps_start, P->S.p, nullptr, s);
+      KRR_CHECK_HIP(hipMemcpyAsync(P->S_host.data(), P->S.p, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+    }
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    P->t_build_ms[1] = krr::ms_since(t0);
+    krr::build_from_anchors(*P, X, s);
+    P->t_build_ms[5] = krr::ms_since(t_all);
     *out = P.release();
     return (int)KRR_OK;
   });

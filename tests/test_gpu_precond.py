@@ -26,9 +26,10 @@ def _pts(n, d, seed):
 @pytest.mark.gpu
 # mixed: the l sketch columns go through the block MVM (two BF16 parts of K and Omega; measured 3e-6)
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6), ("mixed", 1e-5)])
-def test_sketch_dense_parity(gpu_lib, prec, tol):
+@pytest.mark.parametrize("l", [37, 300])     # 300: two column chunks (256 + 44)
+def test_sketch_dense_parity(gpu_lib, prec, tol, l):
     X = _pts(1300, 3, 1)
-    om = datagen.sketch_dense_omega(1300, 37, seed=2)
+    om = datagen.sketch_dense_omega(1300, l, seed=2)
     ref = op.sketch_dense(X, 0.05, om)
     scale = ok.kernel_matrix(X, X, 0.05) @ np.abs(om)
     Y = gpu_lib.sketch(torch.from_numpy(X), 0.05, omega=torch.from_numpy(om), prec=prec).cpu().numpy()
