@@ -221,7 +221,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fp32", choices=["mixed", "fp32", "small", "block", "adjoint"])
     ap.add_argument("--prec", default=None, help="working precision (default: the workload's)")
     ap.add_argument("--fp64-solve", action="store_true", help="also run the full FP64 solve (minutes)")

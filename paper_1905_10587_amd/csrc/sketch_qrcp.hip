@@ -11,6 +11,11 @@
 // This selects the same pivots as Householder QR with column pivoting in exact arithmetic
 // (the residual norms are those of the trailing columns), without forming R or T (Sec. 2.3:
 // only the permutation is needed).
+#include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
+
+#include <cstdlib>
+
 #include "kmv_kernels.h"
 #include "sketch_qrcp.h"
 
@@ -306,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_qr_normalize(const double* __restrict_
 }
 
 template <typename T>
-static void qrcp_impl(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t* piv, double* rdiag,
+static void qrcp_full(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t* piv, double* rdiag,
                       hipStream_t s) {
   const int64_t nblk = ceil_div(N, (int64_t)kQrBlock);
   // Split the l rows into slabs so that a pass launches about 4096 blocks (at least 16 rows per slab).
@@ -342,11 +347,294 @@ static void qrcp_impl(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t
   }
 }
 
+// ------------------------------------------------------------------ candidate-set pivoting
+// Residual norms never grow, so a norm computed at step j0 is an upper bound at every later step.
+// After a refresh (all norms brought up to date), the T columns with the largest norms become
+// candidates; their norms are kept exact step by step (T dot products per step), the others stay
+// stale.  The best candidate is the true argmax as long as its norm exceeds tau, the largest stale
+// norm outside the set; otherwise (and at least every kQrBatch steps) the norms are refreshed with one
+// pass over Yt that applies all pending directions q_{j0} .. q_{j-1}, and the candidates are chosen
+// again.  The pivots are those of the one-pass-per-step algorithm (up to rounding in the norms).
+constexpr int kQrCand = 1024;    // candidates
+constexpr int kQrBatch = 32;     // pending directions per refresh pass at most
+
+// nrm2[c] -= (q_t^T Yt[:, c])^2 for t = 0 .. b-1 in order (clamped at 0), q_t = QT[:, j0 + t] (QT: l x ldq,
+// row-major, zero beyond the computed columns).  One column per thread; the q values are
+// wave-uniform (scalar loads).  Selected columns (nrm2 < 0) are left as they are.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_qr_refresh(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
+                                                    const double* __restrict__ QT, int ldq, int j0, int b,
+                                                    double* __restrict__ nrm2) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cr = c < N ? c : N - 1;
+  double acc[B];
+#pragma unroll
+  for (int t = 0; t < B; ++t) acc[t] = 0.0;
+  for (int i = 0; i < l; ++i) {
+    const double y = (double)Yt[(int64_t)i * ldy + cr];
+    const double* q = QT + (int64_t)i * ldq + j0;
+#pragma unroll
+    for (int t = 0; t < B; ++t) acc[t] = __builtin_fma(q[t], y, acc[t]);
+  }
+  if (c >= N) return;
+  double v = nrm2[c];
+  if (v < 0.0) return;
+  for (int t = 0; t < b; ++t) {
+    v -= acc[t] * acc[t];
+    v = v > 0.0 ? v : 0.0;
+  }
+  nrm2[c] = v;
+}
+
+// Sort keys: larger norm first, selected columns last (ascending order of the key).
+__global__ void k_qr_keys(const double* __restrict__ nrm2, int64_t N, uint64_t* __restrict__ key,
+                          int64_t* __restrict__ idx) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  const double v = nrm2[c];
+  key[c] = v < 0.0 ? ~0ull : 0x7FFFFFFFFFFFFFFFull - (uint64_t)__double_as_longlong(v);
+  idx[c] = c;
+}
+
+// Candidate t: its column gathered into Yc[t, :] (FP64, row stride l), its norm into cnrm[t]
+// (-1 past the unselected columns); tau = norm of the first column after the candidates (-1 if none).
+template <typename T>
+__global__ __launch_bounds__(256) void k_qr_gather(const T* __restrict__ Yt, int64_t ldy, int l,
+                                                   const int64_t* __restrict__ sidx,
+                                                   const uint64_t* __restrict__ skey, int64_t N, int Tc,
+                                                   const double* __restrict__ nrm2, int64_t* __restrict__ cidx,
+                                                   double* __restrict__ cnrm, double* __restrict__ Yc,
+                                                   double* __restrict__ tau) {
+  const int t = blockIdx.x;
+  const bool live = t < N && skey[t] != ~0ull;
+  const int64_t c = live ? sidx[t] : 0;
+  if (threadIdx.x == 0) {
+    cidx[t] = live ? c : INT64_MAX;
+    cnrm[t] = live ? nrm2[c] : -1.0;
+    if (t == 0) *tau = (Tc < N && skey[Tc] != ~0ull) ? nrm2[sidx[Tc]] : -1.0;
+  }
+  for (int i = threadIdx.x; i < l; i += 256) Yc[(int64_t)t * l + i] = live ? (double)Yt[(int64_t)i * ldy + c] : 0.0;
+}
+
+// Step j's pivot among the candidates.  ok: 1 while the steps of this batch are valid; a pick whose
+// norm does not exceed tau (unless the candidates are fresh) clears it and records the step in *fail,
+// and every later kernel of the batch does nothing.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_qr_cpick(const double* __restrict__ cnrm, const int64_t* __restrict__ cidx,
+                                                   int Tc, const double* __restrict__ tau, int fresh,
+                                                   const T* __restrict__ Yt, int64_t ldy, int l, int j,
+                                                   double* __restrict__ nrm2, int64_t* __restrict__ piv,
+                                                   double* __restrict__ rdiag, double* __restrict__ w,
+                                                   int* __restrict__ ok, int* __restrict__ fail) {
+  __shared__ ArgMax red[1024];
+  __shared__ int go;
+  if (*ok == 0) return;
+  ArgMax best{-2.0, INT64_MAX};
+  for (int t = threadIdx.x; t < Tc; t += 1024) {
+    const double v = cnrm[t];
+    if (v >= 0.0) best = amax(best, ArgMax{v, cidx[t]});
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = amax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const ArgMax b = red[0];
+    go = b.i != INT64_MAX && (fresh || b.v > *tau);
+    if (go) {
+      piv[j] = b.i;
+      rdiag[j] = sqrt(b.v > 0 ? b.v : 0.0);
+      nrm2[b.i] = -1.0;   // selected
+    } else {
+      *ok = 0;
+      *fail = j;
+    }
+  }
+  __syncthreads();
+  if (!go) return;
+  const int64_t p = red[0].i;
+  for (int i = threadIdx.x; i < l; i += 1024) w[i] = (double)Yt[(int64_t)i * ldy + p];
+}
+
+// t[c] = Q[c, :] . w for c < j (one block per c), skipped when the batch is stopped.
+__global__ __launch_bounds__(256) void k_qr_cdots(const double* __restrict__ Q, int l, int j,
+                                                  const double* __restrict__ w, double* __restrict__ t,
+                                                  const int* __restrict__ ok) {
+  __shared__ double red[256];
+  if (*ok == 0) return;
+  const int c = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < l; i += 256) s = __builtin_fma(Q[(int64_t)c * l + i], w[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t[c] = red[0];
+}
+
+// w[i] -= sum_{c<j} t[c] QT[i, c]: one wave per row i reading row i of QT contiguously.
+__global__ __launch_bounds__(256) void k_qr_csub(const double* __restrict__ QT, int ldq, int l, int j,
+                                                 const double* __restrict__ t, double* __restrict__ w,
+                                                 const int* __restrict__ ok) {
+  if (*ok == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= l) return;
+  double s = 0;
+  for (int c = lane; c < j; c += 64) s = __builtin_fma(t[c], QT[(int64_t)i * ldq + c], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) w[i] -= s;
+}
+
+// q_j = w / ||w|| into Q[j, :] and QT[:, j]; then the candidates' norms are downdated with q_j
+// (one wave per candidate; every block recomputes ||w|| from w, block 0 stores q_j).
+__global__ __launch_bounds__(256) void k_qr_cupdate(const double* __restrict__ w, int l, int j,
+                                                    double* __restrict__ Q, double* __restrict__ QT, int ldq,
+                                                    const double* __restrict__ Yc, const int64_t* __restrict__ cidx,
+                                                    int Tc, const int64_t* __restrict__ piv,
+                                                    double* __restrict__ cnrm, const int* __restrict__ ok) {
+  __shared__ double red[256];
+  __shared__ double qs[4096];
+  if (*ok == 0) return;
+  double s = 0;
+  for (int i = threadIdx.x; i < l; i += 256) s = __builtin_fma(w[i], w[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    const double q = w[i] * inv;
+    qs[i] = q;
+    if (blockIdx.x == 0) {
+      Q[(int64_t)j * l + i] = q;
+      QT[(int64_t)i * ldq + j] = q;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= Tc) return;
+  if (cidx[t] == piv[j]) {
+    if (lane == 0) cnrm[t] = -1.0;   // the pivot itself
+    return;
+  }
+  const double v = cnrm[t];
+  if (v < 0.0) return;
+  double r = 0;
+  for (int i = lane; i < l; i += 64) r = __builtin_fma(qs[i], Yc[(int64_t)t * l + i], r);
+  for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+  if (lane == 0) {
+    const double nv = v - r * r;
+    cnrm[t] = nv > 0.0 ? nv : 0.0;
+  }
+}
+
+__global__ void k_qr_reset_ok(int* ok) { *ok = 1; }
+
+template <typename T>
+static void refresh_pass(const T* Yt, int64_t ldy, int64_t N, int l, const double* QT, int ldq, int j0, int b,
+                         double* nrm2, hipStream_t s) {
+  const dim3 g((unsigned)ceil_div(N, 256));
+#define KRR_QRF(B) hipLaunchKernelGGL((k_qr_refresh<T, B>), g, dim3(256), 0, s, Yt, ldy, N, l, QT, ldq, j0, b, nrm2)
+  if (b <= 4) KRR_QRF(4);
+  else if (b <= 8) KRR_QRF(8);
+  else if (b <= 16) KRR_QRF(16);
+  else KRR_QRF(32);
+#undef KRR_QRF
+  KRR_LAUNCH_CHECK();
+}
+
+template <typename T>
+static void qrcp_cand(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t* piv, double* rdiag, hipStream_t s) {
+  const int64_t nblk = ceil_div(N, (int64_t)kQrBlock);
+  const int want = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div((int64_t)4096, nblk)), ceil_div(l, 16));
+  const int slab = (int)ceil_div(l, want);
+  const int nslab = (int)ceil_div(l, slab);
+  const int Tc = (int)std::min<int64_t>(kQrCand, N);
+  const int ldq = k + kQrBatch;   // QT columns past k stay zero (read by the widest refresh form)
+  DevBuf<double> nrm2(N, s), Q((size_t)k * l, s), QT((size_t)l * ldq, s), w(l, s), t(std::max(k, 1), s),
+      part((size_t)nslab * N, s), Yc((size_t)Tc * l, s), cnrm(Tc, s), tau(1, s);
+  DevBuf<ArgMax> am(nblk, s);
+  DevBuf<uint64_t> key(N, s), skey(N, s);
+  DevBuf<int64_t> idx(N, s), sidx(N, s), cidx(Tc, s);
+  DevBuf<int> flags(2, s);   // ok, fail step
+  int* ok = flags.p;
+  int* fail = flags.p + 1;
+  KRR_CHECK_HIP(hipMemsetAsync(QT.p, 0, QT.bytes(), s));
+  size_t tmp_bytes = 0;
+  KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key.p, skey.p, idx.p, sidx.p, (int)N, 0, 64, s));
+  DevBuf<char> tmp(tmp_bytes, s);
+  // initial squared norms
+  const dim3 g2((unsigned)nblk, (unsigned)nslab);
+  hipLaunchKernelGGL((k_qr_slab<T, 1>), g2, dim3(kQrBlock), 0, s, Yt, ldy, N, l, slab, (const double*)nullptr,
+                     part.p);
+  hipLaunchKernelGGL(k_qr_update, dim3((unsigned)nblk), dim3(kQrBlock), 0, s, (const double*)part.p, nslab, N, 1,
+                     nrm2.p, am.p);
+  KRR_LAUNCH_CHECK();
+  int j = 0, j0 = 0;
+  const bool verbose = std::getenv("KRR_QR_VERBOSE") != nullptr;
+  int refreshes = 0;
+  while (j < k) {
+    // refresh: bring every norm up to date with q_{j0} .. q_{j-1}, choose the candidates
+    if (j > j0) refresh_pass(Yt, ldy, N, l, QT.p, ldq, j0, j - j0, nrm2.p, s);
+    j0 = j;
+    ++refreshes;
+    hipLaunchKernelGGL(k_qr_keys, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, (const double*)nrm2.p, N,
+                       key.p, idx.p);
+    KRR_LAUNCH_CHECK();
+    KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, key.p, skey.p, idx.p, sidx.p, (int)N, 0, 64, s));
+    hipLaunchKernelGGL(k_qr_gather<T>, dim3((unsigned)Tc), dim3(256), 0, s, Yt, ldy, l, (const int64_t*)sidx.p,
+                       (const uint64_t*)skey.p, N, Tc, (const double*)nrm2.p, cidx.p, cnrm.p, Yc.p, tau.p);
+    hipLaunchKernelGGL(k_qr_reset_ok, dim3(1), dim3(1), 0, s, ok);
+    KRR_LAUNCH_CHECK();
+    // a batch of steps on the candidates, stopped on the device at the first invalid pick
+    const int jend = std::min(k, j0 + kQrBatch);
+    for (int jj = j0; jj < jend; ++jj) {
+      hipLaunchKernelGGL(k_qr_cpick<T>, dim3(1), dim3(1024), 0, s, (const double*)cnrm.p, (const int64_t*)cidx.p, Tc,
+                         (const double*)tau.p, jj == j0 ? 1 : 0, Yt, ldy, l, jj, nrm2.p, piv, rdiag, w.p, ok,
+                         fail);
+      if (jj > 0) {
+        for (int pass = 0; pass < 2; ++pass) {   // Gram-Schmidt twice
+          hipLaunchKernelGGL(k_qr_cdots, dim3(jj), dim3(256), 0, s, (const double*)Q.p, l, jj, (const double*)w.p,
+                             t.p, (const int*)ok);
+          hipLaunchKernelGGL(k_qr_csub, dim3((unsigned)ceil_div(l, 4)), dim3(256), 0, s, (const double*)QT.p, ldq, l,
+                             jj, (const double*)t.p, w.p, (const int*)ok);
+        }
+      }
+      hipLaunchKernelGGL(k_qr_cupdate, dim3((unsigned)ceil_div(Tc, 4)), dim3(256), 0, s, (const double*)w.p, l, jj,
+                         Q.p, QT.p, ldq, (const double*)Yc.p, (const int64_t*)cidx.p, Tc, (const int64_t*)piv,
+                         cnrm.p, (const int*)ok);
+      KRR_LAUNCH_CHECK();
+    }
+    int hf[2];
+    KRR_CHECK_HIP(hipMemcpyAsync(hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    KRR_REQUIRE(hf[0] || hf[1] > j0, "pivoted QR: no valid pivot on fresh candidates");
+    j = hf[0] ? jend : hf[1];
+  }
+  if (verbose) std::fprintf(stderr, "krr qrcp: %d steps, %d candidate refreshes\n", k, refreshes);
+}
+
 void qrcp_t(const void* Yt, int64_t ldy, int64_t N, int l, int k, int prec, int64_t* piv, double* rdiag,
             hipStream_t s) {
   KRR_REQUIRE(k >= 1 && k <= l && k <= N, "pivoted QR needs 1 <= k <= min(l, n)");
-  if (prec == KRR_FP64) qrcp_impl<double>((const double*)Yt, ldy, N, l, k, piv, rdiag, s);
-  else qrcp_impl<float>((const float*)Yt, ldy, N, l, k, piv, rdiag, s);
+  // KRR_QR_FULL: one pass over Yt per step (also used for l > 4096, beyond the candidate kernels' LDS)
+  const bool full = std::getenv("KRR_QR_FULL") != nullptr || l > 4096;
+  if (prec == KRR_FP64) {
+    if (full) qrcp_full<double>((const double*)Yt, ldy, N, l, k, piv, rdiag, s);
+    else qrcp_cand<double>((const double*)Yt, ldy, N, l, k, piv, rdiag, s);
+  } else {
+    if (full) qrcp_full<float>((const float*)Yt, ldy, N, l, k, piv, rdiag, s);
+    else qrcp_cand<float>((const float*)Yt, ldy, N, l, k, piv, rdiag, s);
+  }
 }
 
 }  // namespace krr

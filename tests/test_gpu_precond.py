@@ -84,6 +84,30 @@ def test_qrcp_valid_greedy_on_sketch(gpu_lib, prec, rtol):
                                atol=1e-12 * forced["rdiag"][0])
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_qrcp_candidates_match_full_pass(gpu_lib, prec, monkeypatch):
+    """The candidate-set pivoting (exact norms for the top candidates, stale upper bounds for the rest,
+    batched refresh passes) against one pass over the sketch per step: same pivots; and valid greedy
+    pivots for the oracle's Householder QR run along them.  30,000 columns, so the candidate set (1024)
+    is a small part and picks fall outside it (refreshes before the batch limit)."""
+    n, l, k = 30_000, 320, 300
+    X = _pts(n, 3, 60)
+    idx, sign = datagen.sketch_sparse_draws(n, l, 8, seed=61)
+    Y = gpu_lib.sketch(torch.from_numpy(X), 0.01, idx=torch.from_numpy(idx), sign=torch.from_numpy(sign),
+                       prec="fp64")
+    monkeypatch.setenv("KRR_QR_VERBOSE", "1")
+    piv_c, rd_c = gpu_lib.qrcp(Y, k, prec=prec)
+    monkeypatch.setenv("KRR_QR_FULL", "1")
+    piv_f, rd_f = gpu_lib.qrcp(Y, k, prec=prec)
+    monkeypatch.delenv("KRR_QR_FULL")
+    piv_c, piv_f = piv_c.cpu().numpy(), piv_f.cpu().numpy()
+    np.testing.assert_array_equal(piv_c, piv_f)
+    np.testing.assert_allclose(rd_c.cpu().numpy(), rd_f.cpu().numpy(), rtol=1e-9)
+    forced = op.qrcp(Y.cpu().numpy().T, k, forced=piv_c)
+    assert np.all(forced["rdiag"] >= forced["maxnorm"] * (1 - (1e-10 if prec == "fp64" else 1e-4)))
+
+
 @pytest.fixture(scope="module")
 def small_build(gpu_lib):
     wl = datagen.make_workload("small")
