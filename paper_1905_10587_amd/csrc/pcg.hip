@@ -131,6 +131,38 @@ __global__ void k_beta(double* __restrict__ rho, const double* __restrict__ rho_
   beta[c] = b;
 }
 
+// Per-iteration status for the host in one store into host-mapped memory:
+// hs = [rr (R) | gamma (R) | beta of the previous iteration (R) | flags (2)].
+__global__ void k_pack_status(const double* __restrict__ rr, const double* __restrict__ gamma,
+                              const double* __restrict__ beta, const int* __restrict__ flags, int R,
+                              double* __restrict__ hs) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < R) {
+    hs[c] = rr[c];
+    hs[R + c] = gamma[c];
+    hs[2 * R + c] = beta[c];
+  }
+  if (c == 0) {
+    hs[3 * R] = (double)flags[0];
+    hs[3 * R + 1] = (double)flags[1];
+  }
+}
+
+// Pinned, device-visible host buffer for k_pack_status (one per thread, grown on demand, kept for the
+// life of the process).
+static double* status_buffer(size_t count) {
+  thread_local double* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (count > cap) {
+    if (buf) KRR_CHECK_HIP(hipHostFree(buf));
+    buf = nullptr;
+    cap = 0;
+    KRR_CHECK_HIP(hipHostMalloc((void**)&buf, count * sizeof(double), hipHostMallocDefault));
+    cap = count;
+  }
+  return buf;
+}
+
 // p = z + beta p (active columns)
 __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ beta,
                            const int* __restrict__ active, int64_t n, int R) {
@@ -324,7 +356,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // the true-residual check that follows replaces r by a vector of rounding-error size relative to the
   // recurrence, after which the coefficients no longer describe a Lanczos process of the operator.
   std::vector<double> lanczos_g, lanczos_b;
-  bool lanczos_open = true;
+  bool lanczos_open = true, pending_b = false;
+  double* hs = status_buffer(3 * (size_t)R + 2);
   // Safeguards: the best iterate by true residual is kept per column.  The residual 2-norm of CG is
   // not monotone (CG minimises the A-norm of the error), so a column is only stopped (KRR_ENOCONV, best
   // iterate returned) when its true residual is not finite or exceeds 1e6 times its best, or when its
@@ -361,12 +394,15 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, p.p, q.p, gamma, n, R);
     red.dot(r.p, nullptr, n, rr, s);
     KRR_LAUNCH_CHECK();
-    KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-    KRR_CHECK_HIP(hipMemcpyAsync(h.data() + R, gamma, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-    KRR_CHECK_HIP(hipMemcpyAsync(hflags, flags.p, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_pack_status, dim3(nb(R)), dim3(256), 0, s, (const double*)rr, (const double*)gamma,
+                       (const double*)beta, (const int*)flags.p, R, hs);
+    KRR_LAUNCH_CHECK();
     KRR_CHECK_HIP(hipStreamSynchronize(s));
     tm.collect();
-    if (hflags[1]) { breakdown = true; break; }
+    std::copy(hs, hs + 2 * (size_t)R, h.begin());
+    if (hs[3 * R + 1] != 0.0) { breakdown = true; break; }
+    if (pending_b) lanczos_b.push_back(hs[2 * R]);   // beta of the previous iteration, column 0
+    pending_b = false;
     std::vector<double> hrec(h.begin(), h.begin() + R);
     if (act[0] && lanczos_open) lanczos_g.push_back(h[R]);
     bool candidate = false;
@@ -435,12 +471,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
     hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, p.p, z.p, beta, active.p, n, R);
     KRR_LAUNCH_CHECK();
-    if (act[0] && lanczos_open) {
-      double b0;
-      KRR_CHECK_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, s));
-      KRR_CHECK_HIP(hipStreamSynchronize(s));
-      lanczos_b.push_back(b0);
-    }
+    pending_b = act[0] && lanczos_open;   // read with the next iteration's status
   }
   // final true residuals for columns still active (maxit or breakdown); stopped columns return their
   // best iterate

@@ -359,29 +359,64 @@ constexpr int kQrCand = 1024;    // candidates
 constexpr int kQrBatch = 32;     // pending directions per refresh pass at most
 
 // nrm2[c] -= (q_t^T Yt[:, c])^2 for t = 0 .. b-1 in order (clamped at 0), q_t = QT[:, j0 + t] (QT: l x ldq,
-// row-major, zero beyond the computed columns).  One column per thread; the q values are
-// wave-uniform (scalar loads).  Selected columns (nrm2 < 0) are left as they are.
+// row-major, zero beyond the computed columns).  A block covers 128 columns with two threads per column,
+// each summing half of the rows (the halves are added in a fixed order); the q values are wave-uniform
+// (scalar loads) and the next group of kQrRows rows is loaded while the current one is multiplied.
+// Selected columns (nrm2 < 0) are left as they are.
+constexpr int kQrRows = 8;
+
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_qr_refresh(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
                                                     const double* __restrict__ QT, int ldq, int j0, int b,
                                                     double* __restrict__ nrm2) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double part[B][128];
+  const int cl = threadIdx.x & 127;
+  const int half = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);   // uniform per wave: row range and q loads too
+  const int64_t c = (int64_t)blockIdx.x * 128 + cl;
   const int64_t cr = c < N ? c : N - 1;
+  const int lh = (l + 1) / 2;
+  const int i0 = half ? lh : 0, i1 = half ? l : lh;
   double acc[B];
 #pragma unroll
   for (int t = 0; t < B; ++t) acc[t] = 0.0;
-  for (int i = 0; i < l; ++i) {
-    const double y = (double)Yt[(int64_t)i * ldy + cr];
-    const double* q = QT + (int64_t)i * ldq + j0;
+  const T* yp = Yt + cr;
+  T ycur[kQrRows];
 #pragma unroll
-    for (int t = 0; t < B; ++t) acc[t] = __builtin_fma(q[t], y, acc[t]);
+  for (int u = 0; u < kQrRows; ++u) ycur[u] = (i0 + u < i1) ? yp[(int64_t)(i0 + u) * ldy] : (T)0;
+  for (int i = i0; i < i1; i += kQrRows) {
+    T ynext[kQrRows];
+#pragma unroll
+    for (int u = 0; u < kQrRows; ++u) {
+      const int in = i + kQrRows + u;
+      ynext[u] = in < i1 ? yp[(int64_t)in * ldy] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kQrRows; ++u) {
+      if (i + u < i1) {
+        const double y = (double)ycur[u];
+        const double* q = QT + (int64_t)(i + u) * ldq + j0;
+#pragma unroll
+        for (int t = 0; t < B; ++t) acc[t] = __builtin_fma(q[t], y, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kQrRows; ++u) ycur[u] = ynext[u];
   }
-  if (c >= N) return;
+  if (half) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) part[t][cl] = acc[t];
+  }
+  __syncthreads();
+  if (half || c >= N) return;
   double v = nrm2[c];
   if (v < 0.0) return;
-  for (int t = 0; t < b; ++t) {
-    v -= acc[t] * acc[t];
-    v = v > 0.0 ? v : 0.0;
+#pragma unroll
+  for (int t = 0; t < B; ++t) {
+    if (t < b) {
+      const double r = acc[t] + part[t][cl];
+      v -= r * r;
+      v = v > 0.0 ? v : 0.0;
+    }
   }
   nrm2[c] = v;
 }
@@ -542,7 +577,7 @@ __global__ void k_qr_reset_ok(int* ok) { *ok = 1; }
 template <typename T>
 static void refresh_pass(const T* Yt, int64_t ldy, int64_t N, int l, const double* QT, int ldq, int j0, int b,
                          double* nrm2, hipStream_t s) {
-  const dim3 g((unsigned)ceil_div(N, 256));
+  const dim3 g((unsigned)ceil_div(N, 128));
 #define KRR_QRF(B) hipLaunchKernelGGL((k_qr_refresh<T, B>), g, dim3(256), 0, s, Yt, ldy, N, l, QT, ldq, j0, b, nrm2)
   if (b <= 4) KRR_QRF(4);
   else if (b <= 8) KRR_QRF(8);
