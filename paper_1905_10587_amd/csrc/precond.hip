@@ -14,6 +14,7 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <memory>
 #include <numeric>
@@ -141,8 +142,9 @@ __global__ __launch_bounds__(256) void k_sym_gemv(const double* __restrict__ G, 
   if (lane == 0) z[i] = s;
 }
 
-// out[i] = (x[i] - sum_c W[i, c] z[c]) / beta; one wave per row, z staged in LDS.
-template <typename TW>
+// out[i] = (x[i] - sum_c W[i, c] z[c]) / beta; a wave takes RW rows at a time (their loads in flight
+// together), lane l sums columns l, l + 64, ... of each row, then a butterfly over the wave; z staged in LDS.
+template <typename TW, int kWzRows>
 __global__ __launch_bounds__(256) void k_w_z(const TW* __restrict__ W, int64_t n, int kept,
                                              const double* __restrict__ z, const double* __restrict__ x, int ldx,
                                              double inv_beta, double* __restrict__ out, int ldo) {
@@ -150,12 +152,27 @@ __global__ __launch_bounds__(256) void k_w_z(const TW* __restrict__ W, int64_t n
   for (int c = threadIdx.x; c < kept; c += 256) zs[c] = z[c];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
-    double s = 0;
-    const TW* wr = W + i * kept;
-    for (int c = lane; c < kept; c += 64) s = __builtin_fma((double)wr[c], zs[c], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) out[i * ldo] = (x[i * ldx] - s) * inv_beta;
+  const int64_t stride = (int64_t)gridDim.x * 4 * kWzRows;
+  for (int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kWzRows; i0 < n; i0 += stride) {
+    double sum[kWzRows];
+    const TW* wr[kWzRows];
+#pragma unroll
+    for (int r = 0; r < kWzRows; ++r) {
+      sum[r] = 0.0;
+      wr[r] = W + (i0 + r < n ? i0 + r : n - 1) * kept;
+    }
+#pragma unroll 4
+    for (int c = lane; c < kept; c += 64) {
+      const double zc = zs[c];
+#pragma unroll
+      for (int r = 0; r < kWzRows; ++r) sum[r] = __builtin_fma((double)wr[r][c], zc, sum[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kWzRows; ++r)
+      for (int o = 32; o > 0; o >>= 1) sum[r] += __shfl_xor(sum[r], o);
+#pragma unroll
+    for (int r = 0; r < kWzRows; ++r)
+      if (lane == r && i0 + r < n) out[(i0 + r) * ldo] = (x[(i0 + r) * ldx] - sum[r]) * inv_beta;
   }
 }
 
@@ -216,13 +233,14 @@ void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bid
       hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, 1, partial.p);
     hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)kept), dim3(256), 0, s, partial.p, nb, kept, t.p);
     hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t.p, z.p);
-    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 4), 8192);
+    // two rows per wave and at most 2048 blocks (measured best among 1, 2, 4 rows and 1024-8192 blocks)
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 8), 2048);
     const size_t lds = (size_t)kept * sizeof(double);
     if (use32)
-      hipLaunchKernelGGL(k_w_z<float>, dim3(g), dim3(256), lds, s, P.W32.p, n, kept, z.p, x, 1,
+      hipLaunchKernelGGL((k_w_z<float, 2>), dim3(g), dim3(256), lds, s, P.W32.p, n, kept, z.p, x, 1,
                          1.0 / P.betas[b], out, 1);
     else
-      hipLaunchKernelGGL(k_w_z<double>, dim3(g), dim3(256), lds, s, P.W64.p, n, kept, z.p, x, 1,
+      hipLaunchKernelGGL((k_w_z<double, 2>), dim3(g), dim3(256), lds, s, P.W64.p, n, kept, z.p, x, 1,
                          1.0 / P.betas[b], out, 1);
     KRR_LAUNCH_CHECK();
     return;
