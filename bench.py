@@ -31,13 +31,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "PCG solve s to rel-res 1e-6 + kernel-MVM Gpairs/s; mixed vs FP64, same GPU"
-# VALU bound of the kernel MVM on MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s.
+# VALU-only bound of the kernel MVM on MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s.
 # Direct form: one pair needs one v_exp_f32 (half rate: 2 slots) and one FMA (1 slot) -> 13.1e12 pairs/s.
 # Symmetric form (square products): one exp and two FMAs (row and column sums) serve two pairs of the
 # product -> 2 slots per pair -> 19.7e12 pairs/s.  Pairs are the product's n^2 (the algorithmic units).
 SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_PAIRS = SLOTS / 3.0
 PEAK_PAIRS_SYM = SLOTS / 2.0
+# The mixed forms also issue NCH MFMAs (v_mfma_f32_16x16x32_bf16, 16 cycles each at full rate) per 256
+# evaluated pairs, and on this part MFMA and VALU work do not overlap (measured with a register-only probe
+# and with the kernel's own counters), so the bound is VALU cycles + MFMA cycles per 256 evaluated pairs:
+# direct 48 + 16 NCH, symmetric 64 + 16 NCH (symmetric: two product pairs per evaluated pair).
+SIMD_CYCLES = 256 * 4 * 2.4e9
+
+
+def mixed_chunks(d):
+    need = -(-(6 * d + 6) // 32)
+    return next(c for c in (1, 2, 3, 4, 6, 8, 13, 25) if c >= need)
+
+
+def peak_mixed(d, sym):
+    nch = mixed_chunks(d)
+    return (2.0 if sym else 1.0) * 256 * SIMD_CYCLES / ((64 if sym else 48) + 16 * nch)
 # Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
 # for roofline.traffic only while these hash to the value recorded with it.
 KERNEL_SOURCES = ("paper_1905_10587_amd/csrc/kmv_kernels.h", "paper_1905_10587_amd/csrc/kmv_mixed.hip",
@@ -335,7 +350,8 @@ def main(argv=None):
     avg_mvm_ms = st["t_mvm_kernel_ms"] / max(st["n_mvm"], 1)
     achieved = float(n) * n / (avg_mvm_ms * 1e-3)
     variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec == "mixed" else (None, False)
-    peak = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
+    peak_valu = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
+    peak = peak_mixed(wl.d, sym) if prec == "mixed" else peak_valu
     traffic = stored_traffic(wl.name) if prec == "mixed" and R == 1 else None
     block_mvm = prec == "mixed" and R > 1
     if block_mvm:
@@ -380,9 +396,12 @@ def main(argv=None):
         "roofline": roofline if block_mvm else {"bound": "alu",
                      "kernel": (f"{prec} MVM, variant {variant}, " if variant is not None else f"{prec} MVM, ")
                                + ("symmetric form (exp + 2 FMA per evaluated pair)" if sym
-                                  else "direct form (exp + FMA per pair)") + f", d={wl.d}",
+                                  else "direct form (exp + FMA per pair)")
+                               + (f" + {mixed_chunks(wl.d)} MFMA per 256 evaluated pairs, serialized with the VALU"
+                                  if prec == "mixed" else "") + f", d={wl.d}",
                      "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
                      "unit": "Tpairs/s", "frac": round(achieved / peak, 3),
+                     "peak_valu_only": round(peak_valu / 1e12, 2), "frac_valu_only": round(achieved / peak_valu, 3),
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
                      "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]},
     }
