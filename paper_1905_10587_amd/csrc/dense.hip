@@ -155,16 +155,39 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
   if ((int64_t)Q * W >= k && r != 0) return;
   auto gcol = [&](int lc) { return lc < W ? P * W + lc : Q * W + (lc - W); };
   const int ks = k | 1;
-  // a thread moves one row of the 2W columns at a time, so its 2W loads are in flight together
-  for (int t = tid; t < k; t += 256) {
-    double row[C2];
+  // Rows per thread: at most RMAX (k <= 256 RMAX, which the host guarantees for each W).  All of a
+  // thread's A loads are issued before the first LDS store; its V rows are loaded into registers right
+  // after, so their latency is hidden behind the Gram matrix and the rotations.
+  constexpr int RMAX = W == 8 ? 5 : 9;
+  {
+    double row[RMAX][C2];
+#pragma unroll
+    for (int u = 0; u < RMAX; ++u) {
+      const int t = tid + 256 * u;
+#pragma unroll
+      for (int lc = 0; lc < C2; ++lc) {
+        const int g = gcol(lc);
+        row[u][lc] = (t < k && g < k) ? A[(int64_t)g * k + t] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RMAX; ++u) {
+      const int t = tid + 256 * u;
+      if (t < k) {
+#pragma unroll
+        for (int lc = 0; lc < C2; ++lc) sa[lc * ks + t] = row[u][lc];
+      }
+    }
+  }
+  double vpre[RMAX][C2];
+#pragma unroll
+  for (int u = 0; u < RMAX; ++u) {
+    const int t = tid + 256 * u;
 #pragma unroll
     for (int lc = 0; lc < C2; ++lc) {
       const int g = gcol(lc);
-      row[lc] = g < k ? A[(int64_t)g * k + t] : 0.0;
+      vpre[u][lc] = (t < k && g < k) ? V[(int64_t)g * k + t] : 0.0;
     }
-#pragma unroll
-    for (int lc = 0; lc < C2; ++lc) sa[lc * ks + t] = row[lc];
   }
   __syncthreads();
   // fresh Gram G = S^T S: lane (row group, 4 x 4 block) accumulates its block over the rows of its group,
@@ -278,15 +301,14 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
       __syncthreads();
     }
   }
-  // A <- S J, V <- V J on the 2W columns, one row per thread at a time
-  for (int t = tid; t < k; t += 256) {
-    double so[C2], vo[C2];
+  // A <- S J, V <- V J on the 2W columns, one row per thread at a time (V from the prefetched rows)
 #pragma unroll
-    for (int m = 0; m < C2; ++m) {
-      const int g = gcol(m);
-      so[m] = sa[m * ks + t];
-      vo[m] = g < k ? V[(int64_t)g * k + t] : 0.0;
-    }
+  for (int u = 0; u < RMAX; ++u) {
+    const int t = tid + 256 * u;
+    if (t >= k) break;
+    double so[C2];
+#pragma unroll
+    for (int m = 0; m < C2; ++m) so[m] = sa[m * ks + t];
 #pragma unroll 1
     for (int lc = 0; lc < C2; ++lc) {   // J is read from LDS here (not hoisted into registers)
       const int g = gcol(lc);
@@ -295,7 +317,7 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
 #pragma unroll
       for (int m = 0; m < C2; ++m) {
         xa = __builtin_fma(so[m], J[m][lc], xa);
-        xv = __builtin_fma(vo[m], J[m][lc], xv);
+        xv = __builtin_fma(vpre[u][m], J[m][lc], xv);
       }
       A[(int64_t)g * k + t] = xa;
       V[(int64_t)g * k + t] = xv;
