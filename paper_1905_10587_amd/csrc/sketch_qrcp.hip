@@ -359,61 +359,77 @@ constexpr int kQrCand = 1024;    // candidates
 constexpr int kQrBatch = 32;     // pending directions per refresh pass at most
 
 // nrm2[c] -= (q_t^T Yt[:, c])^2 for t = 0 .. b-1 in order (clamped at 0), q_t = QT[:, j0 + t] (QT: l x ldq,
-// row-major, zero beyond the computed columns).  A block covers 128 columns with two threads per column,
-// each summing half of the rows (the halves are added in a fixed order); the q values are wave-uniform
-// (scalar loads) and the next group of kQrRows rows is loaded while the current one is multiplied.
+// row-major, zero beyond the computed columns).  A block covers 64 columns; its four waves each sum a
+// quarter of the rows (lane = column) and the quarters are added in a fixed order through LDS.  Each wave
+// stages its q rows through its own LDS buffer in chunks of kQrChunk rows (coalesced loads, the next chunk
+// in registers while the current one is used; broadcast reads), and loads its Yt rows one chunk ahead.
 // Selected columns (nrm2 < 0) are left as they are.
-constexpr int kQrRows = 8;
+constexpr int kQrChunk = 16;
 
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_qr_refresh(const T* __restrict__ Yt, int64_t ldy, int64_t N, int l,
                                                     const double* __restrict__ QT, int ldq, int j0, int b,
                                                     double* __restrict__ nrm2) {
-  __shared__ double part[B][128];
-  const int cl = threadIdx.x & 127;
-  const int half = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);   // uniform per wave: row range and q loads too
-  const int64_t c = (int64_t)blockIdx.x * 128 + cl;
+  constexpr int QPL = kQrChunk * B / 64;   // q values per lane per chunk
+  static_assert(QPL >= 1 && (kQrChunk * B) % 64 == 0, "chunk must fill the wave");
+  __shared__ double qs[4][kQrChunk * B];
+  __shared__ double part[3][B][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   const int64_t cr = c < N ? c : N - 1;
-  const int lh = (l + 1) / 2;
-  const int i0 = half ? lh : 0, i1 = half ? l : lh;
+  const int lq = (l + 3) / 4;
+  const int i0 = wave * lq < l ? wave * lq : l;
+  const int i1 = i0 + lq < l ? i0 + lq : l;
+  double* qw = qs[wave];
   double acc[B];
 #pragma unroll
   for (int t = 0; t < B; ++t) acc[t] = 0.0;
   const T* yp = Yt + cr;
-  T ycur[kQrRows];
+  // chunk 0 into registers
+  double qn[QPL];
+  T yn[kQrChunk];
 #pragma unroll
-  for (int u = 0; u < kQrRows; ++u) ycur[u] = (i0 + u < i1) ? yp[(int64_t)(i0 + u) * ldy] : (T)0;
-  for (int i = i0; i < i1; i += kQrRows) {
-    T ynext[kQrRows];
-#pragma unroll
-    for (int u = 0; u < kQrRows; ++u) {
-      const int in = i + kQrRows + u;
-      ynext[u] = in < i1 ? yp[(int64_t)in * ldy] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < kQrRows; ++u) {
-      if (i + u < i1) {
-        const double y = (double)ycur[u];
-        const double* q = QT + (int64_t)(i + u) * ldq + j0;
-#pragma unroll
-        for (int t = 0; t < B; ++t) acc[t] = __builtin_fma(q[t], y, acc[t]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kQrRows; ++u) ycur[u] = ynext[u];
+  for (int u = 0; u < QPL; ++u) {
+    const int e = lane + 64 * u, r = e / B, t = e % B;
+    qn[u] = i0 + r < i1 ? QT[(int64_t)(i0 + r) * ldq + j0 + t] : 0.0;
   }
-  if (half) {
 #pragma unroll
-    for (int t = 0; t < B; ++t) part[t][cl] = acc[t];
+  for (int u = 0; u < kQrChunk; ++u) yn[u] = i0 + u < i1 ? yp[(int64_t)(i0 + u) * ldy] : (T)0;
+  for (int i = i0; i < i1; i += kQrChunk) {
+    // current chunk: q into LDS, y into registers; then start loading the next chunk
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) qw[lane + 64 * u] = qn[u];
+    T ycur[kQrChunk];
+#pragma unroll
+    for (int u = 0; u < kQrChunk; ++u) ycur[u] = yn[u];
+    const int inx = i + kQrChunk;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+      const int e = lane + 64 * u, r = e / B, t = e % B;
+      qn[u] = inx + r < i1 ? QT[(int64_t)(inx + r) * ldq + j0 + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kQrChunk; ++u) yn[u] = inx + u < i1 ? yp[(int64_t)(inx + u) * ldy] : (T)0;
+#pragma unroll
+    for (int u = 0; u < kQrChunk; ++u) {
+      const double y = (double)ycur[u];   // rows past i1 hold zeros in both y and q
+#pragma unroll
+      for (int t = 0; t < B; ++t) acc[t] = __builtin_fma(qw[u * B + t], y, acc[t]);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) part[wave - 1][t][lane] = acc[t];
   }
   __syncthreads();
-  if (half || c >= N) return;
+  if (wave > 0 || c >= N) return;
   double v = nrm2[c];
   if (v < 0.0) return;
 #pragma unroll
   for (int t = 0; t < B; ++t) {
     if (t < b) {
-      const double r = acc[t] + part[t][cl];
+      const double r = ((acc[t] + part[0][t][lane]) + part[1][t][lane]) + part[2][t][lane];
       v -= r * r;
       v = v > 0.0 ? v : 0.0;
     }
@@ -577,7 +593,7 @@ __global__ void k_qr_reset_ok(int* ok) { *ok = 1; }
 template <typename T>
 static void refresh_pass(const T* Yt, int64_t ldy, int64_t N, int l, const double* QT, int ldq, int j0, int b,
                          double* nrm2, hipStream_t s) {
-  const dim3 g((unsigned)ceil_div(N, 128));
+  const dim3 g((unsigned)ceil_div(N, 64));
 #define KRR_QRF(B) hipLaunchKernelGGL((k_qr_refresh<T, B>), g, dim3(256), 0, s, Yt, ldy, N, l, QT, ldq, j0, b, nrm2)
   if (b <= 4) KRR_QRF(4);
   else if (b <= 8) KRR_QRF(8);
