@@ -677,8 +677,9 @@ static void qrcp_cand(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t
 void qrcp_t(const void* Yt, int64_t ldy, int64_t N, int l, int k, int prec, int64_t* piv, double* rdiag,
             hipStream_t s) {
   KRR_REQUIRE(k >= 1 && k <= l && k <= N, "pivoted QR needs 1 <= k <= min(l, n)");
-  // KRR_QR_FULL: one pass over Yt per step (also used for l > 4096, beyond the candidate kernels' LDS)
-  const bool full = std::getenv("KRR_QR_FULL") != nullptr || l > 4096;
+  // KRR_QR_FULL: one pass over Yt per step (also used for l > 4096, beyond the candidate kernels' LDS,
+  // and for more than 2^31 - 1 columns)
+  const bool full = std::getenv("KRR_QR_FULL") != nullptr || l > 4096 || N > INT32_MAX;   // sort counts are int
   if (prec == KRR_FP64) {
     if (full) qrcp_full<double>((const double*)Yt, ldy, N, l, k, piv, rdiag, s);
     else qrcp_cand<double>((const double*)Yt, ldy, N, l, k, piv, rdiag, s);
