@@ -53,6 +53,16 @@ def mixed_chunks(d):
 def peak_mixed(d, sym):
     nch = mixed_chunks(d)
     return (2.0 if sym else 1.0) * 256 * SIMD_CYCLES / ((64 if sym else 48) + 16 * nch)
+
+
+def peak_direct(d, prec, sym):
+    """VALU bound of the FP32 / FP64 forms (one lane-slot per VALU instruction, exp2 in FP32 counted as two):
+    FP32 per pair d subtractions + d FMAs + exp + one FMA; FP64 per pair d subtractions + d FMAs + a
+    16-instruction exp2 (reduction, degree-11 polynomial, scaling) + one FMA, + one more FMA in the symmetric
+    form, whose evaluated pair serves two pairs of the product."""
+    if prec == "fp32":
+        return SLOTS / (2 * d + 3)
+    return (2.0 * SLOTS / (2 * d + 18)) if sym else SLOTS / (2 * d + 17)
 # Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
 # for roofline.traffic only while these hash to the value recorded with it.
 KERNEL_SOURCES = ("paper_1905_10587_amd/csrc/kmv_kernels.h", "paper_1905_10587_amd/csrc/kmv_mixed.hip",
@@ -349,9 +359,12 @@ def main(argv=None):
     # roofline: the main MVM kernel alone (HIP events around its launch, on the solver's stream)
     avg_mvm_ms = st["t_mvm_kernel_ms"] / max(st["n_mvm"], 1)
     achieved = float(n) * n / (avg_mvm_ms * 1e-3)
-    variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec == "mixed" else (None, False)
-    peak_valu = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
-    peak = peak_mixed(wl.d, sym) if prec == "mixed" else peak_valu
+    variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec in ("mixed", "fp64") else (None, False)
+    if prec == "mixed":
+        peak_valu = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
+        peak = peak_mixed(wl.d, sym)
+    else:
+        peak_valu = peak = peak_direct(wl.d, prec, sym)
     traffic = stored_traffic(wl.name) if prec == "mixed" and R == 1 else None
     block_mvm = prec == "mixed" and R > 1
     if block_mvm:
@@ -395,8 +408,10 @@ def main(argv=None):
         "mvm_gpairs_s": round(achieved / 1e9, 1),
         "roofline": roofline if block_mvm else {"bound": "alu",
                      "kernel": (f"{prec} MVM, variant {variant}, " if variant is not None else f"{prec} MVM, ")
-                               + ("symmetric form (exp + 2 FMA per evaluated pair)" if sym
-                                  else "direct form (exp + FMA per pair)")
+                               + (("symmetric form (exp + 2 FMA per evaluated pair)" if sym
+                                   else "direct form (exp + FMA per pair)") if prec == "mixed" else
+                                  (f"{'symmetric' if sym else 'direct'} form, {prec} VALU bound "
+                                   f"({'2d+18 per evaluated pair' if sym else '2d+17 per pair' if prec == 'fp64' else '2d+3 per pair'})"))
                                + (f" + {mixed_chunks(wl.d)} MFMA per 256 evaluated pairs, serialized with the VALU"
                                   if prec == "mixed" else "") + f", d={wl.d}",
                      "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
