@@ -1001,13 +1001,10 @@ namespace krr {
 // target fragments of 16 and the block covers 16 * NRC right-hand sides (grid.z walks the rest).
 // V is staged as BF16 parts in groups of four sources: V4[((j/4) * Rp + r) * 4 + j%4].
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint16_t bf16_bits_rn(float f) {
-  uint32_t b = __float_as_uint(f);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return (uint16_t)(b >> 16);
-}
-__device__ __forceinline__ float bf16_bits_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
 
 template <int NCH, int NT, int NRC, int NS>
 __global__ __launch_bounds__(256) void k_kmv_block(const uint4* __restrict__ A, const uint4* __restrict__ B,
@@ -1056,18 +1053,14 @@ __global__ __launch_bounds__(256) void k_kmv_block(const uint4* __restrict__ A, 
         f32x4 q = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sf[ch], tg[t][ch], q, 0, 0, 0);
-        uint16_t hb[4], mb[4], lb[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 4; ++e) {   // round-to-nearest-even splits (v_cvt_pk_bf16_f32, two per instruction)
           const float p = __builtin_amdgcn_exp2f(q[e]);
-          hb[e] = bf16_bits_rn(p);
-          const float r1 = p - bf16_bits_to_f(hb[e]);
-          mb[e] = bf16_bits_rn(r1);
-          if (NS == 6) lb[e] = bf16_bits_rn(r1 - bf16_bits_to_f(mb[e]));
+          ph[t][e] = (__bf16)p;
+          const float r1 = p - (float)ph[t][e];
+          pm[t][e] = (__bf16)r1;
+          if (NS == 6) pl[t][e] = (__bf16)(r1 - (float)pm[t][e]);
         }
-        ph[t] = __builtin_bit_cast(bf16x4, make_ushort4(hb[0], hb[1], hb[2], hb[3]));
-        pm[t] = __builtin_bit_cast(bf16x4, make_ushort4(mb[0], mb[1], mb[2], mb[3]));
-        if (NS == 6) pl[t] = __builtin_bit_cast(bf16x4, make_ushort4(lb[0], lb[1], lb[2], lb[3]));
       }
       const int64_t vg = (j >> 2) + kq;   // group of four sources
 #pragma unroll
@@ -1115,10 +1108,6 @@ __global__ __launch_bounds__(256) void k_kmv_block(const uint4* __restrict__ A, 
 
 namespace krr {
 
-__device__ __forceinline__ uint4 pack8(const uint16_t* v) {
-  return uint4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
-               (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
-}
 
 // Block MVM, K = 32 form: the K.V contraction uses v_mfma_f32_16x16x32_bf16 on 32 sources at a time.
 // Two 16-source cross-term tiles give each lane 8 exp'd values (sources j+4g+e and j+16+4g+e,
@@ -1162,10 +1151,11 @@ __global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A
       for (int c = 0; c < NRC; ++c) a32[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int64_t j = j0; j < j0 + 256; j += 32) {
       bf16x8 sa[NCH], sb[NCH];
+      const uint4* bp = B + (j + r16) * KV + kq;   // one address per step, constant offsets after it
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
-        sa[ch] = __builtin_bit_cast(bf16x8, B[(j + r16) * KV + ch * 4 + kq]);
-        sb[ch] = __builtin_bit_cast(bf16x8, B[(j + 16 + r16) * KV + ch * 4 + kq]);
+        sa[ch] = __builtin_bit_cast(bf16x8, bp[ch * 4]);
+        sb[ch] = __builtin_bit_cast(bf16x8, bp[16 * KV + ch * 4]);
       }
       bf16x8 ph[NT], pm[NT], pl[NT];
 #pragma unroll
@@ -1176,25 +1166,30 @@ __global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A
           qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[ch], tg[t][ch], qa, 0, 0, 0);
           qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sb[ch], tg[t][ch], qb, 0, 0, 0);
         }
-        uint16_t hb[8], mb[8], lb[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float p = __builtin_amdgcn_exp2f(e < 4 ? qa[e] : qb[e - 4]);
-          hb[e] = bf16_bits_rn(p);
-          const float r1 = p - bf16_bits_to_f(hb[e]);
-          mb[e] = bf16_bits_rn(r1);
-          if (NS == 6) lb[e] = bf16_bits_rn(r1 - bf16_bits_to_f(mb[e]));
+        for (int e = 0; e < 8; e += 2) {   // round-to-nearest-even splits, two values per v_cvt_pk_bf16_f32
+          const f32x2 p = {__builtin_amdgcn_exp2f(e < 4 ? qa[e] : qb[e - 4]),
+                           __builtin_amdgcn_exp2f(e < 4 ? qa[e + 1] : qb[e - 3])};
+          const bf16x2 h = __builtin_convertvector(p, bf16x2);
+          const f32x2 r1 = p - __builtin_convertvector(h, f32x2);
+          const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+          ph[t][e] = h[0]; ph[t][e + 1] = h[1];
+          pm[t][e] = m[0]; pm[t][e + 1] = m[1];
+          if (NS == 6) {
+            const bf16x2 lo = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+            pl[t][e] = lo[0]; pl[t][e + 1] = lo[1];
+          }
         }
-        ph[t] = __builtin_bit_cast(bf16x8, pack8(hb));
-        pm[t] = __builtin_bit_cast(bf16x8, pack8(mb));
-        if (NS == 6) pl[t] = __builtin_bit_cast(bf16x8, pack8(lb));
       }
-      const int64_t ga = (j >> 2) + kq, gb = ga + 4;   // the lane's two groups of four sources
+      // the lane's two groups of four sources, (j/4 + kq) and four groups further
+      const int64_t ga = (j >> 2) + kq;
+      const uint2* vha = Vh + ga * Rp + rbase + r16;
+      const uint2* vma = Vm + ga * Rp + rbase + r16;
+      const int64_t g4 = 4 * (int64_t)Rp;
 #pragma unroll
       for (int c = 0; c < NRC; ++c) {
-        const int col = rbase + 16 * c + r16;
-        const uint2 h0 = Vh[ga * Rp + col], h1 = Vh[gb * Rp + col];
-        const uint2 m0 = Vm[ga * Rp + col], m1 = Vm[gb * Rp + col];
+        const uint2 h0 = vha[16 * c], h1 = vha[g4 + 16 * c];
+        const uint2 m0 = vma[16 * c], m1 = vma[g4 + 16 * c];
         const bf16x8 vh = __builtin_bit_cast(bf16x8, uint4{h0.x, h0.y, h1.x, h1.y});
         const bf16x8 vm = __builtin_bit_cast(bf16x8, uint4{m0.x, m0.y, m1.x, m1.y});
 #pragma unroll
@@ -1204,7 +1199,8 @@ __global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A
           a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm[t], vh, a32[t][c], 0, 0, 0);
         }
         if (NS == 6) {
-          const uint2 l0 = Vl[ga * Rp + col], l1 = Vl[gb * Rp + col];
+          const uint2* vla = Vl + ga * Rp + rbase + r16;
+          const uint2 l0 = vla[16 * c], l1 = vla[g4 + 16 * c];
           const bf16x8 vl = __builtin_bit_cast(bf16x8, uint4{l0.x, l0.y, l1.x, l1.y});
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
