@@ -297,7 +297,7 @@ const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 }  // namespace
 
 int kmv_num_variants(int prec, int R) {
-  if (rclass(prec, R) == 3) return 12;
+  if (rclass(prec, R) == 3) return 13;   // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
   // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
   // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2)
@@ -310,8 +310,15 @@ bool kmv_uses_block(int prec, int d, int R, int deriv) {
 }
 
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square) {
-  // block MVM: K = 32 contraction, 4 target fragments x 2 column groups (fastest at n = 5e5, R = 128)
-  if (rclass(prec, R) == 3) return prec == KRR_MIXED ? 7 : 0;
+  // block MVM (measured at n = 5e5, d = 6): split-BF16 with two parts runs K = 32 contractions over
+  // 4 target fragments x 2 column groups (variant 7; the shared-tile form only ties it at R = 128); with
+  // three parts the exp/split work weighs more and the shared-tile form is 1.26x faster at R = 128 when at
+  // least 7/8 of its waves hold columns, else variant 7 (1.36x faster than variant 0)
+  if (rclass(prec, R) == 3) {
+    if (prec == KRR_MIXED) return 7;
+    const int rb = (int)round_up(R, 32);
+    return R >= 128 && 8 * rb >= 7 * 128 * (int)ceil_div(rb, 128) ? 12 : 7;
+  }
   if (prec == KRR_MIXED) {
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
@@ -437,18 +444,19 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int D = T.dpad;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
-  bool k32 = false;
+  bool k32 = false, shared = false;
   if (block) {
-    const int vb = variant % 6;
-    k32 = variant >= 6 && variant < 12;
+    shared = variant == 12;
+    const int vb = shared ? 1 : variant % 6;
+    k32 = variant >= 6;
     int nrc_max = 1;
     while (nrc_max * 2 <= ceil_div(R, 16)) nrc_max *= 2;
     NT = kBlockNT[vb];
     NRC = std::min(kBlockNRC[vb], nrc_max);
-    stage_vectors_block(V, Vraw, S.n, S.npad, R, 16 * NRC, prec == KRR_MIXED ? 2 : 3, s);
+    stage_vectors_block(V, Vraw, S.n, S.npad, R, shared ? 32 : 16 * NRC, prec == KRR_MIXED ? 2 : 3, s);
     Rpart = V.Rb;
-    rows = 64 * NT;
-    gz = V.Rb / (16 * NRC);
+    rows = shared ? 64 : 64 * NT;
+    gz = shared ? (int)ceil_div(V.Rb, 128) : V.Rb / (16 * NRC);   // shared form: 128 columns per block
   } else if (prec == KRR_MIXED) {
     const int nch = T.ka / 32;
     int var = variant;
@@ -491,6 +499,9 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   DevBuf<double> own;
   DevBuf<double>& part = ws ? *ws : own;
   auto run = [&](const KmvGrid& g) -> bool {
+    if (block && shared)
+      return launch_kmv_block_shared(T.ka / 32, prec == KRR_MIXED ? 3 : 6, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
+                                     prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
     if (block)
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);

@@ -41,5 +41,8 @@ bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, 
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,
                       const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part,
                       hipStream_t s);
+// Shared-tile block MVM: 64 targets x 128 right-hand sides per block (V staged with a multiple of 128 columns).
+bool launch_kmv_block_shared(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+                             const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
 
 }  // namespace krr

@@ -1229,4 +1229,146 @@ __global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A
     }
 }
 
+
+// Block MVM, shared-tile form: a block covers 64 targets (four fragments of 16) and 128 right-hand sides
+// (grid.z walks the rest); wave w evaluates the cross term and exp2 of fragment w only, splits it into BF16
+// parts and stores them in LDS in the A-operand layout of the K.V MFMA, and after one barrier every wave
+// contracts all four fragments with its own 32 right-hand sides.  The columns are padded to a multiple of
+// 32 only: a wave whose 32 columns lie beyond the padded count still evaluates its fragment for the others
+// but loads, contracts and stores nothing.  The exp/split work is done once per
+// block instead of once per 32-column group.  Accumulation order per (fragment, column group) is that of
+// k_kmv_block32<NCH, 4, 2, NS>.
+template <int NCH, int NS>
+__global__ __launch_bounds__(256) void k_kmv_block32s(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                      const uint2* __restrict__ Vh, const uint2* __restrict__ Vm,
+                                                      const uint2* __restrict__ Vl, int Rp, int64_t src_len,
+                                                      int64_t n_src, double* __restrict__ part, int64_t mpad,
+                                                      int Rout) {
+  constexpr int KV = NCH * 4;
+  constexpr int NT = 4, NRC = 2, NP = NS == 6 ? 3 : 2;
+  __shared__ uint4 ps[2][NT][NP][64];   // exp'd fragments, double buffered: [step parity][fragment][part][lane]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * (16 * NT);
+  const int rbase = blockIdx.z * 128 + wave * 16 * NRC;
+  const bool live = rbase < Rp;   // wave-uniform: Rp is a multiple of 32
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+
+  bf16x8 tg[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) tg[ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * wave + r16) * KV + ch * 4 + kq]);
+
+  double acc[NT][NRC][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < NRC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][c][e] = 0.0;
+
+  int buf = 0;
+  for (int64_t j0 = jb; j0 < je; j0 += 256) {
+    f32x4 a32[NT][NRC];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) a32[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t j = j0; j < j0 + 256; j += 32) {
+      // this wave's V values for the step, loaded first so that they arrive while the tile is computed
+      const int64_t ga = (j >> 2) + kq;
+      const int64_t g4 = 4 * (int64_t)Rp;
+      bf16x8 vh[NRC], vm[NRC], vl[NRC];
+      if (live) {
+        const uint2* vha = Vh + ga * Rp + rbase + r16;
+        const uint2* vma = Vm + ga * Rp + rbase + r16;
+#pragma unroll
+        for (int c = 0; c < NRC; ++c) {
+          const uint2 h0 = vha[16 * c], h1 = vha[g4 + 16 * c];
+          const uint2 m0 = vma[16 * c], m1 = vma[g4 + 16 * c];
+          vh[c] = __builtin_bit_cast(bf16x8, uint4{h0.x, h0.y, h1.x, h1.y});
+          vm[c] = __builtin_bit_cast(bf16x8, uint4{m0.x, m0.y, m1.x, m1.y});
+          if (NS == 6) {
+            const uint2* vla = Vl + ga * Rp + rbase + r16;
+            const uint2 l0 = vla[16 * c], l1 = vla[g4 + 16 * c];
+            vl[c] = __builtin_bit_cast(bf16x8, uint4{l0.x, l0.y, l1.x, l1.y});
+          }
+        }
+      }
+      {   // this wave's fragment: cross term, exp2, BF16 splits -> LDS
+        const uint4* bp = B + (j + r16) * KV + kq;
+        f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[ch * 4]), tg[ch], qa, 0, 0, 0);
+          qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[16 * KV + ch * 4]), tg[ch], qb,
+                                                      0, 0, 0);
+        }
+        bf16x8 ph, pm, pl;
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {   // round-to-nearest-even splits, two values per v_cvt_pk_bf16_f32
+          const f32x2 p = {__builtin_amdgcn_exp2f(e < 4 ? qa[e] : qb[e - 4]),
+                           __builtin_amdgcn_exp2f(e < 4 ? qa[e + 1] : qb[e - 3])};
+          const bf16x2 h = __builtin_convertvector(p, bf16x2);
+          const f32x2 r1 = p - __builtin_convertvector(h, f32x2);
+          const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+          ph[e] = h[0]; ph[e + 1] = h[1];
+          pm[e] = m[0]; pm[e + 1] = m[1];
+          if (NS == 6) {
+            const bf16x2 lo = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+            pl[e] = lo[0]; pl[e + 1] = lo[1];
+          }
+        }
+        ps[buf][wave][0][lane] = __builtin_bit_cast(uint4, ph);
+        ps[buf][wave][1][lane] = __builtin_bit_cast(uint4, pm);
+        if (NS == 6) ps[buf][wave][2][lane] = __builtin_bit_cast(uint4, pl);
+      }
+      __syncthreads();   // the other buffer is rewritten only after the next barrier
+      if (live) {
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 ph = __builtin_bit_cast(bf16x8, ps[buf][t][0][lane]);
+          const bf16x8 pm = __builtin_bit_cast(bf16x8, ps[buf][t][1][lane]);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vh[c], a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vm[c], a32[t][c], 0, 0, 0);
+          a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm, vh[c], a32[t][c], 0, 0, 0);
+        }
+        if (NS == 6) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const bf16x8 ph = __builtin_bit_cast(bf16x8, ps[buf][t][0][lane]);
+            const bf16x8 pm = __builtin_bit_cast(bf16x8, ps[buf][t][1][lane]);
+            const bf16x8 pl = __builtin_bit_cast(bf16x8, ps[buf][t][2][lane]);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vl[c], a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl, vh[c], a32[t][c], 0, 0, 0);
+            a32[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm, vm[c], a32[t][c], 0, 0, 0);
+          }
+        }
+      }
+      }
+      buf ^= 1;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NRC; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[t][c][e] += (double)a32[t][c][e];
+  }
+  if (!live) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = row0 + 16 * t + kq * 4 + e;
+      double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout;
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) prow[rbase + 16 * c + r16] = acc[t][c][e];
+    }
+}
+
 }  // namespace krr

@@ -101,6 +101,8 @@ BLOCK_CASES = [
     (2100, 1100, 4, 40),
     (1030, 2000, 6, 128),
     (900, 700, 16, 33),
+    (1200, 1500, 16, 96),    # shared-tile form (variant 12): 96 columns padded to 128, four K chunks
+    (800, 1300, 6, 200),     # shared-tile form over two 128-column groups
 ]
 
 
