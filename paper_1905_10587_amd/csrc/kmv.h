@@ -69,6 +69,8 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv,
 // Variant bookkeeping for the autotuner.
 int kmv_num_variants(int prec, int R);
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t n, bool square = false);
+// FP64 with several columns, variant 3: the FP64 matrix-core kernel (needs the column count padded to 16)
+bool kmv_f64_uses_mfma(int prec, int d, int R, int deriv, int variant);
 // Whether variant v runs the symmetric square-product form for these parameters.
 bool kmv_is_symmetric(int prec, int d, int R, int deriv, bool square, int v);
 void kmv_set_override(int d, int R, int prec, int variant);

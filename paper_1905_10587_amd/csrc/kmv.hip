@@ -202,7 +202,8 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
                    hipStream_t s) {
   sv.npad = npad;
   sv.Rreal = R;
-  sv.R = (int)round_up(R, 8);   // column chunks are at most 8 wide
+  // column chunks are at most 8 wide; FP64 with more than 8 columns pads to 16 for the matrix-core kernel
+  sv.R = (int)round_up(R, prec == KRR_FP64 && R > 8 ? 16 : 8);
   const int64_t tot = npad * sv.R;
   const size_t cap = (size_t)(npad + kPrefetchRows) * sv.R;   // padding rows: read by the last prefetch only
   if (prec == KRR_FP64) {
@@ -301,8 +302,15 @@ int kmv_num_variants(int prec, int R) {
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
   // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
   // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2)
+  // FP64 several columns: 0..2 direct (TM 1, 2, 4; R >= 16: TM 1 with 16 / 32-column chunks), 3 the FP64
+  // matrix-core form (d <= 16, K only; else variant 1)
   if (prec == KRR_MIXED) return 12;
-  return prec == KRR_FP64 && rclass(prec, R) == 1 ? 5 : 3;
+  if (prec == KRR_FP64) return rclass(prec, R) == 1 ? 5 : 4;
+  return 3;
+}
+
+bool kmv_f64_uses_mfma(int prec, int d, int R, int deriv, int variant) {
+  return prec == KRR_FP64 && R > 1 && deriv == 0 && variant == 3 && padded_dim(d) >= 1 && padded_dim(d) <= 16;
 }
 
 bool kmv_uses_block(int prec, int d, int R, int deriv) {
@@ -331,6 +339,9 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
   }
   if (kmv_is_symmetric(prec, d, R, 0, square, 4)) return 4;   // FP64 symmetric square product, TM 4
   if (padded_dim(d) >= 32) return 0;
+  // FP64, more than 8 columns: the matrix-core kernel evaluates each pair once for up to 128 columns
+  // (n = 2e5, d = 6: 2.05x faster than the 32-column chunks at R = 128, 1.14x at R = 16)
+  if (prec == KRR_FP64 && R > 8) return 3;
   return m >= 65536 ? 1 : 0;
 }
 
@@ -442,6 +453,9 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   int form = 0;   // mixed single-column kernel form
   bool sym = false;   // symmetric square product (mixed, one column)
   const int D = T.dpad;
+  // FP64 many-column product on the FP64 matrix cores (variant 3 of FP64 with R > 1)
+  const bool f64m = kmv_f64_uses_mfma(prec, T.d, R, deriv, variant) && Rp % 16 == 0;
+  int NRG = 8;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
   bool k32 = false, shared = false;
@@ -474,6 +488,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     }
     rows = 64 * NF;
     gz = 1;
+  } else if (f64m) {
+    while ((Rp / 16) % NRG) NRG /= 2;
+    rows = 64;
+    gz = Rp / (16 * NRG);
   } else {
     int var = variant;
     if (prec == KRR_FP64 && var >= 3) {
@@ -506,6 +524,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
     if (prec == KRR_FP64 && sym) return launch_kmv_f64_sym(D, TM, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
+    if (f64m) return launch_kmv_f64_mfma(D, NRG, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP32) return launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
     if (sym) return launch_kmv_mixed_sym(T.ka / 32, NF, g, T.sa.p, S.sb.p, V.v32.p, part.p, s);

@@ -24,6 +24,10 @@ bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const doubl
 bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const double* v, double neg_c,
                         double* part, hipStream_t s);
 bool kmv_f64_has_sym(int D);
+// FP64 many-column product on the FP64 matrix cores: D <= 16 (instantiated D), NRG in {1, 2, 4, 8} groups
+// of 16 columns per block (16 * NRG divides Rp), K only.
+bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, const double* xs, const double* v,
+                         double neg_c, double* part, hipStream_t s);
 bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,
                     const float* v, double* part, hipStream_t s);
 // MFMA kernel (one column per launch): NCH in {1,2,3,4,6,8,13,25}, NF in {1,2,4,8} (limited by NCH),
@@ -41,7 +45,7 @@ bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, 
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,
                       const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part,
                       hipStream_t s);
-// Shared-tile block MVM: 64 targets x 128 right-hand sides per block (V staged with a multiple of 128 columns).
+// Shared-tile block MVM: 64 targets x 128 right-hand sides per block (V staged with a multiple of 32 columns).
 bool launch_kmv_block_shared(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                              const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
 

@@ -40,6 +40,31 @@ static void go64s(const KmvGrid& g, const double* x, const double* v, double neg
                      g.Rout);
 }
 
+template <int D, int NRG>
+static void go64m(const KmvGrid& g, const double* xt, const double* xs, const double* v, double neg_c,
+                  double* part, hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_mfma<D, NRG>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_f64_mfma<D, NRG>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src, neg_c,
+                     part, g.mpad, g.Rout);
+}
+
+bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, const double* xs, const double* v,
+                         double neg_c, double* part, hipStream_t s) {
+#define KRR_M64(DD)                                                               \
+  if (D == DD) {                                                                  \
+    if (NRG == 1) { go64m<DD, 1>(g, xt, xs, v, neg_c, part, s); return true; }    \
+    if (NRG == 2) { go64m<DD, 2>(g, xt, xs, v, neg_c, part, s); return true; }    \
+    if (NRG == 4) { go64m<DD, 4>(g, xt, xs, v, neg_c, part, s); return true; }    \
+    if (NRG == 8) { go64m<DD, 8>(g, xt, xs, v, neg_c, part, s); return true; }    \
+  }
+  KRR_M64(2) KRR_M64(3) KRR_M64(4) KRR_M64(6) KRR_M64(8) KRR_M64(16)
+#undef KRR_M64
+  return false;
+}
+
 bool kmv_f64_has_sym(int D) { return D == 2 || D == 4 || D == 6 || D == 8 || D == 16; }
 
 bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const double* v, double neg_c,

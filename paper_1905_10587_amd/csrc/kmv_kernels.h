@@ -119,6 +119,72 @@ __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, 
   }
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// FP64 product with many right-hand sides on the FP64 matrix cores (v_mfma_f64_16x16x4_f64, A 16 x 4,
+// B 4 x 16, exact FP64 products and sums).  A block covers 64 targets (wave w: targets row0 + 16 w ..) and
+// 16 * NRG columns; sources and their V rows stream through LDS in tiles of 32.  At each 4-source step
+// lane l evaluates the one pair (target l % 16, source l / 16) in FP64 direct differences, which is its
+// A-operand element, and the NRG MFMAs contract it with the V rows of the four sources.  The kernel value
+// of a pair is evaluated once for all 16 * NRG columns; the column-chunked VALU kernel evaluates it once
+// per chunk of 32.
+template <int D, int NRG>
+__global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__ xt, const double* __restrict__ xs,
+                                                      const double* __restrict__ v, int Rp, int64_t src_len,
+                                                      int64_t n_src, double neg_c, double* __restrict__ part,
+                                                      int64_t mpad, int Rout) {
+  constexpr int TS = 32;
+  constexpr int RCH = 16 * NRG;
+  constexpr int VS = RCH + 16;   // LDS row stride (doubles): consecutive rows start 128 bytes apart in the banks
+  __shared__ double sx[TS * D];
+  __shared__ double sv[TS * VS];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int c0 = blockIdx.z * RCH;
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = xt[(row0 + r16) * D + k];
+  f64x4 acc[NRG];
+#pragma unroll
+  for (int g = 0; g < NRG; ++g) acc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t jt = jb; jt < je; jt += TS) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < TS * D; u += 256) sx[u] = xs[jt * D + u];
+    for (int u = threadIdx.x; u < TS * RCH; u += 256) {
+      const int r = u / RCH, c = u % RCH;
+      sv[r * VS + c] = v[(jt + r) * Rp + c0 + c];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int s4 = 0; s4 < TS; s4 += 4) {
+      const int js = s4 + kq;
+      double d2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double df = xi[k] - sx[js * D + k];
+        d2 = __builtin_fma(df, df, d2);
+      }
+      const double e = exp2_neg_f64(d2 * neg_c);
+#pragma unroll
+      for (int g = 0; g < NRG; ++g)
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e, sv[js * VS + 16 * g + r16], acc[g], 0, 0, 0);
+    }
+  }
+  // result element e of the lane: target row0 + 4 e + l / 16, column c0 + 16 g + l % 16 (the FP64 16 x 16
+  // result interleaves its rows, unlike the FP32 16 x 16 results; checked by a lane-layout probe on gfx950)
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double* prow = part + ((int64_t)blockIdx.y * mpad + row0 + 4 * e + kq) * Rout + c0 + r16;
+#pragma unroll
+    for (int g = 0; g < NRG; ++g) prow[16 * g] = acc[g][e];
+  }
+}
+
 // Symmetric FP64 form for the square product u = K(X, X) v (one column), D even and <= 16.  Super-tiles
 // and partial slots as in k_kmv_mixed_sym: block b owns one pair (r, c <= ...) of the upper triangle,
 // evaluates the E x E tile once and writes its row sums to part[c][rows of r] and, off the diagonal, its

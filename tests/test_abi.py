@@ -95,6 +95,11 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(6, 200, "fp32") == (12, False)    # 224 of 256 columns
     assert krr.kmv_variant(6, 160, "fp32") == (7, False)     # 160 of 256 columns
     assert krr.kmv_variant(6, 64, "fp32") == (7, False)
+    # FP64 with more than 8 columns: the FP64 matrix-core kernel (variant 3)
+    assert krr.kmv_variant(6, 128, "fp64") == (3, False)
+    assert krr.kmv_variant(16, 9, "fp64") == (3, False)
+    assert krr.kmv_variant(6, 8, "fp64") == (0, False)
+    assert krr.kmv_variant(40, 128, "fp64") == (0, False)
     krr.set_variant(8, 1, "mixed", 3)
     assert krr.kmv_variant(8, 1, "mixed", square=True) == (3, False)
     krr.set_variant(8, 1, "mixed", 11)

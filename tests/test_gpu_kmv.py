@@ -101,8 +101,8 @@ BLOCK_CASES = [
     (2100, 1100, 4, 40),
     (1030, 2000, 6, 128),
     (900, 700, 16, 33),
-    (1200, 1500, 16, 96),    # shared-tile form (variant 12): 96 columns padded to 128, four K chunks
-    (800, 1300, 6, 200),     # shared-tile form over two 128-column groups
+    (1200, 1500, 16, 96),    # shared-tile form (variant 12): three of its four waves hold columns, four K chunks
+    (800, 1300, 6, 200),     # shared-tile form over two 128-column groups (224 padded columns: 3 live waves in the second)
 ]
 
 
@@ -130,6 +130,44 @@ def test_block_mv_parity(gpu_lib, prec, tol, case):
         print(f"block {prec} m={m} n={n} d={d} R={R} variant={variant}: max scaled error {err:.2e}", flush=True)
         assert err <= tol
     gpu_lib.set_variant(d, R, prec, -1)
+
+
+F64_MANY_CASES = [
+    # (m, n, d, R): FP64 products with several columns; variant 3 runs the FP64 matrix-core kernel
+    # (16 * NRG columns per block, NRG = 1, 2, 4, 8; more than 8 columns are padded to a multiple of 16)
+    (1500, 1700, 6, 16),
+    (2100, 1100, 4, 48),     # 48 columns: three blocks of 16
+    (1030, 2000, 6, 128),    # NRG 8, ragged targets
+    (900, 700, 16, 64),      # NRG 4, widest instantiated dimension
+    (800, 1300, 3, 32),      # odd padded dimension, NRG 2
+    (700, 900, 2, 200),      # 200 columns padded to 208 = 13 x 16: NRG 1, thirteen column blocks
+    (600, 1100, 40, 24),     # d = 40: no matrix-core form (variant 3 runs variant 1)
+    (500, 800, 5, 9),        # 9 columns padded to 16
+    (1000, 1000, 8, 256),    # two 128-column blocks
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", F64_MANY_CASES, ids=[f"m{c[0]}_n{c[1]}_d{c[2]}_R{c[3]}" for c in F64_MANY_CASES])
+def test_fp64_many_columns_variants(gpu_lib, case):
+    """FP64 K V with several columns, every variant (direct TM 1, 2, 4 and the matrix-core form) against
+    the oracle at the FP64 bar."""
+    m, n, d, R = case
+    rng = np.random.default_rng(m + 3 * R)
+    Xs = rng.random((n, d))
+    Xt = rng.random((m, d))
+    V = rng.standard_normal((n, R))
+    eps = 0.1 * d
+    K = ok.kernel_matrix(Xt, Xs, eps)
+    ref, scale = K @ V, K @ np.abs(V)
+    for variant in range(gpu_lib.num_variants("fp64", R)):
+        gpu_lib.set_variant(d, R, "fp64", variant)
+        U = gpu_lib.kernel_mv(torch.from_numpy(Xt), torch.from_numpy(Xs), eps, torch.from_numpy(V),
+                              prec="fp64").cpu().numpy()
+        err = _scaled_err(U, ref, scale)
+        print(f"fp64 m={m} n={n} d={d} R={R} variant={variant}: max scaled error {err:.2e}", flush=True)
+        assert err <= TOL["fp64"]
+    gpu_lib.set_variant(d, R, "fp64", -1)
 
 
 MIXED_VARIANT_CASES = [
