@@ -489,9 +489,15 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     rows = 64 * NF;
     gz = 1;
   } else if (f64m) {
-    while ((Rp / 16) % NRG) NRG /= 2;
+    // block width 16 * NRG: per 4-source step a block costs NRG MFMAs (64 cycles each) plus the pair's
+    // distance and exp (about 112 VALU cycles); dead groups of a partly filled last block are contracted too
+    double best = 1e300;
+    for (int nr : {8, 4, 2, 1}) {
+      const double cost = (double)ceil_div(Rp, 16 * nr) * (64.0 * nr + 112.0);
+      if (cost < best * (1 - 1e-9)) { best = cost; NRG = nr; }
+    }
     rows = 64;
-    gz = Rp / (16 * NRG);
+    gz = (int)ceil_div(Rp, 16 * NRG);   // the last block may hold fewer than 16 * NRG columns
   } else {
     int var = variant;
     if (prec == KRR_FP64 && var >= 3) {

@@ -25,7 +25,7 @@ bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const 
                         double* part, hipStream_t s);
 bool kmv_f64_has_sym(int D);
 // FP64 many-column product on the FP64 matrix cores: D <= 16 (instantiated D), NRG in {1, 2, 4, 8} groups
-// of 16 columns per block (16 * NRG divides Rp), K only.
+// of 16 columns per block (Rp a multiple of 16; the last block may be partly filled), K only.
 bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, const double* xs, const double* v,
                          double neg_c, double* part, hipStream_t s);
 bool launch_kmv_f32(int D, int TM, int RC, int DV, const KmvGrid& g, const float* xt, const float* xs,

@@ -127,7 +127,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // lane l evaluates the one pair (target l % 16, source l / 16) in FP64 direct differences, which is its
 // A-operand element, and the NRG MFMAs contract it with the V rows of the four sources.  The kernel value
 // of a pair is evaluated once for all 16 * NRG columns; the column-chunked VALU kernel evaluates it once
-// per chunk of 32.
+// per chunk of 32.  The last column block may be partly filled: groups of 16 columns at or beyond Rp
+// (a multiple of 16) are zero in LDS and contracted like the others (a branch around their MFMAs slows
+// the loop far more than the wasted products cost) but not stored.
 template <int D, int NRG>
 __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__ xt, const double* __restrict__ xs,
                                                       const double* __restrict__ v, int Rp, int64_t src_len,
@@ -144,6 +146,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__
   const int kq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int c0 = blockIdx.z * RCH;
+  const int ng = (Rp - c0) / 16 < NRG ? (Rp - c0) / 16 : NRG;   // live column groups of this block
   const int64_t jb = (int64_t)blockIdx.y * src_len;
   const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
   double xi[D];
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__
     for (int u = threadIdx.x; u < TS * D; u += 256) sx[u] = xs[jt * D + u];
     for (int u = threadIdx.x; u < TS * RCH; u += 256) {
       const int r = u / RCH, c = u % RCH;
-      sv[r * VS + c] = v[(jt + r) * Rp + c0 + c];
+      sv[r * VS + c] = c < 16 * ng ? v[(jt + r) * Rp + c0 + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll 2
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__
   for (int e = 0; e < 4; ++e) {
     double* prow = part + ((int64_t)blockIdx.y * mpad + row0 + 4 * e + kq) * Rout + c0 + r16;
 #pragma unroll
-    for (int g = 0; g < NRG; ++g) prow[16 * g] = acc[g][e];
+    for (int g = 0; g < NRG; ++g)
+      if (g < ng) prow[16 * g] = acc[g][e];
   }
 }
 

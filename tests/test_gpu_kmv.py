@@ -134,13 +134,15 @@ def test_block_mv_parity(gpu_lib, prec, tol, case):
 
 F64_MANY_CASES = [
     # (m, n, d, R): FP64 products with several columns; variant 3 runs the FP64 matrix-core kernel
-    # (16 * NRG columns per block, NRG = 1, 2, 4, 8; more than 8 columns are padded to a multiple of 16)
+    # (16 * NRG columns per block, NRG = 1, 2, 4, 8, the last block possibly partly filled; more than 8
+    # columns are padded to a multiple of 16)
     (1500, 1700, 6, 16),
-    (2100, 1100, 4, 48),     # 48 columns: three blocks of 16
+    (2100, 1100, 4, 48),     # 48 columns: one block of 64, three live groups of 16
     (1030, 2000, 6, 128),    # NRG 8, ragged targets
     (900, 700, 16, 64),      # NRG 4, widest instantiated dimension
     (800, 1300, 3, 32),      # odd padded dimension, NRG 2
-    (700, 900, 2, 200),      # 200 columns padded to 208 = 13 x 16: NRG 1, thirteen column blocks
+    (700, 900, 2, 200),      # 200 columns padded to 208: 128 + 80 (five live groups in the second block)
+    (600, 700, 3, 170),      # the dense-sketch width of the small workload: 176 = 128 + 48
     (600, 1100, 40, 24),     # d = 40: no matrix-core form (variant 3 runs variant 1)
     (500, 800, 5, 9),        # 9 columns padded to 16
     (1000, 1000, 8, 256),    # two 128-column blocks
