@@ -4,13 +4,17 @@
 //   K'  :    sum_j (D2_ij/eps) exp(-D2_ij/eps) V[j, c]             (eps dK/deps, for the gradient path)
 //
 // Three arithmetic forms:
-//   FP64  direct differences, FP64 exp written from its Cody-Waite reduction and Taylor series.
+//   FP64  direct differences; 2^q split as 2^rint(q) * 2^f, 2^f by a degree-10 near-minimax polynomial.
 //   FP32  direct differences on coordinates pre-scaled by sqrt(log2 e / eps), hardware exp2.
 //   MIXED the exp2 argument q_ij = -log2(e) ||t_i - s_j||^2 / eps comes straight out of one
 //         v_mfma_f32_16x16x32_bf16 per 32-wide K chunk: both operands are 3-way BF16 splits of
 //         the centred coordinates (hi/mid/lo, six cross products) plus the split row norms, so the
 //         MFMA's FP32 accumulation yields q without any VALU work; the VALU then does only
 //         exp2 and one FMA with v per pair.
+// Many right-hand sides: the exp'd tile is itself an MFMA operand.  MIXED and FP32 split it into BF16
+// parts and contract with split-BF16 V on v_mfma_f32_16x16x32_bf16 (block kernels); FP64 contracts it on
+// v_mfma_f64_16x16x4_f64 (k_kmv_f64_mfma).  Square one-column products have symmetric forms (MIXED and
+// FP64) that evaluate each pair once for both of its rows.
 // Sources are split across the grid's y dimension; every block writes FP64 partial sums which a
 // finishing kernel adds in a fixed order (deterministic), together with the ridge term.
 #include "kmv.h"
