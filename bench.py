@@ -262,8 +262,8 @@ def main(argv=None):
                          "condition numbers with/without the preconditioner on 10,000-point subsets")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU row sharding of the "
-                                   "solver is a design (see the design notes), not an implementation",
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the solver has no multi-GPU path "
+                                   "(row sharding of the targets is designed, not implemented)",
                           "n_gpus": a.gpus}))
         return 2
 
