@@ -68,6 +68,27 @@ def test_block_workload_mvm(gpu_lib):
 
 
 @pytest.mark.gpu
+def test_block_workload_fp64_replacement_product(gpu_lib):
+    """n = 500,000, d = 6, 128 right-hand sides in FP64: the block solve's residual-replacement product
+    (FP64 matrix-core kernel), with the per-column ridge shifts of the four beta values.
+
+    Bar: each block sums its source range (at most 65,536 sources) recursively in FP64, so the rounding
+    error of a row has a standard deviation of about sqrt(m) u = 256 x 1.1e-16 = 2.8e-14 of sum |K v|
+    (worst case m u = 7e-12); 2e-13 is about 7 standard deviations."""
+    wl = datagen.make_workload("block")
+    R = wl.y.shape[1]
+    betas = np.repeat(np.asarray(wl.betas, dtype=np.float64), R // len(wl.betas))
+    assert gpu_lib.kmv_variant(wl.d, R, "fp64", square=True) == (3, False)
+    rows = np.sort(np.random.default_rng(14).choice(wl.n, 16, replace=False))
+    U = gpu_lib.kernel_mv(torch.from_numpy(wl.X), None, wl.eps, torch.from_numpy(wl.y), shift=list(betas),
+                          prec="fp64").cpu().numpy()
+    ref, scale = _sampled(wl.X, wl.X, wl.eps, wl.y, rows)
+    ref = ref + betas * wl.y[rows]
+    scale = scale + betas * np.abs(wl.y[rows])
+    _check(U, rows, ref, scale, 2e-13, "block workload fp64 R=128 (+ ridge shifts)")
+
+
+@pytest.mark.gpu
 def test_adjoint_workload_cross_products(gpu_lib):
     """Validation x training products of the adjoint workload (20,000 x 200,000, d = 16), fused (K, K')."""
     wl = datagen.make_workload("adjoint")
