@@ -7,8 +7,10 @@
 // `replace_every` iterations, and whenever a column's recursive residual claims convergence, the
 // residual is recomputed as y - (K + beta I) x with the FP64 MVM (residual replacement).
 // Convergence is decided on the host from the R residual norms read back once per iteration.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -172,6 +174,15 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   if (active[c]) p[t] = __builtin_fma(beta[c], p[t], z[t]);
 }
 
+// out = z + beta p for active columns, p for the others (the look-ahead iteration writes a second buffer)
+__global__ void k_update_p_to(double* __restrict__ out, const double* __restrict__ p, const double* __restrict__ z,
+                              const double* __restrict__ beta, const int* __restrict__ active, int64_t n, int R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int c = (int)(t % R);
+  out[t] = active[c] ? __builtin_fma(beta[c], p[t], z[t]) : p[t];
+}
+
 __global__ void k_copy_active(double* __restrict__ dst, const double* __restrict__ src,
                               const int* __restrict__ active, int64_t n, int R) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -224,17 +235,23 @@ struct EventTimer {
     return ext;
   }
   hipEvent_t ext[2] = {nullptr, nullptr};
-  // collect after a synchronise
-  void collect() {
-    for (size_t i = 0; i < ev.size(); ++i) {
+  // collect after a synchronise (the first `upto` intervals: those recorded before the point waited for)
+  void collect(size_t upto = SIZE_MAX) {
+    upto = std::min(upto, ev.size());
+    for (size_t i = 0; i < upto; ++i) {
       float ms = 0;
       KRR_CHECK_HIP(hipEventElapsedTime(&ms, ev[i].first, ev[i].second));
       *pending[i] += ms;
       (void)hipEventDestroy(ev[i].first);
       (void)hipEventDestroy(ev[i].second);
     }
-    ev.clear();
-    pending.clear();
+    ev.erase(ev.begin(), ev.begin() + upto);
+    pending.erase(pending.begin(), pending.begin() + upto);
+  }
+  size_t marks() const { return ev.size(); }
+  // intervals not collected yet are charged to `where` instead (work whose result was discarded)
+  void retarget(double* where) {
+    for (auto& w : pending) w = where;
   }
   std::vector<double*> pending;
   ~EventTimer() {
@@ -296,8 +313,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     A64.init(X, n, d, eps, KRR_FP64, center.p, R, s);
     Atrue = &A64;
   }
-  DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s);
-  DevBuf<double> sc(8 * (size_t)R, s);   // rho, pq, gamma, beta, rr, rho_new, yy, spare
+  DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s), p2(nR, s), q2(nR, s);
+  DevBuf<double> sc(8 * (size_t)R, s);   // rho, pq, gamma, beta, rr, rho_new, yy, rho before a look-ahead
   double* rho = sc.p;
   double* pq = sc.p + R;
   double* gamma = sc.p + 2 * R;
@@ -305,6 +322,12 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   double* rr = sc.p + 4 * R;
   double* rho_new = sc.p + 5 * R;
   double* yy = sc.p + 6 * R;
+  double* rho_save = sc.p + 7 * R;
+  // current search direction and its product; the look-ahead iteration writes the other pair
+  double* pp = p.p;
+  double* qq = q.p;
+  double* pa = p2.p;
+  double* qa = q2.p;
   DevBuf<int> active(R, s), flags(2, s);
   ColReducer red;
   red.init(R, s);
@@ -349,7 +372,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     }
   };
   precondition(r.p, z.p);
-  KRR_CHECK_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+  KRR_CHECK_HIP(hipMemcpyAsync(pp, z.p, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
   red.dot(r.p, z.p, n, rho, s);
 
   // Lanczos coefficients of column 0, recorded until its recursive residual first claims convergence:
@@ -382,25 +405,63 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // KRR_PROGRESS=k prints the iteration count and the largest recursive relative residual every k iterations
   const char* prog_env = std::getenv("KRR_PROGRESS");
   const int progress = prog_env ? std::atoi(prog_env) : 0;
+  // Look-ahead: after the status of iteration `it` is enqueued, the next iteration's preconditioner
+  // apply, p update and product are enqueued too (into the second p / q buffers), and the host then waits
+  // for the status only, so the GPU is not idle while the host reads it and launches the next kernels.
+  // The look-ahead is kept when the status asks for nothing (the common case): its kernels are the ones the
+  // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
+  // before a scheduled residual replacement, and it is discarded (rho restored, its product's time not
+  // counted) when the status triggers a true-residual check or reports a breakdown.
+  hipEvent_t ev_status;
+  KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
+  struct EventGuard {
+    hipEvent_t e;
+    ~EventGuard() { (void)hipEventDestroy(e); }
+  } ev_guard{ev_status};
+  double discarded_ms = 0.0;
+  bool have_next = false;   // this iteration's product was enqueued by the previous look-ahead
   while (any_active && it < maxit) {
     ++it;
     // q = (K + beta I) p in the working precision
-    tm.start(&res.st.t_mvm_ms);
-    Aw.apply(p.p, betas, q.p, s, tm.external(&res.st.t_mvm_kernel_ms));
-    tm.stop();
+    if (!have_next) {
+      tm.start(&res.st.t_mvm_ms);
+      Aw.apply(pp, betas, qq, s, tm.external(&res.st.t_mvm_kernel_ms));
+      tm.stop();
+    }
+    have_next = false;
     res.st.n_mvm++;
-    red.dot(p.p, q.p, n, pq, s);
+    red.dot(pp, qq, n, pq, s);
     hipLaunchKernelGGL(k_gamma, dim3(nb(R)), dim3(256), 0, s, rho, pq, active.p, R, gamma, flags.p + 1);
-    hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, p.p, q.p, gamma, n, R);
+    hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, pp, qq, gamma, n, R);
     red.dot(r.p, nullptr, n, rr, s);
     KRR_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_pack_status, dim3(nb(R)), dim3(256), 0, s, (const double*)rr, (const double*)gamma,
                        (const double*)beta, (const int*)flags.p, R, hs);
     KRR_LAUNCH_CHECK();
-    KRR_CHECK_HIP(hipStreamSynchronize(s));
-    tm.collect();
+    KRR_CHECK_HIP(hipEventRecord(ev_status, s));
+    const size_t tmark = tm.marks();
+    const bool scheduled = replace_every > 0 && it % replace_every == 0;
+    const bool ahead = !scheduled && it < maxit;
+    if (ahead) {
+      KRR_CHECK_HIP(hipMemcpyAsync(rho_save, rho, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
+      precondition(r.p, z.p);
+      red.dot(r.p, z.p, n, rho_new, s);
+      hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
+      hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
+                         (const double*)beta, (const int*)active.p, n, R);
+      KRR_LAUNCH_CHECK();
+      tm.start(&res.st.t_mvm_ms);
+      Aw.apply(pa, betas, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
+      tm.stop();
+    }
+    KRR_CHECK_HIP(hipEventSynchronize(ev_status));
+    tm.collect(tmark);
     std::copy(hs, hs + 2 * (size_t)R, h.begin());
-    if (hs[3 * R + 1] != 0.0) { breakdown = true; break; }
+    if (hs[3 * R + 1] != 0.0) {
+      tm.retarget(&discarded_ms);
+      breakdown = true;
+      break;
+    }
     if (pending_b) lanczos_b.push_back(hs[2 * R]);   // beta of the previous iteration, column 0
     pending_b = false;
     std::vector<double> hrec(h.begin(), h.begin() + R);
@@ -422,15 +483,25 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
                    std::chrono::duration<double, std::milli>(clk::now() - t_start).count());
       std::fflush(stderr);
     }
-    const bool scheduled = replace_every > 0 && it % replace_every == 0;
+    if (ahead && !candidate) {   // keep the look-ahead: it is the next iteration's direction and product
+      std::swap(pp, pa);
+      std::swap(qq, qa);
+      have_next = true;
+      pending_b = act[0] && lanczos_open;   // read with the next iteration's status
+      continue;
+    }
+    if (ahead) {   // discard it: the true-residual check below replaces r first
+      KRR_CHECK_HIP(hipMemcpyAsync(rho, rho_save, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
+      tm.retarget(&discarded_ms);
+    }
     if (candidate || scheduled) {
       // true residual in FP64 (replaces the recursive one)
       tm.start(&res.st.t_mvm_fp64_ms);
-      Atrue->apply(x, betas, q.p, s);
+      Atrue->apply(x, betas, qq, s);
       tm.stop();
       res.st.n_mvm_fp64++;
       if (scheduled) res.st.n_replace++;
-      hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+      hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R);
       red.dot(r.p, nullptr, n, rr, s);
       KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
       KRR_CHECK_HIP(hipStreamSynchronize(s));
@@ -469,7 +540,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     precondition(r.p, z.p);
     red.dot(r.p, z.p, n, rho_new, s);
     hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
-    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, p.p, z.p, beta, active.p, n, R);
+    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, pp, z.p, beta, active.p, n, R);
     KRR_LAUNCH_CHECK();
     pending_b = act[0] && lanczos_open;   // read with the next iteration's status
   }
@@ -478,9 +549,9 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   bool unfinished = false;
   for (int c = 0; c < R; ++c) unfinished |= act[c] != 0;
   if (unfinished) {
-    Atrue->apply(x, betas, q.p, s);
+    Atrue->apply(x, betas, qq, s);
     res.st.n_mvm_fp64++;
-    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R);
     red.dot(r.p, nullptr, n, rr, s);
     KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
     KRR_CHECK_HIP(hipStreamSynchronize(s));
