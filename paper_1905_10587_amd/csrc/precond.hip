@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_sym_gemv(const double* __restrict__ G, 
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= kept) return;
   double s = 0;
+#pragma unroll 16   // the row's loads in flight together; the FMA chain keeps its order
   for (int c = lane; c < kept; c += 64) s = __builtin_fma(G[(int64_t)i * kept + c], t[c], s);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) z[i] = s;
