@@ -120,16 +120,13 @@ __global__ void k_residual(double* __restrict__ r, const double* __restrict__ y,
   if (active[t % R]) r[t] = y[t] - q[t];
 }
 
-// beta_c = rho_new_c / rho_c ; rho_c = rho_new_c (active columns)
-__global__ void k_beta(double* __restrict__ rho, const double* __restrict__ rho_new, const int* __restrict__ active,
-                       int R, double* __restrict__ beta) {
+// beta = rho_new / rho for active columns (rho and rho_new are two buffers the host alternates)
+__global__ void k_beta(const double* __restrict__ rho, const double* __restrict__ rho_new,
+                       const int* __restrict__ active, int R, double* __restrict__ beta) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= R) return;
   double b = 0.0;
-  if (active[c]) {
-    b = rho[c] != 0.0 ? rho_new[c] / rho[c] : 0.0;
-    rho[c] = rho_new[c];
-  }
+  if (active[c]) b = rho[c] != 0.0 ? rho_new[c] / rho[c] : 0.0;
   beta[c] = b;
 }
 
@@ -314,15 +311,16 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     Atrue = &A64;
   }
   DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s), p2(nR, s), q2(nR, s);
-  DevBuf<double> sc(8 * (size_t)R, s);   // rho, pq, gamma, beta, rr, rho_new, yy, rho before a look-ahead
+  DevBuf<double> sc(7 * (size_t)R, s);   // rho (two buffers), pq, gamma, beta, rr, yy
+  // r^T z of the current iteration and of the next one; the host swaps the two when an iteration
+  // advances, so a discarded look-ahead leaves rho as it was
   double* rho = sc.p;
+  double* rho_new = sc.p + 5 * R;
   double* pq = sc.p + R;
   double* gamma = sc.p + 2 * R;
   double* beta = sc.p + 3 * R;
   double* rr = sc.p + 4 * R;
-  double* rho_new = sc.p + 5 * R;
   double* yy = sc.p + 6 * R;
-  double* rho_save = sc.p + 7 * R;
   // current search direction and its product; the look-ahead iteration writes the other pair
   double* pp = p.p;
   double* qq = q.p;
@@ -410,7 +408,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // for the status only, so the GPU is not idle while the host reads it and launches the next kernels.
   // The look-ahead is kept when the status asks for nothing (the common case): its kernels are the ones the
   // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
-  // before a scheduled residual replacement, and it is discarded (rho restored, its product's time not
+  // before a scheduled residual replacement, and it is discarded (rho left as it was, its product's time not
   // counted) when the status triggers a true-residual check or reports a breakdown.
   hipEvent_t ev_status;
   KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
@@ -443,10 +441,10 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     const bool scheduled = replace_every > 0 && it % replace_every == 0;
     const bool ahead = !scheduled && it < maxit;
     if (ahead) {
-      KRR_CHECK_HIP(hipMemcpyAsync(rho_save, rho, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
       precondition(r.p, z.p);
       red.dot(r.p, z.p, n, rho_new, s);
-      hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
+      hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, (const double*)rho, (const double*)rho_new,
+                         (const int*)active.p, R, beta);
       hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
                          (const double*)beta, (const int*)active.p, n, R);
       KRR_LAUNCH_CHECK();
@@ -486,14 +484,12 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     if (ahead && !candidate) {   // keep the look-ahead: it is the next iteration's direction and product
       std::swap(pp, pa);
       std::swap(qq, qa);
+      std::swap(rho, rho_new);
       have_next = true;
       pending_b = act[0] && lanczos_open;   // read with the next iteration's status
       continue;
     }
-    if (ahead) {   // discard it: the true-residual check below replaces r first
-      KRR_CHECK_HIP(hipMemcpyAsync(rho, rho_save, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
-      tm.retarget(&discarded_ms);
-    }
+    if (ahead) tm.retarget(&discarded_ms);   // discard it: the true-residual check below replaces r first
     if (candidate || scheduled) {
       // true residual in FP64 (replaces the recursive one)
       tm.start(&res.st.t_mvm_fp64_ms);
@@ -539,9 +535,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     if (!any_active) break;
     precondition(r.p, z.p);
     red.dot(r.p, z.p, n, rho_new, s);
-    hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, rho, rho_new, active.p, R, beta);
+    hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, (const double*)rho, (const double*)rho_new,
+                       (const int*)active.p, R, beta);
     hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, pp, z.p, beta, active.p, n, R);
     KRR_LAUNCH_CHECK();
+    std::swap(rho, rho_new);
     pending_b = act[0] && lanczos_open;   // read with the next iteration's status
   }
   // final true residuals for columns still active (maxit or breakdown); stopped columns return their
