@@ -54,9 +54,25 @@ __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, co
   if (rl == 0 && c < R) part[(int64_t)blockIdx.y * R + c] = red[threadIdx.x];
 }
 
-// out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256).
+// Scalar work done by the final reduction kernel on the column's sum v (saves a launch per scalar step):
+//   kGamma:  gamma_c = rho_c / v for active columns (0 otherwise), breakdown flag if v <= 0 or not finite;
+//   kBeta:   beta_c = v / rho_c for active columns (0 otherwise; v is the new r^T z);
+//   kStatus: the per-iteration status for the host in one store into host-mapped memory,
+//            hs = [rr = v (R) | gamma (R) | beta of the previous iteration (R) | flags (2)].
+struct DotEpilogue {
+  enum Mode { kNone = 0, kGamma = 1, kBeta = 2, kStatus = 3 };
+  int mode = kNone;
+  const double* rho = nullptr;
+  const int* active = nullptr;
+  double* gamma = nullptr;
+  double* beta = nullptr;
+  int* flags = nullptr;
+  double* hs = nullptr;
+};
+
+// out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256), then the epilogue.
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nby, int R,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, DotEpilogue e) {
   __shared__ double red[256];
   const int c = blockIdx.x;
   red[threadIdx.x] = (int)threadIdx.x < nby ? part[(int64_t)threadIdx.x * R + c] : 0.0;
@@ -65,7 +81,29 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = red[0];
+  if (threadIdx.x != 0) return;
+  const double v = red[0];
+  out[c] = v;
+  if (e.mode == DotEpilogue::kGamma) {
+    double g = 0.0;
+    if (e.active[c]) {
+      if (!(v > 0.0) || !isfinite(v)) atomicOr(e.flags, 1);
+      else g = e.rho[c] / v;
+    }
+    e.gamma[c] = g;
+  } else if (e.mode == DotEpilogue::kBeta) {
+    double b = 0.0;
+    if (e.active[c]) b = e.rho[c] != 0.0 ? v / e.rho[c] : 0.0;
+    e.beta[c] = b;
+  } else if (e.mode == DotEpilogue::kStatus) {
+    e.hs[c] = v;
+    e.hs[R + c] = e.gamma[c];
+    e.hs[2 * R + c] = e.beta[c];
+    if (c == 0) {
+      e.hs[3 * R] = (double)e.flags[0];
+      e.hs[3 * R + 1] = (double)e.flags[1];
+    }
+  }
 }
 
 struct ColReducer {
@@ -77,31 +115,18 @@ struct ColReducer {
     while (CB * 2 <= R && CB < 64) CB *= 2;
     part.alloc((size_t)kRedBlocks * R, s);
   }
-  // out[c] = sum_i a[i,c] * b[i,c]  (b == nullptr: sum a^2)
-  void dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
+  // out[c] = sum_i a[i,c] * b[i,c]  (b == nullptr: sum a^2), then the epilogue's scalar step
+  void dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s,
+           const DotEpilogue& e = DotEpilogue()) {
     dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
     if (b) hipLaunchKernelGGL(k_coldot<0>, grid, dim3(256), 0, s, a, b, n, R, CB, part.p);
     else hipLaunchKernelGGL(k_coldot<1>, grid, dim3(256), 0, s, a, a, n, R, CB, part.p);
-    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out, e);
     KRR_LAUNCH_CHECK();
   }
 };
 
 // ------------------------------------------------------------------ elementwise / scalar kernels
-// gamma_c = rho_c / (p^T q)_c for active columns (0 otherwise); flags a breakdown.
-__global__ void k_gamma(const double* __restrict__ rho, const double* __restrict__ pq, const int* __restrict__ active,
-                        int R, double* __restrict__ gamma, int* __restrict__ breakdown) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= R) return;
-  double g = 0.0;
-  if (active[c]) {
-    const double d = pq[c];
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(breakdown, 1);
-    else g = rho[c] / d;
-  }
-  gamma[c] = g;
-}
-
 // x += gamma p ; r -= gamma q
 __global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                         const double* __restrict__ q, const double* __restrict__ gamma, int64_t n, int R) {
@@ -120,34 +145,7 @@ __global__ void k_residual(double* __restrict__ r, const double* __restrict__ y,
   if (active[t % R]) r[t] = y[t] - q[t];
 }
 
-// beta = rho_new / rho for active columns (rho and rho_new are two buffers the host alternates)
-__global__ void k_beta(const double* __restrict__ rho, const double* __restrict__ rho_new,
-                       const int* __restrict__ active, int R, double* __restrict__ beta) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= R) return;
-  double b = 0.0;
-  if (active[c]) b = rho[c] != 0.0 ? rho_new[c] / rho[c] : 0.0;
-  beta[c] = b;
-}
-
-// Per-iteration status for the host in one store into host-mapped memory:
-// hs = [rr (R) | gamma (R) | beta of the previous iteration (R) | flags (2)].
-__global__ void k_pack_status(const double* __restrict__ rr, const double* __restrict__ gamma,
-                              const double* __restrict__ beta, const int* __restrict__ flags, int R,
-                              double* __restrict__ hs) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < R) {
-    hs[c] = rr[c];
-    hs[R + c] = gamma[c];
-    hs[2 * R + c] = beta[c];
-  }
-  if (c == 0) {
-    hs[3 * R] = (double)flags[0];
-    hs[3 * R + 1] = (double)flags[1];
-  }
-}
-
-// Pinned, device-visible host buffer for k_pack_status (one per thread, grown on demand, kept for the
+// Pinned, device-visible host buffer for the status store (one per thread, grown on demand, kept for the
 // life of the process).
 static double* status_buffer(size_t count) {
   thread_local double* buf = nullptr;
@@ -410,6 +408,30 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
   // before a scheduled residual replacement, and it is discarded (rho left as it was, its product's time not
   // counted) when the status triggers a true-residual check or reports a breakdown.
+  // scalar steps carried by the final kernels of the dot products
+  auto epi_gamma = [&](const double* rho_cur) {
+    DotEpilogue e;
+    e.mode = DotEpilogue::kGamma;
+    e.rho = rho_cur;
+    e.active = active.p;
+    e.gamma = gamma;
+    e.flags = flags.p + 1;
+    return e;
+  };
+  auto epi_beta = [&](const double* rho_cur) {
+    DotEpilogue e;
+    e.mode = DotEpilogue::kBeta;
+    e.rho = rho_cur;
+    e.active = active.p;
+    e.beta = beta;
+    return e;
+  };
+  DotEpilogue epi_status;
+  epi_status.mode = DotEpilogue::kStatus;
+  epi_status.gamma = gamma;
+  epi_status.beta = beta;
+  epi_status.flags = flags.p;
+  epi_status.hs = hs;
   hipEvent_t ev_status;
   KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
   struct EventGuard {
@@ -428,13 +450,9 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     }
     have_next = false;
     res.st.n_mvm++;
-    red.dot(pp, qq, n, pq, s);
-    hipLaunchKernelGGL(k_gamma, dim3(nb(R)), dim3(256), 0, s, rho, pq, active.p, R, gamma, flags.p + 1);
+    red.dot(pp, qq, n, pq, s, epi_gamma(rho));
     hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, pp, qq, gamma, n, R);
-    red.dot(r.p, nullptr, n, rr, s);
-    KRR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_pack_status, dim3(nb(R)), dim3(256), 0, s, (const double*)rr, (const double*)gamma,
-                       (const double*)beta, (const int*)flags.p, R, hs);
+    red.dot(r.p, nullptr, n, rr, s, epi_status);
     KRR_LAUNCH_CHECK();
     KRR_CHECK_HIP(hipEventRecord(ev_status, s));
     const size_t tmark = tm.marks();
@@ -442,9 +460,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     const bool ahead = !scheduled && it < maxit;
     if (ahead) {
       precondition(r.p, z.p);
-      red.dot(r.p, z.p, n, rho_new, s);
-      hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, (const double*)rho, (const double*)rho_new,
-                         (const int*)active.p, R, beta);
+      red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
       hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
                          (const double*)beta, (const int*)active.p, n, R);
       KRR_LAUNCH_CHECK();
@@ -534,9 +550,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
     if (!any_active) break;
     precondition(r.p, z.p);
-    red.dot(r.p, z.p, n, rho_new, s);
-    hipLaunchKernelGGL(k_beta, dim3(nb(R)), dim3(256), 0, s, (const double*)rho, (const double*)rho_new,
-                       (const int*)active.p, R, beta);
+    red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
     hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, pp, z.p, beta, active.p, n, R);
     KRR_LAUNCH_CHECK();
     std::swap(rho, rho_new);
