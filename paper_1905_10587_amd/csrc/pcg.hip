@@ -54,6 +54,37 @@ __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, co
   if (rl == 0 && c < R) part[(int64_t)blockIdx.y * R + c] = red[threadIdx.x];
 }
 
+// x += gamma p ; r -= gamma q, and the partial sums of the new r^2 in the order of k_coldot<1> (the same
+// grid, rows and tree), so the residual norms are those of the separate update and dot product.
+__global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ p, const double* __restrict__ q,
+                                                  const double* __restrict__ gamma, int64_t n, int R, int CB,
+                                                  double* __restrict__ part) {
+  __shared__ double red[256];
+  const int cl = threadIdx.x % CB;
+  const int rl = threadIdx.x / CB;
+  const int rows_per = 256 / CB;
+  const int c = blockIdx.x * CB + cl;
+  double s = 0;
+  if (c < R) {
+    const double g = gamma[c];
+    for (int64_t i = (int64_t)blockIdx.y * rows_per + rl; i < n; i += (int64_t)gridDim.y * rows_per) {
+      const int64_t t = i * R + c;
+      x[t] = __builtin_fma(g, p[t], x[t]);
+      const double u = __builtin_fma(-g, q[t], r[t]);
+      r[t] = u;
+      s = __builtin_fma(u, u, s);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = rows_per / 2; w > 0; w >>= 1) {
+    if (rl < w) red[threadIdx.x] += red[threadIdx.x + w * CB];
+    __syncthreads();
+  }
+  if (rl == 0 && c < R) part[(int64_t)blockIdx.y * R + c] = red[threadIdx.x];
+}
+
 // Scalar work done by the final reduction kernel on the column's sum v (saves a launch per scalar step):
 //   kGamma:  gamma_c = rho_c / v for active columns (0 otherwise), breakdown flag if v <= 0 or not finite;
 //   kBeta:   beta_c = v / rho_c for active columns (0 otherwise; v is the new r^T z);
@@ -124,19 +155,17 @@ struct ColReducer {
     hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out, e);
     KRR_LAUNCH_CHECK();
   }
+  // x += gamma p, r -= gamma q, rr = column sums of the new r^2 (as dot(r, nullptr) after the update)
+  void axpy2_rr(double* x, double* r, const double* p, const double* q, const double* gamma, int64_t n,
+                double* rr, hipStream_t s, const DotEpilogue& e) {
+    dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
+    hipLaunchKernelGGL(k_axpy2_rr, grid, dim3(256), 0, s, x, r, p, q, gamma, n, R, CB, part.p);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, rr, e);
+    KRR_LAUNCH_CHECK();
+  }
 };
 
 // ------------------------------------------------------------------ elementwise / scalar kernels
-// x += gamma p ; r -= gamma q
-__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                        const double* __restrict__ q, const double* __restrict__ gamma, int64_t n, int R) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * R) return;
-  const double g = gamma[t % R];
-  x[t] = __builtin_fma(g, p[t], x[t]);
-  r[t] = __builtin_fma(-g, q[t], r[t]);
-}
-
 // r = y - q for active columns
 __global__ void k_residual(double* __restrict__ r, const double* __restrict__ y, const double* __restrict__ q,
                            const int* __restrict__ active, int64_t n, int R) {
@@ -451,9 +480,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     have_next = false;
     res.st.n_mvm++;
     red.dot(pp, qq, n, pq, s, epi_gamma(rho));
-    hipLaunchKernelGGL(k_axpy2, dim3(nb(nR)), dim3(256), 0, s, x, r.p, pp, qq, gamma, n, R);
-    red.dot(r.p, nullptr, n, rr, s, epi_status);
-    KRR_LAUNCH_CHECK();
+    red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, s, epi_status);
     KRR_CHECK_HIP(hipEventRecord(ev_status, s));
     const size_t tmark = tm.marks();
     const bool scheduled = replace_every > 0 && it % replace_every == 0;
