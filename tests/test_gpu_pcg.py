@@ -120,6 +120,25 @@ def test_pcg_rejects_unknown_beta(gpu_lib, small):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_breakdown_reported_and_solver_reusable(gpu_lib, prec):
+    """Right-hand sides near the top of the FP64 range overflow p^T A p to infinity at the first step: the
+    solve ends with KRR_EBREAKDOWN (its look-ahead iteration discarded), and the next solve is unaffected."""
+    rng = np.random.default_rng(4)
+    X = rng.random((500, 2))
+    y = 1e200 * rng.standard_normal(500)
+    eps, beta = 0.1, 1e-2
+    with pytest.raises(gpu_lib.KRRError, match="breakdown"):
+        gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y), eps, beta, None, tol=1e-8, maxit=100,
+                          prec=prec)
+    y1 = y * 1e-200
+    a, its, rel, st, status = gpu_lib.pcg_solve(torch.from_numpy(X), torch.from_numpy(y1), eps, beta, None,
+                                                tol=1e-8, maxit=5000, replace_every=10, prec=prec)
+    assert status == 0
+    assert _true_relres(X, eps, beta, y1, a.cpu().numpy()) <= 1.5e-8
+
+
+@pytest.mark.gpu
 def test_unattainable_tolerance_returns_best_iterate(gpu_lib):
     """A tolerance below CG's attainable accuracy ends in KRR_ENOCONV with the best iterate, not garbage."""
     rng = np.random.default_rng(0)
