@@ -430,13 +430,6 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // KRR_PROGRESS=k prints the iteration count and the largest recursive relative residual every k iterations
   const char* prog_env = std::getenv("KRR_PROGRESS");
   const int progress = prog_env ? std::atoi(prog_env) : 0;
-  // Look-ahead: after the status of iteration `it` is enqueued, the next iteration's preconditioner
-  // apply, p update and product are enqueued too (into the second p / q buffers), and the host then waits
-  // for the status only, so the GPU is not idle while the host reads it and launches the next kernels.
-  // The look-ahead is kept when the status asks for nothing (the common case): its kernels are the ones the
-  // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
-  // before a scheduled residual replacement, and it is discarded (rho left as it was, its product's time not
-  // counted) when the status triggers a true-residual check or reports a breakdown.
   // scalar steps carried by the final kernels of the dot products
   auto epi_gamma = [&](const double* rho_cur) {
     DotEpilogue e;
@@ -461,6 +454,13 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   epi_status.beta = beta;
   epi_status.flags = flags.p;
   epi_status.hs = hs;
+  // Look-ahead: after the status of iteration `it` is enqueued, the next iteration's preconditioner
+  // apply, p update and product are enqueued too (into the second p / q buffers), and the host then waits
+  // for the status only, so the GPU is not idle while the host reads it and launches the next kernels.
+  // The look-ahead is kept when the status asks for nothing (the common case): its kernels are the ones the
+  // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
+  // before a scheduled residual replacement, and it is discarded (rho left as it was, its product's time not
+  // counted) when the status triggers a true-residual check or reports a breakdown.
   hipEvent_t ev_status;
   KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
   struct EventGuard {
