@@ -179,14 +179,32 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
       }
     }
   }
-  double vpre[RMAX][C2];
+  // W = 8 applies the rotation on the FP64 matrix cores: wave w takes the 16-row tiles w, w + 4, ...
+  // (at most TPW of them), and lane l holds rows 16 tile + l % 16 of columns 4 kc + l / 16 (kc = 0..3):
+  // its B-operand elements.  Its V values are loaded here in that layout.  W = 4: rows tid + 256 u.
+  constexpr bool kMfmaApply = C2 == 16;
+  constexpr int TPW = (256 * RMAX / 16 + 3) / 4;
+  const int alane = tid & 63, awave = tid >> 6, ar16 = alane & 15, akq = alane >> 4;
+  double vpre[kMfmaApply ? TPW : RMAX][kMfmaApply ? 4 : C2];
+  if constexpr (kMfmaApply) {
 #pragma unroll
-  for (int u = 0; u < RMAX; ++u) {
-    const int t = tid + 256 * u;
+    for (int tt = 0; tt < TPW; ++tt) {
+      const int t = (awave + 4 * tt) * 16 + ar16;
 #pragma unroll
-    for (int lc = 0; lc < C2; ++lc) {
-      const int g = gcol(lc);
-      vpre[u][lc] = (t < k && g < k) ? V[(int64_t)g * k + t] : 0.0;
+      for (int kc = 0; kc < 4; ++kc) {
+        const int g = gcol(4 * kc + akq);
+        vpre[tt][kc] = (t < k && g < k) ? V[(int64_t)g * k + t] : 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < RMAX; ++u) {
+      const int t = tid + 256 * u;
+#pragma unroll
+      for (int lc = 0; lc < C2; ++lc) {
+        const int g = gcol(lc);
+        vpre[u][lc] = (t < k && g < k) ? V[(int64_t)g * k + t] : 0.0;
+      }
     }
   }
   __syncthreads();
@@ -301,6 +319,35 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
       __syncthreads();
     }
   }
+  if constexpr (kMfmaApply) {
+    // A <- S J, V <- V J as (S J)^T = J^T S^T on v_mfma_f64_16x16x4_f64: the A operand is J^T (lane l
+    // holds J[4 kc + l / 16][l % 16]), the B operand S^T or V^T of a 16-row tile, and result element e of
+    // lane l is column 4 e + l / 16 at row 16 tile + l % 16, so each store instruction writes four runs
+    // of 16 consecutive rows.
+    double ja[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) ja[kc] = J[4 * kc + akq][ar16];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+      const int t = (awave + 4 * tt) * 16 + ar16;
+      if ((awave + 4 * tt) * 16 >= k) break;   // wave-uniform
+      f64x4 da = {0.0, 0.0, 0.0, 0.0}, dv = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const double sb = t < k ? sa[(4 * kc + akq) * ks + t] : 0.0;
+        da = __builtin_amdgcn_mfma_f64_16x16x4f64(ja[kc], sb, da, 0, 0, 0);
+        dv = __builtin_amdgcn_mfma_f64_16x16x4f64(ja[kc], vpre[tt][kc], dv, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int g = gcol(4 * e + akq);
+        if (t < k && g < k) {
+          A[(int64_t)g * k + t] = da[e];
+          V[(int64_t)g * k + t] = dv[e];
+        }
+      }
+    }
+  } else {
   // A <- S J, V <- V J on the 2W columns, one row per thread at a time (V from the prefetched rows)
 #pragma unroll
   for (int u = 0; u < RMAX; ++u) {
@@ -322,6 +369,7 @@ __global__ __launch_bounds__(256) void k_jacobi_blockpair(double* __restrict__ A
       A[(int64_t)g * k + t] = xa;
       V[(int64_t)g * k + t] = xv;
     }
+  }
   }
   // block maximum of the off-diagonal measure -> one atomic
   for (int o = 32; o > 0; o >>= 1) {
