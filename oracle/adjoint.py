@@ -51,7 +51,3 @@ def fd_grad(Xtr, ytr, Xval, yval, eps, beta, h=1e-4):
     g_beta = (f(le, lb + h) - f(le, lb - h)) / (2 * h)
     return g_eps, g_beta
 
-
-def val_loss_grad_from_parts(rv, Kvtp_alpha, lam, Kp_alpha, alpha, beta):
-    """Assemble the two gradients from matrix-free pieces (same formulas as above)."""
-    return float(rv @ Kvtp_alpha - lam @ Kp_alpha), float(-beta * (lam @ alpha))
