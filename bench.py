@@ -1,22 +1,18 @@
 """Benchmark: Gaussian KRR hot path on one MI355X (one JSON line on stdout).
 
-A step is one pass of the whole hot path over the workload: preconditioner build (Algorithm 2
-sparse sketch, pivoted QR, anchor EVD, Nystrom factor, per-beta core Cholesky) and the PCG solve
-(Algorithm 5) to relative residual tol with the Woodbury preconditioner, in the working precision
-with FP64 residual replacement.  Inputs (points, labels, sketch draws) are resident in HBM before
-the timed region starts.
+Default workload "mixed": n = 1,000,000 points uniform in [0,1]^4, y = sum_m sin(2 pi m x_m)/m + 0.1 N(0,1),
+eps = 0.01, beta = 1e-3, k = 2000 anchors from an Algorithm 2 sketch (l = 2020, r = 32), mixed precision
+(split-BF16 MFMA cross term, FP32 exp/accumulate, FP64 scalars and residual replacement every 10
+iterations), tol 1e-6.  Its full solve takes minutes, so a step is one replacement cycle of the PCG
+(Algorithm 5): 10 mixed iterations and the FP64 residual replacement, cold-started on the resident
+inputs; the preconditioner build (Algorithms 2-3) is timed once beside the steps.  After the timed
+region: the same cycle with the FP64 and the FP32 kernels, the CPU oracle, and the full solve to 1e-6
+(its iteration cap set by --budget-s so the run stays within its wall-clock budget).
 
-Default workload "fp32" (the second configuration): n = 100,000, d = 8, points from a mixture of 20
-Gaussians, eps = 0.2, beta = 1e-2, k = 1000, l = 1020, r = 32, tol 1e-8.  The timed step runs the
-mixed precision form (split-BF16 MFMA cross term, FP32 exp/accumulate, FP64 scalars, FP64 residual
-replacement every 10 iterations).  After the timed region the same system is solved with the FP64
-and the FP32 kernels on the same GPU and the same preconditioner, for the mixed-vs-FP64 comparison.
-`--workload mixed` runs n = 1,000,000, d = 4 (eps = 0.01, beta = 1e-3, k = 2000, tol 1e-6); its FP64
-solve (about 50 minutes) is only run with --fp64-solve.
-
-value = kernel pairs evaluated by the step's MVMs (working-precision and FP64) / step wall time,
-in Gpairs/s.  Also reported: solve seconds, iterations, the kernel-MVM rates of the mixed, FP32 and
-FP64 kernels on the same GPU, the roofline of the dominant kernel (the mixed MVM) and the CPU oracle.
+value = kernel pairs evaluated by the step's MVMs (mixed and FP64) / step wall time, in Gpairs/s.
+roofline: the mixed MVM kernel (HIP events around its launches inside the library), against the VALU
+bound of the form that ran.  Other workloads (--workload fp32|small|block|adjoint): a step is the whole
+build + solve (or build + gradient).
 """
 from __future__ import annotations
 
@@ -97,25 +93,51 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def oracle_baseline(X, eps, seconds=12.0):
-    """CPU oracle (FP64 NumPy, as written) timed on a bounded row sample of one kernel MVM."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(X, eps, seconds=15.0, threads=None):
+    """CPU oracle (FP64 NumPy, as written) timed on a bounded row sample of one kernel MVM, on the host's
+    cores: each worker thread runs the oracle's row-sampled product on its own rows (NumPy's array loops
+    release the GIL; BLAS kept to one thread per worker).  Returns (pairs/s over wall time, rows, seconds,
+    threads)."""
+    import concurrent.futures as cf
+    import threading
+
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import kernel as ok
 
-    rng = np.random.default_rng(0)
-    v = rng.standard_normal(X.shape[0])
-    rows_done, t_used, rows = 0, 0.0, 16
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+    v = np.random.default_rng(0).standard_normal(X.shape[0])
+    stop = threading.Event()
+    counts = [0] * threads
+
+    def worker(w):
+        rng = np.random.default_rng(100 + w)
+        while not stop.is_set():
+            ok.kernel_mv_rows(X, eps, v, rng.integers(0, X.shape[0], 8))
+            counts[w] += 8
+
     with threadpool_limits(limits=1):
-        while t_used < seconds:
-            idx = rng.integers(0, X.shape[0], rows)
-            t0 = time.perf_counter()
-            ok.kernel_mv_rows(X, eps, v, idx)
-            t_used += time.perf_counter() - t0
-            rows_done += rows
-            rows = min(rows * 2, 256)
-    pairs = rows_done * X.shape[0]
-    return pairs / t_used, rows_done, t_used
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            futs = [ex.submit(worker, w) for w in range(threads)]
+            time.sleep(seconds)
+            stop.set()
+            for f in futs:
+                f.result()
+        secs = time.perf_counter() - t0
+    rows = sum(counts)
+    return rows * float(X.shape[0]) / secs, rows, secs, threads
 
 
 def kernels_only(a, wl, Xg, krr, torch):
@@ -242,15 +264,182 @@ def study_cond(a, krr, torch, datagen):
     return 0
 
 
+def mvm_roofline(prec, d, R, n, avg_ms, launches, variant, sym, traffic):
+    """Roofline record of the dominant kernel (the working-precision MVM).  frac is against the VALU-only
+    hardware bound of the form that ran (the exp and FMAs it must issue); for the mixed forms the bound that
+    also charges the MFMA cross term, which on this part does not overlap the VALU work, is given beside it
+    as an implementation figure."""
+    achieved = float(n) * n / (avg_ms * 1e-3)
+    if prec == "mixed":
+        peak = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
+        ser = peak_mixed(d, sym)
+        form = "symmetric form (exp + 2 FMA per evaluated pair, two pairs each)" if sym else \
+            "direct form (exp + FMA per pair)"
+    else:
+        peak = ser = peak_direct(d, prec, sym)
+        form = f"{'symmetric' if sym else 'direct'} form, {prec} VALU ops per pair"
+    rec = {"bound": "alu", "kernel": f"{prec} MVM, variant {variant}, {form}, d={d}",
+           "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2), "unit": "Tpairs/s",
+           "frac": round(achieved / peak, 3), "traffic": traffic,
+           "avg_kernel_ms": round(avg_ms, 4), "launches": launches,
+           "pairs_per_launch": float(n) * n}
+    if prec == "mixed":
+        rec["peak_valu_plus_mfma_serialized"] = round(ser / 1e12, 2)
+        rec["frac_of_serialized_bound"] = round(achieved / ser, 3)
+    return rec
+
+
+def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
+    """Default benchmark: the n = 1,000,000, d = 4 mixed-precision solve.  A step is one replacement cycle of
+    its PCG (Algorithm 5): replace_every mixed iterations (split-BF16 MFMA cross term, FP32 exp, Woodbury
+    apply with the FP32 factor, FP64 scalars) and the FP64 residual replacement, from a cold start on the
+    resident inputs; the preconditioner is built once, timed beside the steps.  After the timed region:
+    one cycle each with the FP64 and FP32 kernels (same preconditioner, same GPU), the CPU oracle, and the
+    full solve to rel-res tol under the run's wall-clock budget."""
+    prec, rep = "mixed", 10
+    beta = float(wl.betas[0])
+    n = wl.n
+    # warm-up build on a slice (first use of the build's kernels), not timed
+    m0 = min(n, 16384)
+    import datagen
+    idx0, sign0 = datagen.sketch_sparse_draws(m0, 84, 8, 1)
+    krr.Preconditioner(Xg[:m0], wl.eps, [beta], 64, 84, idx=torch.from_numpy(idx0).to(Xg.device),
+                       sign=torch.from_numpy(sign0).to(Xg.device), prec=prec)
+    torch.cuda.synchronize()
+    log(f"bench: building the preconditioner (k={wl.k}, l={wl.l}, r={wl.r})")
+    t0 = time.perf_counter()
+    P = krr.Preconditioner(Xg, wl.eps, [beta], wl.k, wl.l, prec=prec, **sk)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    phases = {k: round(v, 1) for k, v in P.timings().items()}
+    log(f"bench: build {build_s:.3f} s {phases}")
+
+    def cycle(p=prec, r=rep):
+        return krr.pcg_solve(Xg, Yg, wl.eps, [beta], P, tol=wl.tol, maxit=10, replace_every=r, prec=p,
+                             timing=True)
+
+    for w in range(a.warmup):
+        log(f"bench: warmup step {w + 1}/{a.warmup}")
+        cycle()
+    torch.cuda.synchronize()
+    log(f"bench: timing {a.steps} step(s)")
+    tot = {"n_mvm": 0, "n_mvm_fp64": 0, "t_mvm_kernel_ms": 0.0, "t_mvm_ms": 0.0, "t_mvm_fp64_ms": 0.0,
+           "t_precond_ms": 0.0}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(a.steps):
+        _, its, rel, st, status = cycle()
+        for k in tot:
+            tot[k] += st[k]
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    step_s = t_total / a.steps
+    n_mvm, n_fp64 = tot["n_mvm"] // a.steps, tot["n_mvm_fp64"] // a.steps
+    pairs_step = (n_mvm + n_fp64) * float(n) * n
+    variant, sym = krr.kmv_variant(wl.d, 1, prec, square=True)
+    avg_ms = tot["t_mvm_kernel_ms"] / max(tot["n_mvm"], 1)
+    traffic = stored_traffic(wl.name)
+    out = {
+        "metric": METRIC,
+        "value": round(pairs_step / step_s / 1e9, 2),
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * step_s, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3-split/f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: n={n} d={wl.d} eps={wl.eps} beta={beta} k={wl.k} l={wl.l} "
+                               f"r={wl.r} tol={wl.tol}; uniform points in [0,1]^4, "
+                               f"y = sum_m sin(2 pi m x_m)/m + 0.1 N(0,1)",
+                   "step": f"one replacement cycle of the PCG solve: {rep} mixed iterations + FP64 residual "
+                           f"replacement, cold start", "precision": prec, "replace_every": rep},
+        "step_mvms": {"mixed": n_mvm, "fp64": n_fp64},
+        "step_split_ms": {"mixed_mvm": round(tot["t_mvm_ms"] / a.steps, 2),
+                          "fp64_mvm": round(tot["t_mvm_fp64_ms"] / a.steps, 2),
+                          "woodbury": round(tot["t_precond_ms"] / a.steps, 2)},
+        "build_s": round(build_s, 3),
+        "build_phases_ms": phases,
+        "mvm_gpairs_s": round(float(n) * n / avg_ms / 1e6, 1),
+        "roofline": mvm_roofline(prec, wl.d, 1, n, avg_ms, tot["n_mvm"], variant, sym,
+                                 None if traffic is None else traffic["hbm_bytes_per_launch"]),
+    }
+    # the same cycle with the FP64 and the FP32 kernels (library kernel events, as for the mixed kernel)
+    for p2, r2 in (("fp64", 0), ("fp32", 10)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its2, _, st2, _ = krr.pcg_solve(Xg, Yg, wl.eps, [beta], P, tol=wl.tol, maxit=10, replace_every=r2,
+                                           prec=p2, timing=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        k_ms = st2["t_mvm_kernel_ms"] / max(st2["n_mvm"], 1)
+        v2, s2 = krr.kmv_variant(wl.d, 1, p2, square=True) if p2 == "fp64" else (None, False)
+        out[f"{p2}_cycle"] = {"s": round(dt, 3), "iterations": max(its2), "n_mvm": st2["n_mvm"],
+                              "n_mvm_fp64": st2["n_mvm_fp64"], "mvm_kernel_ms": round(k_ms, 3),
+                              "mvm_gpairs_s": round(float(n) * n / k_ms / 1e6, 1),
+                              "roofline": mvm_roofline(p2, wl.d, 1, n, k_ms, st2["n_mvm"], v2, s2, None)}
+        out[f"mvm_gpairs_s_{p2}"] = out[f"{p2}_cycle"]["mvm_gpairs_s"]
+        log(f"bench: {p2} cycle {dt:.3f} s, MVM kernel {k_ms:.2f} ms")
+    out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
+    out["cycle_speedup_vs_fp64"] = round(out["fp64_cycle"]["s"] / step_s, 2)
+    if not a.no_cpu:
+        log("bench: CPU oracle baseline")
+        rate, rows, secs, thr = oracle_baseline(wl.X, wl.eps)
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gpairs/s", "cores": thr, "kind": "oracle",
+                               "cpu": cpu_model(),
+                               "sample": f"oracle kernel_mv_rows (FP64 NumPy) on {rows} random rows x {n} sources "
+                                         f"({rows * float(n):.3g} pairs, {secs:.1f} s wall, {thr} threads); the "
+                                         f"oracle's solve runs the same product once per iteration"}
+        log(f"bench: CPU oracle {rate / 1e9:.4f} Gpairs/s on {thr} threads")
+    if not a.no_full_solve:
+        # the full solve to tol, capped so that the whole run stays inside its wall-clock budget
+        per_it = step_s / 10.0
+        left = a.budget_s - (time.perf_counter() - t_proc0) - 15.0
+        maxit = int(min(a.maxit, max(0.0, left) / (per_it * 1.05)))
+        log(f"bench: full solve to {wl.tol} (maxit {maxit} from the {a.budget_s:.0f} s budget)")
+        if maxit >= 10:
+            os.environ.setdefault("KRR_PROGRESS", "200")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            alpha, its, rel, st, status = krr.pcg_solve(Xg, Yg, wl.eps, [beta], P, tol=wl.tol, maxit=maxit,
+                                                        replace_every=rep, prec=prec, timing=True)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            fp64_per_it = out["fp64_cycle"]["s"] / max(out["fp64_cycle"]["iterations"], 1)
+            out["solve"] = {"solve_s": round(solve_s, 2), "build_plus_solve_s": round(build_s + solve_s, 2),
+                            "iterations": max(its), "relres_true": max(rel), "status": status,
+                            "converged": bool(status == 0 and max(rel) <= wl.tol), "maxit": maxit,
+                            "n_mvm": st["n_mvm"], "n_mvm_fp64": st["n_mvm_fp64"],
+                            "t_mvm_s": round(st["t_mvm_ms"] / 1e3, 2),
+                            "t_mvm_fp64_s": round(st["t_mvm_fp64_ms"] / 1e3, 2),
+                            "t_woodbury_s": round(st["t_precond_ms"] / 1e3, 2),
+                            "fp64_replacement_share": round(st["t_mvm_fp64_ms"] / 1e3 / solve_s, 3),
+                            "kappa_est": round(st["kappa_est"], 1),
+                            "fp64_solve_s_projected": round(fp64_per_it * max(its), 1),
+                            "solve_speedup_vs_fp64_projected": round(fp64_per_it * max(its) / solve_s, 2),
+                            "projection": "FP64 cycle time per iteration (same GPU, same preconditioner) x "
+                                          "the mixed solve's iteration count"}
+            log(f"bench: solve {solve_s:.1f} s, {max(its)} iterations, relres {max(rel):.3e}, status {status}")
+    return out
+
+
 def main(argv=None):
+    t_proc0 = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32", choices=["mixed", "fp32", "small", "block", "adjoint"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "fp32", "small", "block", "adjoint"])
     ap.add_argument("--prec", default=None, help="working precision (default: the workload's)")
     ap.add_argument("--fp64-solve", action="store_true", help="also run the full FP64 solve (minutes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-full-solve", action="store_true", help="mixed workload: skip the full solve after "
+                                                                 "the timed cycles")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget of the whole run; caps the full solve's iterations")
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling mode: a 1 GiB device copy (counter calibration), then the workload's "
@@ -296,7 +485,21 @@ def main(argv=None):
     else:
         sk = dict(omega=torch.from_numpy(datagen.sketch_dense_omega(wl.n, wl.l, datagen.sketch_seed(wl.name))).to(dev))
     torch.cuda.synchronize()
+    if a.kernels_only:
+        return kernels_only(a, wl, Xg, krr, torch)
+    if a.study == "anchors":
+        return study_anchors(a, wl, Xg, Yg, krr, torch, datagen, prec, replace_every)
+    if a.workload == "mixed" and prec == "mixed":
+        out = cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0)
+        print(json.dumps(out), flush=True)
+        return 0
+    return solve_bench(a, wl, Xg, Yg, sk, betas_col, prec, replace_every, krr, torch)
 
+
+def solve_bench(a, wl, Xg, Yg, sk, betas_col, prec, replace_every, krr, torch):
+    """Other workloads: a step is the whole solve (preconditioner build + PCG to tol, or for the adjoint
+    workload build + gradient)."""
+    dev = Xg.device
     adjoint = wl.X_val is not None
     if adjoint:
         Xvg = torch.from_numpy(wl.X_val).to(dev)
@@ -311,25 +514,22 @@ def main(argv=None):
         if adjoint:
             # the step of this workload is the validation-loss gradient: forward solve, adjoint solve and the
             # FP64 products that assemble loss and gradient
-            loss, ge, gb, alpha, lam, sts = krr.grad(Xg, Yg, Xvg, yvg, wl.eps, wl.betas[0], P, tol=wl.tol,
-                                                     maxit=a.maxit, replace_every=replace_every, prec=prec,
-                                                     return_stats=True)
+            loss, ge, gb, alpha, lam, gstatus, sts = krr.grad(Xg, Yg, Xvg, yvg, wl.eps, wl.betas[0], P,
+                                                              tol=wl.tol, maxit=a.maxit,
+                                                              replace_every=replace_every, prec=prec,
+                                                              return_stats=True)
             torch.cuda.synchronize()
-            grad_out.update(loss=loss, dloss_dlog_eps=ge, dloss_dlog_beta=gb, stats=sts)
+            grad_out.update(loss=loss, dloss_dlog_eps=ge, dloss_dlog_beta=gb, stats=sts, status=gstatus)
             st = {k: sts[0][k] + sts[1][k] for k in sts[0] if k not in ("kappa_est", "iters_max")}
             st["kappa_est"] = sts[0]["kappa_est"]
             st["iters_max"] = max(sts[0]["iters_max"], sts[1]["iters_max"])
-            its, rel, status = [sts[0]["iters_max"], sts[1]["iters_max"]], [0.0], 0
-            return P, alpha, its, rel, st, status, tb, time.perf_counter() - t0
+            its, rel = [sts[0]["iters_max"], sts[1]["iters_max"]], [0.0]
+            return P, alpha, its, rel, st, gstatus, tb, time.perf_counter() - t0
         alpha, its, rel, st, status = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol, maxit=a.maxit,
                                                     replace_every=replace_every, prec=prec, timing=True)
         torch.cuda.synchronize()
         return P, alpha, its, rel, st, status, tb, time.perf_counter() - t0
 
-    if a.kernels_only:
-        return kernels_only(a, wl, Xg, krr, torch)
-    if a.study == "anchors":
-        return study_anchors(a, wl, Xg, Yg, krr, torch, datagen, prec, replace_every)
     os.environ.setdefault("KRR_PROGRESS", "100")
     for w in range(a.warmup):
         log(f"bench: warmup step {w + 1}/{a.warmup}")
@@ -356,26 +556,27 @@ def main(argv=None):
         pairs_step += 2.0 * m * n + float(n) * n
     ms_per_step = 1e3 * t_total / a.steps
     value = pairs_step / (t_total / a.steps) / 1e9
-    # roofline: the main MVM kernel alone (HIP events around its launch, on the solver's stream)
     avg_mvm_ms = st["t_mvm_kernel_ms"] / max(st["n_mvm"], 1)
     achieved = float(n) * n / (avg_mvm_ms * 1e-3)
     variant, sym = krr.kmv_variant(wl.d, R, prec, square=True) if prec in ("mixed", "fp64") else (None, False)
-    if prec == "mixed":
-        peak_valu = PEAK_PAIRS_SYM if sym else PEAK_PAIRS
-        peak = peak_mixed(wl.d, sym)
-    else:
-        peak_valu = peak = peak_direct(wl.d, prec, sym)
     traffic = stored_traffic(wl.name) if prec == "mixed" and R == 1 else None
     block_mvm = prec == "mixed" and R > 1
     if block_mvm:
-        # many right-hand sides: the exp'd tile is contracted with V on MFMA (three BF16 split products per
-        # column), plus the split cross term (NCH chunks of 32) -> MFMA bound; dense BF16 peak 2.5 PFLOP/s
+        # many right-hand sides: the exp'd tile is contracted with V on MFMA; the method's work per pair is one
+        # exp and 2R flops (K V); the split products (three per column) and the cross term are the
+        # implementation's cost.  Dense BF16 peak 2.5 PFLOP/s.
         nch = -(-(6 * wl.d + 6) // 32)
-        flop_pair = 2.0 * 3 * R + 2.0 * 32 * nch
+        flop_impl = 2.0 * 3 * R + 2.0 * 32 * nch
         roofline = {"bound": "mfma", "kernel": f"block MVM (variant {variant}), R={R}, d={wl.d}",
-                    "achieved": round(achieved * flop_pair / 1e12, 1), "peak": 2500.0, "unit": "TFLOP/s",
-                    "frac": round(achieved * flop_pair / 2.5e15, 3), "traffic": None,
-                    "flop_per_pair": flop_pair, "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]}
+                    "achieved": round(achieved * flop_impl / 1e12, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                    "frac": round(achieved * flop_impl / 2.5e15, 3), "traffic": None,
+                    "flop_per_pair_issued": flop_impl, "flop_per_pair_method": 2.0 * R,
+                    "frac_method_flops": round(achieved * 2.0 * R / 2.5e15, 3),
+                    "frac_of_split_bound": round(achieved / min(PEAK_PAIRS, 2.5e15 / (2.0 * R * 3)), 3),
+                    "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]}
+    else:
+        roofline = mvm_roofline(prec, wl.d, R, n, avg_mvm_ms, st["n_mvm"], variant, sym,
+                                None if traffic is None else traffic["hbm_bytes_per_launch"])
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -406,19 +607,7 @@ def main(argv=None):
         "t_precond_s": round(st["t_precond_ms"] / 1e3, 3),
         "kappa_est": round(st["kappa_est"], 1),
         "mvm_gpairs_s": round(achieved / 1e9, 1),
-        "roofline": roofline if block_mvm else {"bound": "alu",
-                     "kernel": (f"{prec} MVM, variant {variant}, " if variant is not None else f"{prec} MVM, ")
-                               + (("symmetric form (exp + 2 FMA per evaluated pair)" if sym
-                                   else "direct form (exp + FMA per pair)") if prec == "mixed" else
-                                  (f"{'symmetric' if sym else 'direct'} form, {prec} VALU bound "
-                                   f"({'2d+18 per evaluated pair' if sym else '2d+17 per pair' if prec == 'fp64' else '2d+3 per pair'})"))
-                               + (f" + {mixed_chunks(wl.d)} MFMA per 256 evaluated pairs, serialized with the VALU"
-                                  if prec == "mixed" else "") + f", d={wl.d}",
-                     "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
-                     "unit": "Tpairs/s", "frac": round(achieved / peak, 3),
-                     "peak_valu_only": round(peak_valu / 1e12, 2), "frac_valu_only": round(achieved / peak_valu, 3),
-                     "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
-                     "avg_kernel_ms": round(avg_mvm_ms, 4), "launches": st["n_mvm"]},
+        "roofline": roofline,
     }
     if R > 1:   # per-beta summary of the block solve's columns
         by_beta = {}
@@ -439,45 +628,31 @@ def main(argv=None):
                            "adjoint": {"iterations": sts[1]["iters_max"], "n_mvm": sts[1]["n_mvm"],
                                        "n_mvm_fp64": sts[1]["n_mvm_fp64"]},
                            "validation_points": int(wl.X_val.shape[0])}
-    # kernel rates of the other precisions on the same GPU (one timed MVM each, same size)
-    if R == 1 and not adjoint:
-        v = torch.randn(n, dtype=torch.float64, device=dev)
-        for p2 in ("fp64", "fp32"):
-            krr.kernel_mv(Xg[:4096], None, wl.eps, v[:4096], prec=p2)
+    if R == 1 and not adjoint and prec != "fp64" and (a.fp64_solve or n <= 200_000):
+        # the same system solved with the FP64 and the FP32 kernels (same preconditioner), after the timed region
+        for p2, rep in (("fp64", 0), ("fp32", 10)):
+            log(f"bench: {p2} solve on the same GPU for comparison")
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            krr.kernel_mv(Xg, None, wl.eps, v, prec=p2)
-            e1.record()
+            t0 = time.perf_counter()
+            a2, its2, rel2, st2, status2 = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol,
+                                                         maxit=a.maxit, replace_every=rep, prec=p2, timing=True)
             torch.cuda.synchronize()
-            out[f"mvm_gpairs_s_{p2}"] = round(float(n) * n / e0.elapsed_time(e1) / 1e6, 1)
+            out[f"{p2}_solve_s"] = round(time.perf_counter() - t0, 3)
+            out[f"{p2}_iterations"] = max(its2)
+            out[f"{p2}_relres_true"] = max(rel2)
+            k_ms = st2["t_mvm_kernel_ms"] / max(st2["n_mvm"], 1)
+            out[f"mvm_gpairs_s_{p2}"] = round(float(n) * n / k_ms / 1e6, 1)
+            if p2 == "fp64":
+                out["alpha_rel_err_vs_fp64"] = float(torch.linalg.norm(alpha - a2) / torch.linalg.norm(a2))
+        out["solve_speedup_vs_fp64"] = round(out["fp64_solve_s"] / (t_step - t_build), 2)
         out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
-        # the same system solved with the FP64 and the FP32 kernels (same preconditioner), after the timed
-        # region; skipped by default where the FP64 solve takes tens of minutes
-        run_fp64 = a.fp64_solve or n <= 200_000
-        if prec != "fp64" and run_fp64:
-            for p2, rep in (("fp64", 0), ("fp32", 10)):
-                log(f"bench: {p2} solve on the same GPU for comparison")
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                a2, its2, rel2, st2, status2 = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol,
-                                                             maxit=a.maxit, replace_every=rep, prec=p2)
-                torch.cuda.synchronize()
-                out[f"{p2}_solve_s"] = round(time.perf_counter() - t0, 3)
-                out[f"{p2}_iterations"] = max(its2)
-                out[f"{p2}_relres_true"] = max(rel2)
-                if p2 == "fp64":
-                    out["alpha_rel_err_vs_fp64"] = float(torch.linalg.norm(alpha - a2) / torch.linalg.norm(a2))
-            out["solve_speedup_vs_fp64"] = round(out["fp64_solve_s"] / (t_step - t_build), 2)
-        elif prec != "fp64":
-            out["fp64_solve_s_projected"] = round(max(its) * float(n) * n / (out["mvm_gpairs_s_fp64"] * 1e9), 1)
     if not a.no_cpu:
         log("bench: CPU oracle baseline")
-        rate, rows, secs = oracle_baseline(wl.X, wl.eps)
-        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
-                               "sample": f"oracle kernel_mv_rows (FP64 NumPy, one thread) on {rows} random rows x "
-                                         f"{n} sources ({rows * n:.3g} pairs, {secs:.1f} s); the oracle's solve "
-                                         f"runs the same MVM once per iteration"}
+        rate, rows, secs, thr = oracle_baseline(wl.X, wl.eps)
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 4), "unit": "Gpairs/s", "cores": thr, "kind": "oracle",
+                               "cpu": cpu_model(),
+                               "sample": f"oracle kernel_mv_rows (FP64 NumPy) on {rows} random rows x {n} sources "
+                                         f"({rows * float(n):.3g} pairs, {secs:.1f} s wall, {thr} threads)"}
     print(json.dumps(out), flush=True)
     return 0
 

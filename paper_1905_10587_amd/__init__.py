@@ -361,8 +361,11 @@ def pcg_solve(X, Y, eps: float, betas, P: Optional[Preconditioner] = None, *, to
 
 def grad(Xtr, ytr, Xval, yval, eps: float, beta: float, P: Optional[Preconditioner] = None, *, tol=1e-8,
          maxit=10000, replace_every=0, prec="fp64", return_stats=False):
-    """(loss, dL/dlog eps, dL/dlog beta, alpha, lambda) by the adjoint method; with return_stats, a sixth
-    element: the forward and adjoint solves' statistics (two dicts)."""
+    """(loss, dL/dlog eps, dL/dlog beta, alpha, lambda, status) by the adjoint method.
+
+    status is KRR_OK (0) or KRR_ENOCONV (1: the forward or the adjoint solve stopped before tol, so the
+    loss and gradients come from unconverged iterates); errors raise KRRError.  With return_stats, a
+    seventh element: the forward and adjoint solves' statistics (two dicts)."""
     lib = load()
     Xtr, ytr, Xval, yval = _dev(Xtr), _dev(ytr), _dev(Xval), _dev(yval)
     n, d = Xtr.shape
@@ -371,27 +374,37 @@ def grad(Xtr, ytr, Xval, yval, eps: float, beta: float, P: Optional[Precondition
     alpha = torch.empty(n, dtype=torch.float64, device=Xtr.device)
     lam = torch.empty(n, dtype=torch.float64, device=Xtr.device)
     st = (SolveStats * 2)()
-    _chk(lib, lib.krr_grad(_p(Xtr), n, _p(ytr), _p(Xval), m, _p(yval), d, float(eps), float(beta),
-                           None if P is None else P.handle, float(tol), int(maxit), int(replace_every),
-                           _prec(prec), ctypes.byref(loss), ctypes.byref(ge), ctypes.byref(gb), _p(alpha), _p(lam),
-                           st if return_stats else None, _stream()))
+    status = _chk(lib, lib.krr_grad(_p(Xtr), n, _p(ytr), _p(Xval), m, _p(yval), d, float(eps), float(beta),
+                                    None if P is None else P.handle, float(tol), int(maxit), int(replace_every),
+                                    _prec(prec), ctypes.byref(loss), ctypes.byref(ge), ctypes.byref(gb), _p(alpha),
+                                    _p(lam), st if return_stats else None, _stream()))
+    out = (loss.value, ge.value, gb.value, alpha, lam, status)
     if return_stats:
-        return loss.value, ge.value, gb.value, alpha, lam, [st[0].as_dict(), st[1].as_dict()]
-    return loss.value, ge.value, gb.value, alpha, lam
+        return out + ([st[0].as_dict(), st[1].as_dict()],)
+    return out
 
 
 class KRRValLoss(torch.autograd.Function):
     """L(log eps, log beta) = 1/2 ||K(Xval, Xtr) alpha - yval||^2 with alpha = (K + beta I)^{-1} ytr.
 
     forward(log_eps, log_beta, Xtr, ytr, Xval, yval, P, opts) -> scalar loss; backward returns the
-    adjoint gradients for log_eps and log_beta (X and y are not differentiated).
+    adjoint gradients for log_eps and log_beta (X and y are not differentiated).  opts are grad()'s keyword
+    arguments plus "allow_noconv": a solve that stops before tol raises KRRError(KRR_ENOCONV) unless it is
+    True, in which case a RuntimeWarning is issued and the unconverged values are returned.
     """
 
     @staticmethod
     def forward(ctx, log_eps, log_beta, Xtr, ytr, Xval, yval, P=None, opts=None):
         opts = dict(opts or {})
+        allow = bool(opts.pop("allow_noconv", False))
         eps, beta = float(torch.exp(log_eps)), float(torch.exp(log_beta))
-        loss, ge, gb, _, _ = grad(Xtr, ytr, Xval, yval, eps, beta, P, **opts)
+        loss, ge, gb, _, _, status = grad(Xtr, ytr, Xval, yval, eps, beta, P, **opts)
+        if status != 0:
+            msg = load().krr_last_error().decode()
+            if not allow:
+                raise KRRError(status, msg)
+            import warnings
+            warnings.warn(f"KRRValLoss: {_STATUS.get(status, status)}: {msg}", RuntimeWarning, stacklevel=2)
         ctx.save_for_backward(torch.tensor([ge, gb], dtype=torch.float64))
         return torch.tensor(loss, dtype=torch.float64, device=log_eps.device)
 

@@ -41,6 +41,11 @@ extern "C" int krr_kernel_mv(const double* Xt, int64_t m, const double* Xs, int6
     KRR_REQUIRE(deriv >= 0 && deriv <= 2, "deriv must be 0, 1 or 2");
     KRR_REQUIRE(shift == nullptr || m == n, "shift requires targets == sources");
     hipStream_t s = (hipStream_t)stream;
+    krr::check_finite_device(Xt, m * (int64_t)d, "Xt", s);
+    if (Xs != Xt) krr::check_finite_device(Xs, n * (int64_t)d, "Xs", s);
+    krr::check_finite_device(V, n * (int64_t)R, "V", s);
+    if (shift)
+      for (int c = 0; c < R; ++c) KRR_REQUIRE(std::isfinite(shift[c]), "shift must be finite");
     const int64_t ldu = deriv == 2 ? 2 * (int64_t)R : R;
     krr::kernel_mv_raw(Xt, m, Xs, n, d, eps, V, R, shift, deriv, prec, U, ldu, s);
     return (int)KRR_OK;

@@ -469,8 +469,10 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   } ev_guard{ev_status};
   double discarded_ms = 0.0;
   bool have_next = false;   // this iteration's product was enqueued by the previous look-ahead
+  bool fresh_true = false;  // the true residuals of the current x were computed by this iteration's check
   while (any_active && it < maxit) {
     ++it;
+    fresh_true = false;
     // q = (K + beta I) p in the working precision
     if (!have_next) {
       tm.start(&res.st.t_mvm_ms);
@@ -556,9 +558,13 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
           changed = true;
           continue;
         }
+        // only a column whose recursive residual claimed convergence and failed the check waits before
+        // its next check; a scheduled replacement leaves the others free to claim at the next iteration
         const bool was_candidate = it >= next_check[c] && std::sqrt(hrec[c]) / ynorm[c] <= tol;
-        next_check[c] = it + recheck;
-        if (was_candidate) ++stall[c];
+        if (was_candidate) {
+          next_check[c] = it + recheck;
+          ++stall[c];
+        }
         if (rel < best_rel[c]) {
           best_rel[c] = rel;
           imp[c] = 1;
@@ -572,10 +578,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       }
       if (improved) copy_columns(xbest.p, x, imp);
       if (changed) KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+      fresh_true = true;
     }
     any_active = false;
     for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
-    if (!any_active) break;
+    if (!any_active || it >= maxit) break;   // no next direction is needed after the last iteration
     precondition(r.p, z.p);
     red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
     hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, pp, z.p, beta, active.p, n, R);
@@ -587,7 +594,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // best iterate
   bool unfinished = false;
   for (int c = 0; c < R; ++c) unfinished |= act[c] != 0;
-  if (unfinished) {
+  if (unfinished && !fresh_true) {   // (after a check in the last iteration its residuals are current)
     Atrue->apply(x, betas, qq, s);
     res.st.n_mvm_fp64++;
     hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R);
