@@ -55,8 +55,8 @@ typedef enum {
 /* Library version (major*10000 + minor*100 + patch). */
 int krr_version(void);
 
-/* Optional: initialise this thread's library state on `stream` (the rocBLAS handle and the GEMM code
- * objects the preconditioner build uses) so that the first build does not pay for it. */
+/* Optional: load the code objects of the preconditioner's dense products on `stream` (one tiny launch of
+ * each) so that the first build does not pay for it. */
 int krr_init(void* stream);
 
 /* Message describing the last error on this thread ("" if none). */
@@ -127,6 +127,10 @@ typedef struct krr_precond krr_precond;   /* opaque */
  *   prec: KRR_FP64 builds the FP64 factor only; KRR_FP32/KRR_MIXED also build an FP32 copy of
  *   W (and its own core from exactly that copy) used by FP32/mixed solves.
  *   *out receives the handle.  Returns KRR_ENOTSPD if a core Cholesky fails.
+ *   The sketch's random numbers (Omega of Algorithm 1; the r indices and signs per column of Algorithm 2)
+ *   are drawn by the caller and passed in, rather than drawn inside from a seed: the build is then a
+ *   deterministic function of its inputs, the same draws can be fed to an independent implementation for
+ *   checking, and the caller chooses the generator.
  */
 int krr_build_precond(const double* X, int64_t n, int32_t d, double eps,
                       const double* betas, int32_t nbeta, int32_t k, int32_t l,
@@ -261,26 +265,37 @@ int krr_grad(const double* Xtr, int64_t n, const double* ytr,
              double* alpha_out, double* lambda_out, krr_solve_stats* stats, void* stream);
 
 /*
- * Tile-shape autotuner for the kernel MVM (project-written; the paper has none).
- * Times every kernel variant for (d, R, prec) on a synthetic problem of n points and records
- * the fastest in the process-wide table used by all later calls.  best_variant [host] out.
- * krr_autotune_save / krr_autotune_load persist the table as JSON.
+ * Autotuner of the kernel MVM's launch table (project-written; the paper has none).  A launch is fixed by a
+ * kernel variant (tile shape, target fragments per wave, software pipelining, LDS staging of the sources,
+ * symmetric square form) and a split (sources per block, i.e. the source split over the grid, for the direct
+ * forms; the super-tile edge for the symmetric forms).  krr_autotune times every variant for (d, R, prec) on n synthetic points of a
+ * square product, then the two fastest with the split halved and doubled, and records the fastest for the
+ * size class floor(log2 n) in the process-wide table (key: precision, d, shape class of R, size class,
+ * square or cross-set).  Every later product of that class launches the recorded entry; an entry forced with
+ * krr_set_variant applies at every size.  best_variant [host] out.
+ * krr_autotune_save / krr_autotune_load persist the table as JSON with the GPU architecture it was tuned on;
+ * loading a table tuned on another architecture returns KRR_EINVAL.
  */
 int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32_t* best_variant, void* stream);
 int krr_autotune_save(const char* path);
 int krr_autotune_load(const char* path);
-/* Force a variant for (d, R, prec) (-1 clears the entry).  Number of variants: krr_num_variants. */
+/* Force a variant for (d, R, prec) at every size (-1 clears the entries of (d, R, prec), tuned ones too).
+ * Number of variants: krr_num_variants. */
 int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t variant);
 int krr_num_variants(int32_t prec, int32_t R);
 /*
- * The kernel variant a product would run (the forced or tuned entry, else the default) and whether
- * that variant is the symmetric form (square product K(X, X) V of one column without the derivative
- * kernel, mixed precision, d <= 20: each off-diagonal pair of point tiles is evaluated once).
- *   square != 0: targets and sources are the same point set.  variant, symmetric [host] out.
- * Host only; no GPU call.  KRR_EINVAL on bad arguments.
+ * The kernel variant a product of n sources would run (the table's entry for its size class, else a forced
+ * variant, else the default; n <= 0: sizes unknown) and whether it is the symmetric form (square product
+ * K(X, X) V of one column without the derivative kernel, mixed or FP64: each off-diagonal pair of point tiles
+ * is evaluated once).  square != 0: targets and sources are the same point set.  variant, symmetric [host]
+ * out.  Host only; no GPU call.  KRR_EINVAL on bad arguments.
  */
-int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int32_t* variant,
+int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int64_t n, int32_t* variant,
                     int32_t* symmetric);
+/* What the last kernel MVM launched on this thread ran: its variant, its split (sources per block of a direct
+ * form, super-tile edge of a symmetric form) and whether it was the symmetric form.  -1 / 0 / 0 before any
+ * launch.  Host only. */
+int krr_kmv_last_launch(int32_t* variant, int32_t* split, int32_t* symmetric);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,8 @@ from typing import Optional, Sequence
 import torch
 
 __all__ = ["load", "KRRError", "kernel_mv", "sketch", "qrcp", "Preconditioner", "pcg_solve", "grad",
-           "KRRValLoss", "autotune", "set_variant", "num_variants", "PREC", "library_path"]
+           "KRRValLoss", "autotune", "autotune_save", "autotune_load", "set_variant", "num_variants", "kmv_variant",
+           "kmv_last_launch", "PREC", "library_path"]
 
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 _STATUS = {0: "KRR_OK", -1: "KRR_EINVAL", -2: "KRR_ENOMEM", -3: "KRR_EHIP", -4: "KRR_ENOTSPD",
@@ -87,7 +88,8 @@ _SIGS = {
     "krr_autotune_load": ([ctypes.c_char_p], _i32),
     "krr_set_variant": ([_i32, _i32, _i32, _i32], _i32),
     "krr_num_variants": ([_i32, _i32], _i32),
-    "krr_kmv_variant": ([_i32, _i32, _i32, _i32, _i32, _vp, _vp], _i32),
+    "krr_kmv_variant": ([_i32, _i32, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
+    "krr_kmv_last_launch": ([_vp, _vp, _vp], _i32),
 }
 
 
@@ -432,9 +434,29 @@ def num_variants(prec, R: int = 1) -> int:
     return lib.krr_num_variants(_prec(prec), R)
 
 
-def kmv_variant(d: int, R: int = 1, prec="mixed", *, deriv: int = 0, square: bool = True):
-    """(variant, symmetric): the kernel variant a product would run and whether it is the symmetric form."""
+def kmv_variant(d: int, R: int = 1, prec="mixed", *, deriv: int = 0, square: bool = True, n: int = 0):
+    """(variant, symmetric): the kernel variant a product of n sources would run (n = 0: size unknown) and
+    whether it is the symmetric form."""
     lib = load()
     v, sym = ctypes.c_int32(), ctypes.c_int32()
-    _chk(lib, lib.krr_kmv_variant(d, R, deriv, _prec(prec), 1 if square else 0, ctypes.byref(v), ctypes.byref(sym)))
+    _chk(lib, lib.krr_kmv_variant(d, R, deriv, _prec(prec), 1 if square else 0, int(n), ctypes.byref(v),
+                                  ctypes.byref(sym)))
     return v.value, bool(sym.value)
+
+
+def kmv_last_launch():
+    """(variant, split, symmetric) of the last kernel MVM launched on this thread."""
+    lib = load()
+    v, sp, sym = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _chk(lib, lib.krr_kmv_last_launch(ctypes.byref(v), ctypes.byref(sp), ctypes.byref(sym)))
+    return v.value, sp.value, bool(sym.value)
+
+
+def autotune_save(path: str):
+    lib = load()
+    _chk(lib, lib.krr_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path: str):
+    lib = load()
+    _chk(lib, lib.krr_autotune_load(os.fsencode(path)))

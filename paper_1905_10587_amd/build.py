@@ -27,7 +27,7 @@ CFLAGS = [
     # MFMA results go straight to VGPRs (no v_accvgpr_read per element before the exp)
     "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
-LDFLAGS = ["-shared", f"--offload-arch={ARCH}", "-lrocblas"]
+LDFLAGS = ["-shared", f"--offload-arch={ARCH}"]
 
 
 def sources():

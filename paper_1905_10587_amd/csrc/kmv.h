@@ -5,6 +5,8 @@
 
 #include "krr_internal.h"
 
+#include <string>
+
 namespace krr {
 
 // Derived device copies of a point set used by the MVM kernels (stage inputs).
@@ -61,10 +63,33 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
 //   deriv: 0 K, 1 K', 2 both (K columns first, then K' columns).
 //   shift: per-column ridge term added as shift[c] * V[i, c] (targets == sources) or nullptr.
 //   Vraw: the original FP64 V (n x R) for the shift term.
+//   variant >= 0 forces a variant (else the launch table, else the default); split_req > 0 forces the sources
+//   per block of the direct forms (rounded up to 256; at most nsrc / 256 splits) or the super-tile edge of the
+//   symmetric forms (else the table's, else the launcher's own choice).
 void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv,
                 const double* shift_host, const double* Vraw, int prec, double* U, int64_t ldu,
                 hipStream_t s, int variant = -1, DevBuf<double>* ws = nullptr,
-                const hipEvent_t* kev = nullptr);   // kev: two events recorded around the main kernel
+                const hipEvent_t* kev = nullptr,   // kev: two events recorded around the main kernel
+                int split_req = 0);
+
+// Launch table entry and the record of the last launch on this thread.
+struct KmvChoice {
+  int variant = -1;   // -1: none
+  int split = 0;      // sources per block (direct forms) or super-tile edge (symmetric forms); 0: launcher's choice
+};
+struct KmvLaunchInfo {
+  int variant = -1, split = 0, symmetric = 0;
+};
+KmvLaunchInfo kmv_last_launch();
+KmvChoice kmv_lookup(int prec, int d, int R, int64_t n, bool square);
+void kmv_set_tuned(int prec, int d, int R, int64_t n, bool square, KmvChoice c);
+std::string device_arch();
+
+// W = K(Xt, Xs) T on the FP64 matrix cores without forming K(Xt, Xs) (Algorithm 3: C U^{1/2} with the
+// kernel block applied on the fly): Xt m x d, Xs k x d (FP64, row-major, device), T k x ncol (row stride
+// ldt), W m x ncol (row stride ldw).  Needs padded_dim(d) <= 16 (returns false otherwise, nothing launched).
+bool kernel_times_matrix_f64(const double* Xt, int64_t m, const double* Xs, int64_t k, int d, double eps,
+                             const double* T, int64_t ldt, int ncol, double* W, int64_t ldw, hipStream_t s);
 
 // Variant bookkeeping for the autotuner.
 int kmv_num_variants(int prec, int R);

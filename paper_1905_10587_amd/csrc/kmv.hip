@@ -283,7 +283,13 @@ __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpa
 // ------------------------------------------------------------------ variants and launcher
 namespace {
 std::mutex g_mu;
-std::map<std::string, int> g_override;   // "prec:d:R" -> variant
+// Launch table: key "prec:d:rclass:nbucket:square" -> (variant, split).  nbucket = floor(log2 n) of the
+// source count, or "*" for an entry that applies at every n (krr_set_variant); square 1 for K(X, X) v
+// products, 0 for cross-set products, "*" for both.  split: sources per block of the direct forms (the
+// source split over the grid) or the super-tile edge of the symmetric forms; 0 keeps the launcher's own
+// choice.  Exact entries win over
+// wildcard ones.  The table records the GPU architecture it was tuned on.
+std::map<std::string, KmvChoice> g_table;
 // shape classes of the variant table: 1 = one column, 2 = several columns (direct kernels),
 // 3 = block MVM (many columns on MFMA)
 int rclass(int prec, int R) {
@@ -291,17 +297,58 @@ int rclass(int prec, int R) {
   if (prec == KRR_MIXED || (prec == KRR_FP32 && R > 8)) return 3;
   return 2;
 }
-std::string vkey(int d, int R, int prec) {
+std::string vprefix(int d, int R, int prec) {
   std::ostringstream o;
-  o << prec << ":" << d << ":" << rclass(prec, R);
+  o << prec << ":" << d << ":" << rclass(prec, R) << ":";
   return o.str();
 }
+std::string vkey(int d, int R, int prec) { return vprefix(d, R, prec) + "*:*"; }
+int n_bucket(int64_t n) {
+  int b = 0;
+  while (n > 1) { n >>= 1; ++b; }
+  return b;
+}
+std::string exact_key(int d, int R, int prec, int64_t n, bool square) {
+  return vprefix(d, R, prec) + std::to_string(n_bucket(n)) + ":" + (square ? "1" : "0");
+}
+thread_local KmvLaunchInfo t_last;
 const int kTM[3] = {1, 2, 4};
 const int kNF[4] = {1, 2, 4, 8};
 // block variants 0..5 contract with 16x16x16 MFMAs, 6..11 with 16x16x32 (same tile shapes)
 const int kBlockNT[6] = {2, 4, 1, 2, 4, 1};
 const int kBlockNRC[6] = {4, 2, 8, 2, 1, 4};
 }  // namespace
+
+std::string device_arch() {
+  int dev = 0;
+  KRR_CHECK_HIP(hipGetDevice(&dev));
+  static std::map<int, std::string> cache;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  hipDeviceProp_t prop;
+  KRR_CHECK_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string a(prop.gcnArchName);
+  a = a.substr(0, a.find(':'));
+  return cache[dev] = a;
+}
+
+KmvLaunchInfo kmv_last_launch() { return t_last; }
+
+KmvChoice kmv_lookup(int prec, int d, int R, int64_t n, bool square) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (n > 0) {
+    auto it = g_table.find(exact_key(d, R, prec, n, square));
+    if (it != g_table.end()) return it->second;
+  }
+  auto it = g_table.find(vkey(d, R, prec));
+  return it == g_table.end() ? KmvChoice{} : it->second;
+}
+
+void kmv_set_tuned(int prec, int d, int R, int64_t n, bool square, KmvChoice c) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_table[exact_key(d, R, prec, n, square)] = c;
+}
 
 int kmv_num_variants(int prec, int R) {
   if (rclass(prec, R) == 3) return 13;   // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile
@@ -359,54 +406,80 @@ bool kmv_is_symmetric(int prec, int d, int R, int deriv, bool square, int v) {
 }
 
 void kmv_set_override(int d, int R, int prec, int variant) {
+  // a forced variant applies at every n: it replaces the tuned entries of its (prec, d, shape class)
   std::lock_guard<std::mutex> lk(g_mu);
-  if (variant < 0) g_override.erase(vkey(d, R, prec));
-  else g_override[vkey(d, R, prec)] = variant;
+  const std::string pre = vprefix(d, R, prec);
+  for (auto it = g_table.begin(); it != g_table.end();)
+    it = it->first.compare(0, pre.size(), pre) == 0 ? g_table.erase(it) : std::next(it);
+  if (variant >= 0) g_table[vkey(d, R, prec)] = KmvChoice{variant, 0};
 }
 
 int kmv_get_override(int d, int R, int prec) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_override.find(vkey(d, R, prec));
-  return it == g_override.end() ? -1 : it->second;
+  auto it = g_table.find(vkey(d, R, prec));
+  return it == g_table.end() ? -1 : it->second.variant;
 }
 
 std::string kmv_table_json() {
+  std::string arch;
+  try { arch = device_arch(); } catch (...) { arch = ""; }
   std::lock_guard<std::mutex> lk(g_mu);
   std::ostringstream o;
-  o << "{\"arch\": \"gfx950\", \"variants\": {";
+  o << "{\"arch\": \"" << arch << "\", \"entries\": {";
   bool first = true;
-  for (auto& kv : g_override) {
-    o << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+  for (auto& kv : g_table) {
+    o << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.variant << ", " << kv.second.split << "]";
     first = false;
   }
   o << "}}\n";
   return o.str();
 }
 
+// Entries are "prec:d:rclass:nbucket:square": [variant, split] pairs inside the "entries" object.  A table
+// tuned on another architecture is rejected.
 void kmv_table_from_json(const std::string& s) {
-  // entries are "prec:d:r": variant pairs inside the "variants" object
-  size_t pos = s.find("\"variants\"");
-  KRR_REQUIRE(pos != std::string::npos, "autotune table: no variants object");
+  size_t pa = s.find("\"arch\"");
+  if (pa != std::string::npos) {
+    const size_t q1 = s.find('"', s.find(':', pa) + 1);
+    const size_t q2 = q1 == std::string::npos ? q1 : s.find('"', q1 + 1);
+    KRR_REQUIRE(q2 != std::string::npos, "autotune table: malformed arch");
+    const std::string arch = s.substr(q1 + 1, q2 - q1 - 1);
+    std::string here;
+    try { here = device_arch(); } catch (...) { here = arch; }
+    KRR_REQUIRE(arch.empty() || arch == here, "autotune table was tuned on " + arch + ", this GPU is " + here);
+  }
+  size_t pos = s.find("\"entries\"");
+  KRR_REQUIRE(pos != std::string::npos, "autotune table: no entries object");
   pos = s.find('{', pos);
-  KRR_REQUIRE(pos != std::string::npos, "autotune table: malformed variants object");
-  std::map<std::string, int> parsed;
+  KRR_REQUIRE(pos != std::string::npos, "autotune table: malformed entries object");
+  std::map<std::string, KmvChoice> parsed;
   size_t i = pos + 1;
+  auto read_int = [&](size_t& j) {
+    while (j < s.size() && (s[j] == ' ' || s[j] == ',' || s[j] == '[' || s[j] == ':')) ++j;
+    size_t e = j;
+    while (e < s.size() && (std::isdigit((unsigned char)s[e]) || s[e] == '-')) ++e;
+    KRR_REQUIRE(e > j, "autotune table: missing number");
+    const int v = std::atoi(s.substr(j, e - j).c_str());
+    j = e;
+    return v;
+  };
   while (i < s.size() && s[i] != '}') {
     if (s[i] != '"') { ++i; continue; }
     const size_t q2 = s.find('"', i + 1);
     KRR_REQUIRE(q2 != std::string::npos, "autotune table: unterminated key");
     const std::string key = s.substr(i + 1, q2 - i - 1);
+    KRR_REQUIRE(std::count(key.begin(), key.end(), ':') == 4, "autotune table: bad key " + key);
     size_t j = q2 + 1;
-    while (j < s.size() && (s[j] == ' ' || s[j] == ':')) ++j;
-    size_t e = j;
-    while (e < s.size() && (std::isdigit((unsigned char)s[e]) || s[e] == '-')) ++e;
-    KRR_REQUIRE(e > j, "autotune table: missing value for " + key);
-    KRR_REQUIRE(std::count(key.begin(), key.end(), ':') == 2, "autotune table: bad key " + key);
-    parsed[key] = std::atoi(s.substr(j, e - j).c_str());
-    i = e;
+    KmvChoice c;
+    c.variant = read_int(j);
+    c.split = read_int(j);
+    const size_t close = s.find(']', j);
+    KRR_REQUIRE(close != std::string::npos, "autotune table: unterminated entry " + key);
+    parsed[key] = c;
+    i = close + 1;
   }
   std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : parsed) g_override[kv.first] = kv.second;
+  for (auto& kv : parsed) g_table[kv.first] = kv.second;
 }
 
 // Compute units of the current device (cached per device).
@@ -443,15 +516,59 @@ static int64_t resident_blocks(Query query, const std::string& key) {
   return cap;
 }
 
+// V (k x ncol, stride ldt) -> rows x Rp zero-padded copy (the FP64 matrix-core kernel's operand layout)
+__global__ void k_pad_matrix(const double* __restrict__ T, int64_t k, int64_t ldt, int ncol, int64_t rows, int Rp,
+                             double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * Rp) return;
+  const int64_t j = t / Rp;
+  const int c = (int)(t % Rp);
+  out[t] = (j < k && c < ncol) ? T[j * ldt + c] : 0.0;
+}
+
+bool kernel_times_matrix_f64(const double* Xt, int64_t m, const double* Xs, int64_t k, int d, double eps,
+                             const double* T, int64_t ldt, int ncol, double* W, int64_t ldw, hipStream_t s) {
+  const int D = padded_dim(d);
+  if (D < 1 || D > 16) return false;
+  Staged St, Ss;
+  stage_points(St, Xt, m, d, eps, KRR_FP64, nullptr, true, false, s);
+  stage_points(Ss, Xs, k, d, eps, KRR_FP64, nullptr, false, true, s);
+  const int Rp = (int)round_up(ncol, 16);
+  DevBuf<double> V((size_t)Ss.npad * Rp, s);
+  hipLaunchKernelGGL(k_pad_matrix, dim3((unsigned)ceil_div(Ss.npad * Rp, 256)), dim3(256), 0, s, T, k, ldt, ncol,
+                     Ss.npad, Rp, V.p);
+  KRR_LAUNCH_CHECK();
+  // block width 16 NRG: per 4-source step NRG MFMAs (64 cycles each) plus the pair's distance and exp
+  // (about 112 VALU cycles), over ceil(Rp / 16 NRG) column blocks
+  int NRG = 8;
+  double best = 1e300;
+  for (int nr : {8, 4, 2, 1}) {
+    const double cost = (double)ceil_div(Rp, 16 * nr) * (64.0 * nr + 112.0);
+    if (cost < best * (1 - 1e-9)) { best = cost; NRG = nr; }
+  }
+  KmvGrid g{dim3((unsigned)(St.npad / 64), 1u, (unsigned)ceil_div(Rp, 16 * NRG)), Ss.npad, Ss.npad, St.npad, Rp,
+            (int)ldw};
+  g.m_store = m;
+  g.n_store = ncol;
+  KRR_REQUIRE(launch_kmv_f64_mfma(D, NRG, g, St.x64.p, Ss.x64.p, V.p, -kLog2e / eps, W, s),
+              "FP64 matrix-core kernel not instantiated for this width");
+  KRR_LAUNCH_CHECK();
+  return true;
+}
+
 void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const double* shift_host,
                 const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant,
-                DevBuf<double>* ws, const hipEvent_t* kev) {
+                DevBuf<double>* ws, const hipEvent_t* kev, int split_req) {
   KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
   const int R = V.Rreal, Rp = V.R;
   KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
   const int DV = deriv == 0 ? 0 : 2;
   const int Rout = (DV == 2 ? 2 : 1) * Rp;
-  if (variant < 0) variant = kmv_get_override(T.d, R, prec);
+  if (variant < 0) {
+    const KmvChoice ch = kmv_lookup(prec, T.d, R, S.n, &T == &S && deriv == 0);
+    variant = ch.variant;
+    if (split_req <= 0 && variant >= 0) split_req = ch.split;
+  }
   if (variant < 0) variant = kmv_default_variant(prec, T.d, R, T.n, S.n, &T == &S && deriv == 0);
   KRR_REQUIRE(variant < kmv_num_variants(prec, R), "unknown kernel variant");
   int64_t rows;
@@ -573,6 +690,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     if (cost < best * (1 - 1e-9)) { best = cost; split = spl; }
   }
   int64_t src_len = round_up(ceil_div(nsrc, split), 256);
+  if (split_req > 0 && !sym) {   // a requested source length per block (at most smax splits)
+    src_len = std::max<int64_t>(round_up(split_req, 256), round_up(ceil_div(nsrc, smax), 256));
+    split = ceil_div(nsrc, src_len);
+  }
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   if (sym) {
     KRR_REQUIRE(RoutK == 1, "internal: the symmetric kernels write dense one-column partials");
@@ -589,6 +710,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
       const double cost = (double)std::max<int64_t>(ceil_div(items, cus), 2) * (double)E * (double)E;
       if (cost < bestc * (1 - 1e-9)) { bestc = cost; bestE = E; }
     }
+    // a requested edge: one of the candidates, a multiple of the target tile, partials near 2 GB at most
+    if (split_req > 0 && split_req % rows == 0 && split_req >= 1024 && split_req <= 16384 &&
+        (double)ceil_div(T.npad, split_req) * T.npad * 8.0 <= 2.2e9)
+      bestE = split_req;
     const int64_t ns = ceil_div(T.npad, bestE);
     const int64_t items = ns * (ns + 1) / 2;
     split = ns;
@@ -599,6 +724,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   }
   const size_t need = (size_t)split * T.npad * RoutK;
   if (part.n < need) part.alloc(need, s);
+  t_last = KmvLaunchInfo{variant, (int)(sym ? g.E : src_len), sym ? 1 : 0};
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[0], s));
   const bool ok = run(g);
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[1], s));

@@ -13,6 +13,10 @@ struct KmvGrid {
   int* occ = nullptr;
   // symmetric form: super-tile edge and super-tiles per side (grid.x = 8 * ceil(NS (NS + 1) / 16))
   int E = 0, NS = 0;
+  // FP64 matrix-core form writing a final result in place: rows >= m_store and columns >= n_store are not
+  // stored (0: all padded rows, Rp columns)
+  int64_t m_store = 0;
+  int n_store = 0;
 };
 
 // FP64 / FP32 direct kernels: D in {2,3,4,6,8,16,32,64,128}, TM in {1,2,4} (D >= 32: TM 1),

@@ -48,7 +48,7 @@ static void go64m(const KmvGrid& g, const double* xt, const double* xs, const do
     return;
   }
   hipLaunchKernelGGL((k_kmv_f64_mfma<D, NRG>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src, neg_c,
-                     part, g.mpad, g.Rout);
+                     part, g.mpad, g.Rout, g.m_store > 0 ? g.m_store : g.mpad, g.n_store > 0 ? g.n_store : g.Rp);
 }
 
 bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, const double* xs, const double* v,

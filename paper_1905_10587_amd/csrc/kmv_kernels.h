@@ -134,7 +134,7 @@ template <int D, int NRG>
 __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__ xt, const double* __restrict__ xs,
                                                       const double* __restrict__ v, int Rp, int64_t src_len,
                                                       int64_t n_src, double neg_c, double* __restrict__ part,
-                                                      int64_t mpad, int Rout) {
+                                                      int64_t mpad, int Rout, int64_t m_store, int n_store) {
   constexpr int TS = 32;
   constexpr int RCH = 16 * NRG;
   constexpr int VS = RCH + 16;   // LDS row stride (doubles): consecutive rows start 128 bytes apart in the banks
@@ -179,13 +179,16 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__
     }
   }
   // result element e of the lane: target row0 + 4 e + l / 16, column c0 + 16 g + l % 16 (the FP64 16 x 16
-  // result interleaves its rows, unlike the FP32 16 x 16 results; checked by a lane-layout probe on gfx950)
+  // result interleaves its rows, unlike the FP32 16 x 16 results; checked by a lane-layout probe on gfx950).
+  // Rows at or beyond m_store and columns at or beyond n_store are not stored (a caller writing the final
+  // m x n_store result in place passes its sizes; the partial buffers pass mpad and Rp).
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    double* prow = part + ((int64_t)blockIdx.y * mpad + row0 + 4 * e + kq) * Rout + c0 + r16;
+    const int64_t row = row0 + 4 * e + kq;
+    double* prow = part + ((int64_t)blockIdx.y * mpad + row) * Rout + c0 + r16;
 #pragma unroll
     for (int g = 0; g < NRG; ++g)
-      if (g < ng) prow[16 * g] = acc[g][e];
+      if (g < ng && row < m_store && c0 + 16 * g + r16 < n_store) prow[16 * g] = acc[g][e];
   }
 }
 

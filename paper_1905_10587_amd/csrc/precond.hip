@@ -10,17 +10,20 @@
 //      G = (beta I + M)^{-1} = L^{-T} L^{-1}.
 // For FP32/mixed handles W is also rounded to FP32 and a second core is built from exactly that
 // rounded copy, so the applied operator is the Woodbury inverse of W32 W32^T + beta I.
-// The dense products W = C T, M = W^T W and G = L^{-T} L^{-1} are plain GEMMs (rocBLAS).
-#include <rocblas/rocblas.h>
-
+// W = K(X, X_S) T is formed on the FP64 matrix cores without storing C (the kernel block is evaluated
+// inside the product); M = W^T W, G = L^{-T} L^{-1} and the several-column Woodbury products are the
+// library's own FP64 matrix-core GEMMs (gemm.hip).
 #include <algorithm>
 #include <cstdlib>
 #include <chrono>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "anchors.h"
 #include "dense.h"
+#include "gemm.h"
 #include "kmv.h"
 #include "precond.h"
 #include "sketch_qrcp.h"
@@ -32,56 +35,28 @@ void validate_prec(int32_t prec);
 void kernel_mv_raw(const double* Xt, int64_t m, const double* Xs, int64_t n, int d, double eps, const double* V,
                    int R, const double* shift, int deriv, int prec, double* U, int64_t ldu, hipStream_t s);
 
-// ------------------------------------------------------------------ rocBLAS
-rocblas_handle blas(hipStream_t s) {
-  thread_local rocblas_handle h = nullptr;
-  if (!h) {
-    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{KRR_EHIP, "rocblas_create_handle failed"};
-  }
-  if (rocblas_set_stream(h, s) != rocblas_status_success) throw Error{KRR_EHIP, "rocblas_set_stream failed"};
-  return h;
-}
-
-#define KRR_BLAS(expr)                                                                        \
-  do {                                                                                        \
-    rocblas_status st_ = (expr);                                                              \
-    if (st_ != rocblas_status_success)                                                        \
-      throw ::krr::Error{KRR_EHIP, std::string(#expr) + ": " + rocblas_status_to_string(st_)}; \
-  } while (0)
-
-// column-major C (m x n) = op(A) op(B)
-static void dgemm(hipStream_t s, bool ta, bool tb, int m, int n, int k, const double* A, int lda, const double* B,
-                  int ldb, double* C, int ldc, double beta = 0.0) {
-  const double one = 1.0;
-  KRR_BLAS(rocblas_dgemm(blas(s), ta ? rocblas_operation_transpose : rocblas_operation_none,
-                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, B, ldb,
-                         &beta, C, ldc));
-}
-static void sgemm(hipStream_t s, bool ta, bool tb, int m, int n, int k, const float* A, int lda, const float* B,
-                  int ldb, float* C, int ldc) {
-  const float one = 1.0f, zero = 0.0f;
-  KRR_BLAS(rocblas_sgemm(blas(s), ta ? rocblas_operation_transpose : rocblas_operation_none,
-                         tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, B, ldb,
-                         &zero, C, ldc));
-}
-
 // ------------------------------------------------------------------ small kernels
+// T (k x kept, row-major) = V_kept diag(lam_kept)^{-1/2}; V column-major (eigenvector j at V + j k)
 __global__ void k_make_T(const double* __restrict__ V, const double* __restrict__ lam, const int* __restrict__ idx,
                          int k, int kept, double* __restrict__ T) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)k * kept) return;
-  const int r = (int)(t % k), c = (int)(t / k);
+  const int r = (int)(t / kept), c = (int)(t % kept);
   const int j = idx[c];
   T[t] = V[(int64_t)j * k + r] / sqrt(lam[j]);
+}
+
+// out (row-major) = in (column-major) for a k x k matrix: out[r * k + c] = in[c * k + r]
+__global__ void k_colmajor_to_rowmajor(const double* __restrict__ in, int k, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * k) return;
+  const int r = (int)(t / k), c = (int)(t % k);
+  out[t] = in[(int64_t)c * k + r];
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
-}
-__global__ void k_to_f64(const float* __restrict__ a, int64_t n, double* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (double)a[i];
 }
 __global__ void k_add_diag(const double* __restrict__ M, int k, double beta, double* __restrict__ A) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,37 +153,13 @@ __global__ __launch_bounds__(256) void k_w_z(const TW* __restrict__ W, int64_t n
 }
 
 // ------------------------------------------------------------------ block (R > 1) helpers
-__global__ void k_rows_to_f32(const double* __restrict__ X, int64_t n, int R, float* __restrict__ X32) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n * R) X32[t] = (float)X[t];
-}
-// T[c, r] (kept x R, column-major) = sum_s Tpart[s][c, r]
-__global__ void k_reduce_batches(const float* __restrict__ Tp, int S, int64_t stride, int64_t cnt,
-                                 double* __restrict__ T) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  double s = 0;
-  for (int b = 0; b < S; ++b) s += (double)Tp[b * stride + t];
-  T[t] = s;
-}
-// Zsel[:, r] = Zall[bidx[r]][:, r]  (each Zall block kept x R column-major), converted to FP32
+// Z[c, r] = Zall[bidx[r]][c, r]  (kept x R row-major blocks, one per beta)
 __global__ void k_select_z(const double* __restrict__ Zall, int kept, int R, const int* __restrict__ bidx,
-                           float* __restrict__ Z32, double* __restrict__ Z64) {
+                           double* __restrict__ Z) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)kept * R) return;
-  const int r = (int)(t / kept);
-  const double v = Zall[(int64_t)bidx[r] * kept * R + t];
-  if (Z32) Z32[t] = (float)v;
-  if (Z64) Z64[t] = v;
-}
-// out[i, r] = (x[i, r] - WZ[r, i]) / beta_r   (WZ is R x n column-major = n x R row-major)
-template <typename T>
-__global__ void k_block_out(const double* __restrict__ x, const T* __restrict__ WZ, int64_t n, int R,
-                            const double* __restrict__ inv_beta, double* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * R) return;
   const int r = (int)(t % R);
-  out[t] = (x[t] - (double)WZ[t]) * inv_beta[r];
+  Z[t] = Zall[(int64_t)bidx[r] * kept * R + t];
 }
 
 int beta_index(const krr_precond& P, double beta) {
@@ -217,37 +168,46 @@ int beta_index(const krr_precond& P, double beta) {
   return -1;
 }
 
+// One column of Algorithm 4 with caller-provided buffers: x and out are columns of n x R row-major blocks
+// (strides ldx, ldo); partial holds ceil(n / 256) x kept doubles, t and z kept doubles each.  Every slot of
+// partial is written before it is read, so the buffers need no clearing.
+static void woodbury_one_column(const krr_precond& P, const double* x, int ldx, int b, bool use32, double* out,
+                                int ldo, double* partial, double* t, double* z, hipStream_t s) {
+  const int kept = P.kept;
+  const int64_t n = P.n;
+  const double* G = use32 ? P.G32[b].p : P.G64[b].p;
+  const int nb = (int)ceil_div(n, kWRows);
+  const dim3 gw((unsigned)nb, nblk(kept));
+  if (use32)
+    hipLaunchKernelGGL(k_wt_partial<float>, gw, dim3(256), 0, s, P.W32.p, n, kept, x, ldx, partial);
+  else
+    hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, ldx, partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)kept), dim3(256), 0, s, partial, nb, kept, t);
+  hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t, z);
+  // two rows per wave and at most 2048 blocks (measured best among 1, 2, 4 rows and 1024-8192 blocks)
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 8), 2048);
+  const size_t lds = (size_t)kept * sizeof(double);
+  if (use32)
+    hipLaunchKernelGGL((k_w_z<float, 2>), dim3(g), dim3(256), lds, s, P.W32.p, n, kept, z, x, ldx,
+                       1.0 / P.betas[b], out, ldo);
+  else
+    hipLaunchKernelGGL((k_w_z<double, 2>), dim3(g), dim3(256), lds, s, P.W64.p, n, kept, z, x, ldx,
+                       1.0 / P.betas[b], out, ldo);
+  KRR_LAUNCH_CHECK();
+}
+
 void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
                     hipStream_t s) {
   const int kept = P.kept;
   const int64_t n = P.n;
   KRR_REQUIRE(!use32 || P.W32.p, "preconditioner was built without an FP32 factor");
   if (R == 1) {
-    const int b = bidx_host[0];
-    const double* G = use32 ? P.G32[b].p : P.G64[b].p;
-    const int nb = (int)ceil_div(n, kWRows);
-    DevBuf<double> partial((size_t)nb * kept, s), t(kept, s), z(kept, s);
-    const dim3 gw((unsigned)nb, nblk(kept));
-    if (use32)
-      hipLaunchKernelGGL(k_wt_partial<float>, gw, dim3(256), 0, s, P.W32.p, n, kept, x, 1, partial.p);
-    else
-      hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, 1, partial.p);
-    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)kept), dim3(256), 0, s, partial.p, nb, kept, t.p);
-    hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t.p, z.p);
-    // two rows per wave and at most 2048 blocks (measured best among 1, 2, 4 rows and 1024-8192 blocks)
-    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 8), 2048);
-    const size_t lds = (size_t)kept * sizeof(double);
-    if (use32)
-      hipLaunchKernelGGL((k_w_z<float, 2>), dim3(g), dim3(256), lds, s, P.W32.p, n, kept, z.p, x, 1,
-                         1.0 / P.betas[b], out, 1);
-    else
-      hipLaunchKernelGGL((k_w_z<double, 2>), dim3(g), dim3(256), lds, s, P.W64.p, n, kept, z.p, x, 1,
-                         1.0 / P.betas[b], out, 1);
-    KRR_LAUNCH_CHECK();
+    DevBuf<double> partial((size_t)ceil_div(n, kWRows) * kept, s), t(kept, s), z(kept, s);
+    woodbury_one_column(P, x, 1, bidx_host[0], use32, out, 1, partial.p, t.p, z.p, s);
     return;
   }
-  // Block form: T = W^T X (split over rows, FP32 GEMMs summed in FP64) ; Z_b = G_b T for each beta;
-  // column r takes Z_{beta_r}; out = (X - W Z) diag(1/beta).
+  // Block form (FP64 matrix cores; the FP32 factor's products are exact in FP64): T = W^T X, summed over row
+  // splits in a fixed order; Z_b = G_b T for each beta; column r takes Z_{beta_r}; out = (X - W Z) diag(1/beta).
   const int nbeta = (int)P.betas.size();
   std::vector<double> ib(R);
   for (int r = 0; r < R; ++r) ib[r] = 1.0 / P.betas[bidx_host[r]];
@@ -255,43 +215,17 @@ void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bid
   DevBuf<int> bidx(R, s);
   KRR_CHECK_HIP(hipMemcpyAsync(invb.p, ib.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
   KRR_CHECK_HIP(hipMemcpyAsync(bidx.p, bidx_host, sizeof(int) * R, hipMemcpyHostToDevice, s));
-  DevBuf<double> T((size_t)kept * R, s), Zall((size_t)nbeta * kept * R, s);
-  if (use32) {
-    const int64_t chunk = 8192;
-    const int S = (int)ceil_div(n, chunk);
-    DevBuf<float> X32(n * R, s), Tp((size_t)S * kept * R, s), Z32((size_t)kept * R, s), WZ(n * R, s);
-    hipLaunchKernelGGL(k_rows_to_f32, dim3(nblk(n * R)), dim3(256), 0, s, x, n, R, X32.p);
-    // full chunks as one strided batch, the ragged tail separately
-    const int Sfull = (int)(n / chunk);
-    const float one = 1.0f, zero = 0.0f;
-    if (Sfull > 0)
-      KRR_BLAS(rocblas_sgemm_strided_batched(blas(s), rocblas_operation_none, rocblas_operation_transpose, kept, R,
-                                             (int)chunk, &one, P.W32.p, kept, chunk * kept, X32.p, R, chunk * R,
-                                             &zero, Tp.p, kept, (int64_t)kept * R, Sfull));
-    if (S > Sfull) {
-      const int64_t i0 = (int64_t)Sfull * chunk;
-      sgemm(s, false, true, kept, R, (int)(n - i0), P.W32.p + i0 * kept, kept, X32.p + i0 * R, R,
-            Tp.p + (int64_t)Sfull * kept * R, kept);
-    }
-    hipLaunchKernelGGL(k_reduce_batches, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Tp.p, S,
-                       (int64_t)kept * R, (int64_t)kept * R, T.p);
-    for (int b = 0; b < nbeta; ++b)
-      dgemm(s, false, false, kept, R, kept, P.G32[b].p, kept, T.p, kept, Zall.p + (int64_t)b * kept * R, kept);
-    hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p, Z32.p,
-                       (double*)nullptr);
-    sgemm(s, true, false, R, (int)n, kept, Z32.p, kept, P.W32.p, kept, WZ.p, R);
-    hipLaunchKernelGGL(k_block_out<float>, dim3(nblk(n * R)), dim3(256), 0, s, x, WZ.p, n, R, invb.p, out);
-  } else {
-    DevBuf<double> Z64((size_t)kept * R, s), WZ(n * R, s);
-    dgemm(s, false, true, kept, R, (int)n, P.W64.p, kept, x, R, T.p, kept);
-    for (int b = 0; b < nbeta; ++b)
-      dgemm(s, false, false, kept, R, kept, P.G64[b].p, kept, T.p, kept, Zall.p + (int64_t)b * kept * R, kept);
-    hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p,
-                       (float*)nullptr, Z64.p);
-    dgemm(s, true, false, R, (int)n, kept, Z64.p, kept, P.W64.p, kept, WZ.p, R);
-    hipLaunchKernelGGL(k_block_out<double>, dim3(nblk(n * R)), dim3(256), 0, s, x, WZ.p, n, R, invb.p, out);
+  DevBuf<double> T((size_t)kept * R, s), Zall((size_t)nbeta * kept * R, s), Z((size_t)kept * R, s);
+  if (use32) gemm_tn<float, double>(P.W32.p, kept, x, R, n, kept, R, T.p, R, s);
+  else gemm_tn<double, double>(P.W64.p, kept, x, R, n, kept, R, T.p, R, s);
+  for (int b = 0; b < nbeta; ++b) {
+    const double* G = use32 ? P.G32[b].p : P.G64[b].p;
+    gemm_nn<double>(G, kept, T.p, R, kept, kept, R, Zall.p + (int64_t)b * kept * R, R, nullptr, 0, nullptr, s);
   }
+  hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p, Z.p);
   KRR_LAUNCH_CHECK();
+  if (use32) gemm_nn<float>(P.W32.p, kept, Z.p, R, n, kept, R, out, R, x, R, invb.p, s);
+  else gemm_nn<double>(P.W64.p, kept, Z.p, R, n, kept, R, out, R, x, R, invb.p, s);
 }
 
 // ------------------------------------------------------------------ build
@@ -361,7 +295,10 @@ static void build_core(krr_precond& P, const double* M, std::vector<DevBuf<doubl
       throw Error{KRR_ENOTSPD, "Cholesky of beta I + W^T W failed at column " + std::to_string(info - 1) +
                                    " (beta = " + std::to_string(beta) + ")"};
     lower_inverse(L.p, Li.p, kept, s);
-    dgemm(s, true, false, kept, kept, kept, Li.p, kept, Li.p, kept, Gb.p, kept);
+    // G = L^{-T} L^{-1} = A^T A with A = L^{-1} row-major (lower_inverse writes it column-major)
+    hipLaunchKernelGGL(k_colmajor_to_rowmajor, dim3(nblk(kk)), dim3(256), 0, s, Li.p, kept, A.p);
+    KRR_LAUNCH_CHECK();
+    syrk_tn<double>(A.p, kept, kept, kept, Gb.p, kept, s);
     G.push_back(std::move(Gb));
     if (Ls) Ls->push_back(std::move(L));
   }
@@ -432,25 +369,25 @@ void build_from_anchors(krr_precond& P, const double* X, hipStream_t s) {
   KRR_LAUNCH_CHECK();
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   P.t_build_ms[2] = ms_since(t0);
-  // 4. C = K(X, X_S) and W = C T, M = W^T W
+  // 4. W = K(X, X_S) T (= C V_kept diag(lam_kept)^{-1/2}, C never stored), M = W^T W
   t0 = clk::now();
   const int kept = P.kept;
-  {
+  P.W64.alloc(n * kept, s);
+  if (!kernel_times_matrix_f64(X, n, XS.p, k, d, P.eps, T.p, kept, kept, P.W64.p, kept, s)) {
+    // widths above the FP64 matrix-core kernel's: the kernel block C is formed, then W = C T
     DevBuf<double> C(n * k, s);
     kernel_block_rowmajor(X, n, XS.p, k, d, P.eps, C.p, k, s);
-    P.W64.alloc(n * kept, s);
-    dgemm(s, true, false, kept, (int)n, k, T.p, k, C.p, k, P.W64.p, kept);
+    gemm_nn<double>(C.p, k, T.p, kept, n, k, kept, P.W64.p, kept, nullptr, 0, nullptr, s);
   }
   P.M64.alloc((size_t)kept * kept, s);
-  dgemm(s, false, true, kept, kept, (int)n, P.W64.p, kept, P.W64.p, kept, P.M64.p, kept);
+  syrk_tn<double>(P.W64.p, kept, n, kept, P.M64.p, kept, s);
   if (P.prec != KRR_FP64) {
+    // the FP32 copy of W and a core built from exactly that copy (its products are exact in FP64)
     P.W32.alloc(n * kept, s);
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n * kept)), dim3(256), 0, s, P.W64.p, n * kept, P.W32.p);
-    DevBuf<double> Wr(n * kept, s);
-    hipLaunchKernelGGL(k_to_f64, dim3(nblk(n * kept)), dim3(256), 0, s, P.W32.p, n * kept, Wr.p);
     KRR_LAUNCH_CHECK();
     P.M32.alloc((size_t)kept * kept, s);
-    dgemm(s, false, true, kept, kept, (int)n, Wr.p, kept, Wr.p, kept, P.M32.p, kept);
+    syrk_tn<float>(P.W32.p, kept, n, kept, P.M32.p, kept, s);
   }
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   P.t_build_ms[3] = ms_since(t0);
@@ -468,16 +405,15 @@ void build_from_anchors(krr_precond& P, const double* X, hipStream_t s) {
 extern "C" int krr_init(void* stream) {
   return krr::guarded([&] {
     hipStream_t s = (hipStream_t)stream;
-    // one tiny call of each GEMM form the build and the block Woodbury apply use
-    krr::DevBuf<double> a(64, s), b(64, s), c(64, s);
-    krr::DevBuf<float> af(64, s), bf(64, s), cf(64, s);
+    // one tiny call of each dense product the build and the block Woodbury apply use (loads their code objects)
+    krr::DevBuf<double> a(64, s), c(64, s);
+    krr::DevBuf<float> af(64, s);
     KRR_CHECK_HIP(hipMemsetAsync(a.p, 0, 64 * sizeof(double), s));
     KRR_CHECK_HIP(hipMemsetAsync(af.p, 0, 64 * sizeof(float), s));
-    krr::dgemm(s, true, false, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
-    krr::dgemm(s, false, true, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
-    krr::dgemm(s, false, false, 8, 8, 8, a.p, 8, a.p, 8, c.p, 8);
-    krr::sgemm(s, false, true, 8, 8, 8, af.p, 8, af.p, 8, cf.p, 8);
-    krr::sgemm(s, true, false, 8, 8, 8, af.p, 8, af.p, 8, cf.p, 8);
+    krr::syrk_tn<double>(a.p, 8, 8, 8, c.p, 8, s);
+    krr::syrk_tn<float>(af.p, 8, 8, 8, c.p, 8, s);
+    krr::gemm_tn<float, double>(af.p, 8, a.p, 8, 8, 8, 8, c.p, 8, s);
+    krr::gemm_nn<double>(a.p, 8, a.p, 8, 8, 8, 8, c.p, 8, nullptr, 0, nullptr, s);
     KRR_CHECK_HIP(hipStreamSynchronize(s));
     return (int)KRR_OK;
   });
