@@ -1,8 +1,11 @@
-// C ABI: kernel-variant control and the tile-shape autotuner (the table consulted by every kernel MVM
-// launch).  The autotuner times each variant of (d, R, prec) on synthetic points with HIP events and
-// keeps the fastest; the table can be saved and loaded as JSON.
+// C ABI: kernel-variant control and the autotuner of the kernel MVM's launch table (consulted by every kernel
+// MVM launch).  The autotuner times the variants (tile shapes, fragments per wave, pipelining, LDS staging,
+// symmetric form) and source splits / super-tile edges of (d, R, prec) at a problem size n with HIP events
+// and keeps the fastest for that size class; the table can be saved and loaded as JSON.
+#include <algorithm>
 #include <fstream>
 #include <sstream>
+#include <vector>
 
 #include "kmv.h"
 
@@ -33,22 +36,39 @@ extern "C" int krr_set_variant(int32_t d, int32_t R, int32_t prec, int32_t varia
 
 extern "C" int krr_num_variants(int32_t prec, int32_t R) { return krr::kmv_num_variants(prec, R); }
 
-extern "C" int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int32_t* variant,
-                               int32_t* symmetric) {
+extern "C" int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int64_t n,
+                               int32_t* variant, int32_t* symmetric) {
   return krr::guarded([&] {
     KRR_REQUIRE(d >= 1 && d <= KRR_MAX_D, "d must be in [1, KRR_MAX_D]");
     KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
     KRR_REQUIRE(deriv >= 0 && deriv <= 2, "deriv must be 0, 1 or 2");
     KRR_REQUIRE(prec >= KRR_FP64 && prec <= KRR_MIXED, "unknown precision");
     KRR_REQUIRE(variant && symmetric, "null output pointer");
-    int v = krr::kmv_get_override(d, R, prec);
-    if (v < 0) v = krr::kmv_default_variant(prec, d, R, 0, 0, square != 0 && deriv == 0);
+    const bool sq = square != 0 && deriv == 0;
+    int v = krr::kmv_lookup(prec, d, R, n, sq).variant;
+    if (v < 0) v = krr::kmv_default_variant(prec, d, R, n > 0 ? n : 0, n > 0 ? n : 0, sq);
     *variant = v;
     *symmetric = krr::kmv_is_symmetric(prec, d, R, deriv, square != 0, v) ? 1 : 0;
     return (int)KRR_OK;
   });
 }
 
+extern "C" int krr_kmv_last_launch(int32_t* variant, int32_t* split, int32_t* symmetric) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(variant && split && symmetric, "null output pointer");
+    const krr::KmvLaunchInfo li = krr::kmv_last_launch();
+    *variant = li.variant;
+    *split = li.split;
+    *symmetric = li.symmetric;
+    return (int)KRR_OK;
+  });
+}
+
+// Search for square products K(X, X) V of n points (the solver's case): every variant at the launcher's own
+// split, then the two fastest with the split halved and doubled (sources per block of the direct forms, the
+// super-tile edge of the symmetric forms).  Each candidate: one warm-up launch, then up to three timed
+// launches (stopped after one when it is already three times slower than the best).  The winner is recorded
+// for (prec, d, shape class of R, floor(log2 n), square).
 extern "C" int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32_t* best_variant, void* stream) {
   using namespace krr;
   return guarded([&] {
@@ -74,23 +94,51 @@ extern "C" int krr_autotune(int32_t d, int32_t R, int32_t prec, int64_t n, int32
     hipEvent_t e0, e1;
     KRR_CHECK_HIP(hipEventCreate(&e0));
     KRR_CHECK_HIP(hipEventCreate(&e1));
+    struct EvGuard {
+      hipEvent_t a, b;
+      ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } guard{e0, e1};
     float best = 1e30f;
-    int bestv = 0;
+    auto time_one = [&](int v, int split, int* used_split) -> float {
+      kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws, nullptr, split);   // warm-up
+      *used_split = kmv_last_launch().split;
+      float tot = 0;
+      int reps = 0;
+      for (; reps < 3; ++reps) {
+        KRR_CHECK_HIP(hipEventRecord(e0, s));
+        kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws, nullptr, split);
+        KRR_CHECK_HIP(hipEventRecord(e1, s));
+        KRR_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        KRR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tot += ms;
+        if (ms > 3.0f * best) { ++reps; break; }
+      }
+      return tot / reps;
+    };
     const int nv = kmv_num_variants(prec, R);
+    std::vector<std::pair<float, std::pair<int, int>>> res;   // (ms, (variant, split))
     for (int v = 0; v < nv; ++v) {
-      kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws);   // warm-up
-      KRR_CHECK_HIP(hipEventRecord(e0, s));
-      for (int rep = 0; rep < 3; ++rep) kmv_launch(S, S, SV, 0, nullptr, V.p, prec, U.p, R, s, v, &ws);
-      KRR_CHECK_HIP(hipEventRecord(e1, s));
-      KRR_CHECK_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      KRR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) { best = ms; bestv = v; }
+      int used = 0;
+      const float ms = time_one(v, 0, &used);
+      res.push_back({ms, {v, used}});
+      best = std::min(best, ms);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    kmv_set_override(d, R, prec, bestv);
-    *best_variant = bestv;
+    std::sort(res.begin(), res.end());
+    KmvChoice win{res[0].second.first, 0};
+    float win_ms = res[0].first;
+    for (size_t t = 0; t < std::min<size_t>(2, res.size()); ++t) {
+      const int v = res[t].second.first, sp0 = res[t].second.second;
+      for (int sp : {sp0 / 2, sp0 * 2}) {
+        if (sp < 1) continue;
+        int used = 0;
+        const float ms = time_one(v, sp, &used);
+        if (used == sp0) continue;   // the launcher would not take this split: nothing new was timed
+        if (ms < win_ms) { win_ms = ms; win = KmvChoice{v, used}; }
+      }
+    }
+    kmv_set_tuned(prec, d, R, n, true, win);
+    *best_variant = win.variant;
     return (int)KRR_OK;
   });
 }

@@ -67,7 +67,7 @@ def test_variant_table_roundtrip(lib, tmp_path):
     krr._chk(L, L.krr_autotune_load(str(a).encode()))
     krr._chk(L, L.krr_autotune_save(str(b).encode()))
     assert a.read_text() == b.read_text()
-    assert '"2:4:1": 3' in a.read_text()
+    assert '"2:4:1:*:*": [3, 0]' in a.read_text()
     assert L.krr_set_variant(4, 1, 2, 99) == -1          # out of range
 
 
@@ -107,6 +107,30 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(8, 1, "mixed", square=False) == (11, False)
     krr.set_variant(8, 1, "mixed", -1)
     v, s = ctypes.c_int32(), ctypes.c_int32()
-    assert L.krr_kmv_variant(0, 1, 0, 2, 1, ctypes.byref(v), ctypes.byref(s)) == -1
-    assert L.krr_kmv_variant(8, 1, 3, 2, 1, ctypes.byref(v), ctypes.byref(s)) == -1
-    assert L.krr_kmv_variant(8, 1, 0, 2, 1, None, ctypes.byref(s)) == -1
+    assert L.krr_kmv_variant(0, 1, 0, 2, 1, 0, ctypes.byref(v), ctypes.byref(s)) == -1
+    assert L.krr_kmv_variant(8, 1, 3, 2, 1, 0, ctypes.byref(v), ctypes.byref(s)) == -1
+    assert L.krr_kmv_variant(8, 1, 0, 2, 1, 0, None, ctypes.byref(s)) == -1
+
+
+def test_launch_table_size_classes(lib, tmp_path):
+    """A tuned entry applies to its size class (floor(log2 n)) and square/cross-set kind only; a forced
+    variant (krr_set_variant) replaces the tuned entries of its (prec, d, shape class) at every size."""
+    import paper_1905_10587_amd as krr
+    L = krr.load()
+    L.krr_set_variant(4, 1, 2, -1)
+    f = tmp_path / "t.json"
+    f.write_text('{"arch": "", "entries": {"2:4:1:19:1": [9, 2048], "2:4:1:16:0": [2, 3]}}')
+    krr.autotune_load(str(f))
+    assert krr.kmv_variant(4, 1, "mixed", square=True, n=1_000_000) == (9, False)    # 2^19 <= n < 2^20
+    assert krr.kmv_variant(4, 1, "mixed", square=True, n=600_000) == (9, False)
+    assert krr.kmv_variant(4, 1, "mixed", square=True, n=1_100_000) == (11, True)    # other class: default
+    assert krr.kmv_variant(4, 1, "mixed", square=False, n=1_000_000) == (3, False)   # cross-set: default
+    assert krr.kmv_variant(4, 1, "mixed", square=False, n=70_000) == (2, False)
+    krr.set_variant(4, 1, "mixed", 8)                                                 # forced: every size
+    assert krr.kmv_variant(4, 1, "mixed", square=True, n=1_000_000) == (8, False)
+    assert krr.kmv_variant(4, 1, "mixed", square=False, n=70_000) == (8, False)
+    krr.set_variant(4, 1, "mixed", -1)
+    assert krr.kmv_variant(4, 1, "mixed", square=True, n=1_000_000) == (11, True)
+    f.write_text('{"arch": "", "entries": {"2:4:1:19": [9, 0]}}')                     # malformed key
+    with pytest.raises(krr.KRRError):
+        krr.autotune_load(str(f))

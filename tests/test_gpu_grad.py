@@ -78,11 +78,3 @@ def test_autograd_function(gpu_lib):
     L, ge, gb, _, _ = oa.val_loss_grad(Xtr, ytr, Xv, yv, 0.1, 1e-2)
     assert _rel(loss.item(), L) <= 1e-8
     assert _rel(le.grad.item(), ge) <= 1e-6 and _rel(lb.grad.item(), gb) <= 1e-6
-
-
-@pytest.mark.gpu
-def test_autotune_picks_a_valid_variant(gpu_lib):
-    for prec, R in (("mixed", 1), ("fp64", 1), ("mixed", 32)):
-        v = gpu_lib.autotune(4, R, prec, n=16384)
-        assert 0 <= v < gpu_lib.num_variants(prec, R)
-        gpu_lib.set_variant(4, R, prec, -1)
