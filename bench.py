@@ -289,6 +289,18 @@ def mvm_roofline(prec, d, R, n, avg_ms, launches, variant, sym, traffic):
     return rec
 
 
+def load_launch_table(krr, torch):
+    """The kernel MVM launch table tuned for this GPU (paper_1905_10587_amd/tuned/<arch>.json, written by
+    python -m paper_1905_10587_amd.tune), if present; its path, else None (the launcher's defaults)."""
+    from paper_1905_10587_amd import tune
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = tune.table_path(arch)
+    if not os.path.exists(path):
+        return None
+    krr.autotune_load(path)
+    return os.path.relpath(path, ROOT)
+
+
 def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
     """Default benchmark: the n = 1,000,000, d = 4 mixed-precision solve.  A step is one replacement cycle of
     its PCG (Algorithm 5): replace_every mixed iterations (split-BF16 MFMA cross term, FP32 exp, Woodbury
@@ -299,6 +311,10 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
     prec, rep = "mixed", 10
     beta = float(wl.betas[0])
     n = wl.n
+    table = load_launch_table(krr, torch)
+    # one product first: the launch the solve's MVMs take (variant, split) is read back from the library
+    krr.kernel_mv(Xg, None, wl.eps, Yg, shift=beta, prec=prec)
+    launched = dict(zip(("variant", "split", "symmetric"), krr.kmv_last_launch()))
     # warm-up build on a slice (first use of the build's kernels), not timed
     m0 = min(n, 16384)
     import datagen
@@ -307,10 +323,15 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
                        sign=torch.from_numpy(sign0).to(Xg.device), prec=prec)
     torch.cuda.synchronize()
     log(f"bench: building the preconditioner (k={wl.k}, l={wl.l}, r={wl.r})")
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.perf_counter()
     P = krr.Preconditioner(Xg, wl.eps, [beta], wl.k, wl.l, prec=prec, **sk)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    # device memory the build held at its peak beyond the resident inputs (all of it comes through torch's
+    # caching allocator)
+    build_peak_gb = round((torch.cuda.max_memory_allocated() - base) / 1e9, 2)
     phases = {k: round(v, 1) for k, v in P.timings().items()}
     log(f"bench: build {build_s:.3f} s {phases}")
 
@@ -363,6 +384,9 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
                           "woodbury": round(tot["t_precond_ms"] / a.steps, 2)},
         "build_s": round(build_s, 3),
         "build_phases_ms": phases,
+        "build_peak_gb": build_peak_gb,
+        "launch_table": table,
+        "mixed_mvm_launch": launched,
         "mvm_gpairs_s": round(float(n) * n / avg_ms / 1e6, 1),
         "roofline": mvm_roofline(prec, wl.d, 1, n, avg_ms, tot["n_mvm"], variant, sym,
                                  None if traffic is None else traffic["hbm_bytes_per_launch"]),
@@ -379,8 +403,9 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
         v2, s2 = krr.kmv_variant(wl.d, 1, p2, square=True) if p2 == "fp64" else (None, False)
         out[f"{p2}_cycle"] = {"s": round(dt, 3), "iterations": max(its2), "n_mvm": st2["n_mvm"],
                               "n_mvm_fp64": st2["n_mvm_fp64"], "mvm_kernel_ms": round(k_ms, 3),
-                              "mvm_gpairs_s": round(float(n) * n / k_ms / 1e6, 1),
-                              "roofline": mvm_roofline(p2, wl.d, 1, n, k_ms, st2["n_mvm"], v2, s2, None)}
+                              "mvm_gpairs_s": round(float(n) * n / k_ms / 1e6, 1)}
+        if p2 == "fp64":   # the FP64 form's VALU bound (its operation count is fixed by its arithmetic)
+            out[f"{p2}_cycle"]["roofline"] = mvm_roofline(p2, wl.d, 1, n, k_ms, st2["n_mvm"], v2, s2, None)
         out[f"mvm_gpairs_s_{p2}"] = out[f"{p2}_cycle"]["mvm_gpairs_s"]
         log(f"bench: {p2} cycle {dt:.3f} s, MVM kernel {k_ms:.2f} ms")
     out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
@@ -438,7 +463,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-full-solve", action="store_true", help="mixed workload: skip the full solve after "
                                                                  "the timed cycles")
-    ap.add_argument("--budget-s", type=float, default=480.0,
+    ap.add_argument("--budget-s", type=float, default=525.0,
                     help="wall-clock budget of the whole run; caps the full solve's iterations")
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--kernels-only", action="store_true",
