@@ -56,7 +56,8 @@ typedef enum {
 int krr_version(void);
 
 /* Optional: load the code objects of the preconditioner's dense products on `stream` (one tiny launch of
- * each) so that the first build does not pay for it. */
+ * each) so that the first build does not pay for it, and look up this device's address of the scratch
+ * array of krr_precond_apply_noalloc. */
 int krr_init(void* stream);
 
 /* Message describing the last error on this thread ("" if none). */
@@ -206,6 +207,20 @@ int krr_precond_get(const krr_precond* P, int32_t what, int32_t bidx, void* dst,
  */
 int krr_precond_apply(const krr_precond* P, const double* x, int32_t R, const double* betas,
                       int32_t prec, double* out, void* stream);
+
+/*
+ * krr_precond_apply without device allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments and result as
+ * krr_precond_apply; the columns are applied one at a time with the one-column kernels, so for R > 1 the
+ * rounding differs from krr_precond_apply's several-column products.  Scratch (ceil(n / 256) * kept + 2 * kept
+ * doubles: the W^T x partial sums, t and z) lives in a 64 MiB device array that the library holds on every
+ * GPU it runs on until the process ends; larger preconditioners return KRR_EINVAL before any GPU work.
+ * Nothing is allocated and no library routine that allocates is called.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.  The array is found once per device (in krr_init, or at the first call on that device).
+ */
+int krr_precond_apply_noalloc(const krr_precond* P, const double* x, int32_t R, const double* betas,
+                              int32_t prec, double* out, void* stream);
 
 void krr_precond_free(krr_precond* P);
 

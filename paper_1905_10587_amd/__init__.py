@@ -78,6 +78,7 @@ _SIGS = {
     "krr_precond_get": ([_vp, _i32, _i32, _vp, _sz, _vp], _i32),
     "krr_precond_timings": ([_vp, _vp, _vp], _i32),
     "krr_precond_apply": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
+    "krr_precond_apply_noalloc": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
     "krr_precond_free": ([_vp], None),
     "krr_pcg_solve": ([_vp, _i64, _i32, _f64, _vp, _i32, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp, _vp, _vp,
                        _i32, _vp], _i32),
@@ -328,6 +329,23 @@ class Preconditioner:
                                                     self.prec if prec is None else _prec(prec), _p(out),
                                                     _stream()))
         return out[:, 0] if vec else out
+
+    def apply_noalloc(self, x, out, betas=None, prec=None):
+        """The Woodbury apply into the caller's `out` (n or n x R FP64 on the device, same shape as x) through
+        krr_precond_apply_noalloc: the library allocates nothing (its scratch is a fixed device array)."""
+        vec = x.dim() == 1
+        x2 = x.reshape(x.shape[0], -1)
+        R = x2.shape[1]
+        if x2.dtype != torch.float64 or not x2.is_cuda or not x2.is_contiguous():
+            raise ValueError("x must be a contiguous FP64 device tensor")
+        if out.shape != x.shape or out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous FP64 device tensor shaped like x")
+        betas = [self.betas[0]] * R if betas is None else betas
+        bh, _ = _host_f64(betas)
+        _chk(self._lib, self._lib.krr_precond_apply_noalloc(self._h, _p(x2), R, bh,
+                                                            self.prec if prec is None else _prec(prec), _p(out),
+                                                            _stream()))
+        return out
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -196,6 +196,11 @@ static void woodbury_one_column(const krr_precond& P, const double* x, int ldx, 
   KRR_LAUNCH_CHECK();
 }
 
+// Doubles of scratch one column of woodbury_one_column needs.
+static int64_t woodbury_column_scratch(const krr_precond& P) {
+  return ceil_div(P.n, kWRows) * (int64_t)P.kept + 2 * (int64_t)P.kept;
+}
+
 void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
                     hipStream_t s) {
   const int kept = P.kept;
@@ -401,6 +406,10 @@ void build_from_anchors(krr_precond& P, const double* X, hipStream_t s) {
 
 }  // namespace krr
 
+namespace krr {
+void* noalloc_scratch();
+}
+
 // ================================================================== C ABI
 extern "C" int krr_init(void* stream) {
   return krr::guarded([&] {
@@ -415,6 +424,7 @@ extern "C" int krr_init(void* stream) {
     krr::gemm_tn<float, double>(af.p, 8, a.p, 8, 8, 8, 8, c.p, 8, s);
     krr::gemm_nn<double>(a.p, 8, a.p, 8, 8, 8, 8, c.p, 8, nullptr, 0, nullptr, s);
     KRR_CHECK_HIP(hipStreamSynchronize(s));
+    (void)krr::noalloc_scratch();   // this device's address of the no-allocation entry point's scratch
     return (int)KRR_OK;
   });
 }
@@ -592,6 +602,65 @@ extern "C" int krr_precond_apply(const krr_precond* P, const double* x, int32_t 
       KRR_REQUIRE(bidx[r] >= 0, "beta not among the preconditioner's betas");
     }
     krr::woodbury_apply(*P, x, R, bidx.data(), prec != KRR_FP64, out, (hipStream_t)stream);
+    return (int)KRR_OK;
+  });
+}
+
+// ------------------------------------------------------------------ apply without device allocation
+// For callers that cannot allocate device memory (HIP graph capture, serving loops): the Woodbury apply
+// one column at a time with its scratch (the W^T x partial sums, t and z) in a file-scope device array.
+// Every GPU the library runs on holds its own copy until the process ends; its address is looked up once
+// per device (hipGetSymbolAddress) and only that address is passed to kernels.  Calls that overlap on one
+// GPU share the array and race.
+namespace krr {
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of that device's copy of `scratch`
+}  // namespace
+
+// Address of this device's scratch array (looked up once per device with that device current).
+void* noalloc_scratch() {
+  int dev = 0;
+  KRR_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  KRR_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  KRR_REQUIRE(p != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_ptr[dev] = p;
+  return p;
+}
+
+size_t noalloc_scratch_bytes() { return kScratchBytes; }
+}  // namespace krr
+
+extern "C" int krr_precond_apply_noalloc(const krr_precond* P, const double* x, int32_t R, const double* betas,
+                                         int32_t prec, double* out, void* stream) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(P && x && out && betas, "null argument");
+    krr::validate_prec(prec);
+    KRR_REQUIRE(R >= 1 && R <= 4096, "R must be in [1, 4096]");
+    const bool use32 = prec != KRR_FP64;
+    KRR_REQUIRE(!use32 || P->W32.p, "preconditioner was built without an FP32 factor");
+    std::vector<int> bidx(R);
+    for (int r = 0; r < R; ++r) {
+      bidx[r] = krr::beta_index(*P, betas[r]);
+      KRR_REQUIRE(bidx[r] >= 0, "beta not among the preconditioner's betas");
+    }
+    const int64_t need = krr::woodbury_column_scratch(*P);
+    KRR_REQUIRE((size_t)need * sizeof(double) <= krr::noalloc_scratch_bytes(),
+                "krr_precond_apply_noalloc: this preconditioner needs " + std::to_string(need * 8) +
+                    " bytes of scratch (ceil(n/256) * kept + 2 * kept doubles); the library's scratch holds " +
+                    std::to_string(krr::noalloc_scratch_bytes()) + " bytes");
+    double* base = static_cast<double*>(krr::noalloc_scratch());
+    double* partial = base;
+    double* t = partial + krr::ceil_div(P->n, krr::kWRows) * P->kept;
+    double* z = t + P->kept;
+    hipStream_t s = (hipStream_t)stream;
+    for (int r = 0; r < R; ++r) krr::woodbury_one_column(*P, x + r, R, bidx[r], use32, out + r, R, partial, t, z, s);
     return (int)KRR_OK;
   });
 }
