@@ -315,6 +315,7 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
     # one product first: the launch the solve's MVMs take (variant, split) is read back from the library
     krr.kernel_mv(Xg, None, wl.eps, Yg, shift=beta, prec=prec)
     launched = dict(zip(("variant", "split", "symmetric"), krr.kmv_last_launch()))
+    c_tot, c_skip = krr.cull_stats()
     # warm-up build on a slice (first use of the build's kernels), not timed
     m0 = min(n, 16384)
     import datagen
@@ -410,6 +411,30 @@ def cycle_bench(a, wl, Xg, Yg, sk, krr, torch, t_proc0):
         log(f"bench: {p2} cycle {dt:.3f} s, MVM kernel {k_ms:.2f} ms")
     out["mvm_speedup_vs_fp64"] = round(out["mvm_gpairs_s"] / out["mvm_gpairs_s_fp64"], 2)
     out["cycle_speedup_vs_fp64"] = round(out["fp64_cycle"]["s"] / step_s, 2)
+    # exact far-tile culling: pairs of the product whose evaluation was skipped, and the same cycle without it
+    off, skipped = {}, {}
+    try:
+        for mode in (1, 2, 0):   # culling forced on; spatial order without skipping; the caller's order
+            krr.set_cull(mode)
+            krr.kernel_mv(Xg, None, wl.eps, Yg, shift=beta, prec=prec)
+            skipped[mode] = krr.cull_stats()[1]
+            _, _, _, st0, _ = krr.pcg_solve(Xg, Yg, wl.eps, [beta], P, tol=wl.tol, maxit=10, replace_every=rep,
+                                            prec=prec, timing=True)
+            off[mode] = st0["t_mvm_kernel_ms"] / max(st0["n_mvm"], 1)
+    finally:
+        krr.set_cull(-1)
+    out["culling"] = {"pairs_per_product": c_tot, "pairs_skipped_default": c_skip,
+                      "pairs_skippable": skipped[1],
+                      "evaluated_fraction_forced": round(1.0 - skipped[1] / max(c_tot, 1), 4),
+                      "mvm_kernel_ms_default": round(avg_ms, 3), "mvm_kernel_ms_culling_forced": round(off[1], 3),
+                      "mvm_kernel_ms_spatial_order_only": round(off[2], 3),
+                      "mvm_kernel_ms_caller_order": round(off[0], 3),
+                      "note": "pairs counted over the points padded to a multiple of 1024; skipped pairs are "
+                              "those whose kernel value is exactly zero in FP32; the default (automatic) mode "
+                              "skips only when at least 10% of the steps can be skipped"}
+    log(f"bench: culling could skip {skipped[1] / max(c_tot, 1):.4f} of the pairs (default skipped "
+        f"{c_skip / max(c_tot, 1):.4f}); mixed MVM {avg_ms:.2f} ms default, {off[1]:.2f} forced, "
+        f"{off[2]:.2f} spatial order only, {off[0]:.2f} caller's order")
     if not a.no_cpu:
         log("bench: CPU oracle baseline")
         rate, rows, secs, thr = oracle_baseline(wl.X, wl.eps)

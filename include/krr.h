@@ -307,6 +307,24 @@ int krr_num_variants(int32_t prec, int32_t R);
  */
 int krr_kmv_variant(int32_t d, int32_t R, int32_t deriv, int32_t prec, int32_t square, int64_t n, int32_t* variant,
                     int32_t* symmetric);
+/*
+ * Exact far-tile culling of square one-column mixed products (the MVM the paper leaves replaceable, Sec. 2.4,
+ * without an approximation).  The operator's points are staged in Morton order of their grid cells; the
+ * symmetric kernel skips the exp/FMA work of a 16-source step for a wave's targets when the two groups'
+ * bounding boxes are so far apart that every kernel value between them is exactly zero in FP32 (scaled
+ * squared distance above 161, plus a bound on the cross term's rounding).  The results are bit for bit those
+ * of the unculled kernel in the same order.  mode: -1 automatic (default: the spatial order when the data's
+ * bounding-box diagonal reaches twice that distance, and the skipping when at least 10% of the 16-source
+ * steps can be skipped; below that the skip logic costs more than it saves), 0 off, 1 on, 2 the spatial
+ * order without skipping (the reference for comparisons).  Process-wide; read when an operator is staged and
+ * launched.
+ */
+int krr_set_cull(int32_t mode);
+/* Pairs of the last kernel MVM launched on this thread: pairs_total = npad^2 (npad the point count padded to
+ * a multiple of 1024), pairs_skipped = those whose evaluation culling skipped (0 if it did not run).
+ * Synchronises the stream.  [host] outputs. */
+int krr_cull_stats(int64_t* pairs_total, int64_t* pairs_skipped, void* stream);
+
 /* What the last kernel MVM launched on this thread ran: its variant, its split (sources per block of a direct
  * form, super-tile edge of a symmetric form) and whether it was the symmetric form.  -1 / 0 / 0 before any
  * launch.  Host only. */

@@ -27,7 +27,7 @@ import torch
 
 __all__ = ["load", "KRRError", "kernel_mv", "sketch", "qrcp", "Preconditioner", "pcg_solve", "grad",
            "KRRValLoss", "autotune", "autotune_save", "autotune_load", "set_variant", "num_variants", "kmv_variant",
-           "kmv_last_launch", "PREC", "library_path"]
+           "kmv_last_launch", "set_cull", "cull_stats", "PREC", "library_path"]
 
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 _STATUS = {0: "KRR_OK", -1: "KRR_EINVAL", -2: "KRR_ENOMEM", -3: "KRR_EHIP", -4: "KRR_ENOTSPD",
@@ -91,6 +91,8 @@ _SIGS = {
     "krr_num_variants": ([_i32, _i32], _i32),
     "krr_kmv_variant": ([_i32, _i32, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "krr_kmv_last_launch": ([_vp, _vp, _vp], _i32),
+    "krr_set_cull": ([_i32], _i32),
+    "krr_cull_stats": ([_vp, _vp, _vp], _i32),
 }
 
 
@@ -468,6 +470,21 @@ def kmv_last_launch():
     v, sp, sym = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _chk(lib, lib.krr_kmv_last_launch(ctypes.byref(v), ctypes.byref(sp), ctypes.byref(sym)))
     return v.value, sp.value, bool(sym.value)
+
+
+def set_cull(mode: int):
+    """Exact far-tile culling of square one-column mixed products: -1 automatic, 0 off, 1 on, 2 spatial order
+    without skipping."""
+    lib = load()
+    _chk(lib, lib.krr_set_cull(int(mode)))
+
+
+def cull_stats():
+    """(pairs_total, pairs_skipped) of the last kernel MVM launched on this thread."""
+    lib = load()
+    tot, sk = ctypes.c_int64(), ctypes.c_int64()
+    _chk(lib, lib.krr_cull_stats(ctypes.byref(tot), ctypes.byref(sk), _stream()))
+    return tot.value, sk.value
 
 
 def autotune_save(path: str):

@@ -21,10 +21,12 @@ void kernel_mv_raw(const double* Xt, int64_t m, const double* Xs, int64_t n, int
   DevBuf<double> center(dpad, s);
   point_mean(Xs, n, d, dpad, center.p, s);
   Staged S, T;
-  stage_points(S, Xs, n, d, eps, prec, center.p, same, true, s);
+  // square one-column mixed products may be staged in spatial order for exact far-tile culling
+  const bool sort = same && prec == KRR_MIXED && R == 1 && deriv == 0 && cull_wanted(Xs, n, d, eps, s);
+  stage_points(S, Xs, n, d, eps, prec, center.p, same, true, s, sort);
   if (!same) stage_points(T, Xt, m, d, eps, prec, center.p, true, false, s);
   StagedVec SV;
-  stage_vectors(SV, V, n, S.npad, R, prec, s);
+  stage_vectors(SV, V, n, S.npad, R, prec, s, S.perm.p);
   kmv_launch(same ? S : T, S, SV, deriv, shift, V, prec, U, ldu, s);
 }
 

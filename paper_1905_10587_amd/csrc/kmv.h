@@ -23,6 +23,15 @@ struct Staged {
   DevBuf<float> x32;
   DevBuf<uint16_t> sa, sb;
   DevBuf<double> center;   // dpad
+  // Spatial order for exact far-tile culling (symmetric mixed form): the staged copies hold the points in
+  // Morton order of their grid cells, perm[i] = original index of staged point i; box16 holds, for every
+  // group of 16 staged points, the bounding box of z' = (x - center) sqrt(log2(e) / eps): lo[dpad] then
+  // hi[dpad].  Empty: the caller's order, no culling.
+  DevBuf<int64_t> perm;
+  DevBuf<double> box16;
+  // skip masks of the symmetric kernel for target groups of 16 NF points (built on first use)
+  mutable DevBuf<uint16_t> cull_mask;
+  mutable int cull_nf = 0;
 };
 
 constexpr int kRowPad = 1024;   // targets/sources are padded to multiples of this
@@ -35,8 +44,24 @@ int mixed_chunks(int d);
 
 // Stage a point set.  center: dpad FP64 on device (translation applied to FP32 and split copies;
 // the kernel is translation invariant).  Pass the same center for targets and sources.
+// sort: stage a square operator's points in spatial order with culling boxes (MIXED only; see Staged).
 void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int prec,
-                  const double* center, bool as_target, bool as_source, hipStream_t s);
+                  const double* center, bool as_target, bool as_source, hipStream_t s, bool sort = false);
+
+// Exact far-tile culling of the symmetric mixed form.  A 16-source step of a wave's 16 NF targets is skipped
+// when every kernel value in it is exactly zero in FP32: the boxes' minimum scaled squared distance exceeds
+// 161 (exp2 of anything below -150 is 0) plus a bound on the split cross term's rounding error.
+//   cull_mode: -1 automatic (square mixed one-column products whose bounding-box diagonal reaches past the
+//   threshold), 0 off, 1 on, 2 spatial order without skipping (for comparisons).
+int cull_mode();
+void set_cull_mode(int mode);
+// Whether a square mixed product of these points should be staged in spatial order under the current mode.
+bool cull_wanted(const double* X, int64_t n, int d, double eps, hipStream_t s);
+// Skip masks for target groups of 16 NF points against 256-source groups (cached in S).
+const uint16_t* cull_masks(const Staged& S, int NF, hipStream_t s);
+// Device counters of skipped 16-source steps (diagonal and off-diagonal super-tiles) of culled launches.
+unsigned long long* cull_counters();
+void cull_reset_counters(hipStream_t s);
 // Mean of the points (FP64), written to center[dpad].
 void point_mean(const double* X, int64_t n, int d, int dpad, double* center, hipStream_t s);
 
@@ -56,8 +81,9 @@ void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad
                          hipStream_t s);
 // Whether kmv_launch takes the block (multi right-hand side) path for these parameters.
 bool kmv_uses_block(int prec, int d, int R, int deriv);
+// perm: the operator's staged order (Staged::perm), nullptr for the caller's order.
 void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
-                   hipStream_t s);
+                   hipStream_t s, const int64_t* perm = nullptr);
 
 // Core launcher: U[i, col0 + c] (row stride ldu) for the staged operands.
 //   deriv: 0 K, 1 K', 2 both (K columns first, then K' columns).
@@ -79,6 +105,9 @@ struct KmvChoice {
 };
 struct KmvLaunchInfo {
   int variant = -1, split = 0, symmetric = 0;
+  int culled = 0;          // the symmetric form ran with far-tile culling (counters valid)
+  int64_t npad = 0;        // padded point count of the launch
+  int nf = 0;              // target fragments per wave (16 NF targets per wave)
 };
 KmvLaunchInfo kmv_last_launch();
 KmvChoice kmv_lookup(int prec, int d, int R, int64_t n, bool square);

@@ -115,16 +115,17 @@ __device__ __forceinline__ void split3(double x, uint16_t& h, uint16_t& m, uint1
 // dropped m*l, l*m, l*l products (relative size below 2^-24).
 __global__ void k_stage_split(const double* __restrict__ X, int64_t n, int d, int64_t npad, int ka,
                               const double* __restrict__ center, double c, int side,
-                              uint16_t* __restrict__ out) {
+                              const int64_t* __restrict__ perm, uint16_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npad) return;
   uint16_t* o = out + i * ka;
   for (int k = 0; k < ka; ++k) o[k] = 0;
   if (i >= n) return;
+  const int64_t src = perm ? perm[i] : i;   // staged point i is the caller's point src
   const uint16_t one = 0x3F80;   // 1.0 in BF16
   double nz = 0;
   for (int k = 0; k < d; ++k) {
-    double z = X[i * d + k] - center[k];
+    double z = X[src * d + k] - center[k];
     nz += z * z;
     double zz = side == 0 ? 2.0 * c * z : z;
     uint16_t h, m, l;
@@ -149,8 +150,10 @@ __global__ void k_stage_split(const double* __restrict__ X, int64_t n, int d, in
   }
 }
 
+void spatial_order(Staged& st, const double* X, const double* center, hipStream_t s);
+
 void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int prec,
-                  const double* center, bool as_target, bool as_source, hipStream_t s) {
+                  const double* center, bool as_target, bool as_source, hipStream_t s, bool sort) {
   st.n = n;
   st.d = d;
   st.npad = round_up(n, kRowPad);
@@ -176,34 +179,38 @@ void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int
     // split vectors: the MFMA kernels (single column for MIXED, block for MIXED and FP32)
     st.ka = 32 * mixed_chunks(d);
     const double c = kLog2e / eps;
+    if (sort) {
+      KRR_REQUIRE(prec == KRR_MIXED && as_target && as_source, "spatial order is for square mixed operators");
+      spatial_order(st, X, center, s);
+    }
     if (as_target) {
       st.sa.alloc(st.npad * st.ka, s);
       hipLaunchKernelGGL(k_stage_split, dim3(ceil_div(st.npad, blk)), dim3(blk), 0, s, X, n, d, st.npad,
-                         st.ka, center, c, 0, st.sa.p);
+                         st.ka, center, c, 0, (const int64_t*)st.perm.p, st.sa.p);
       KRR_LAUNCH_CHECK();
     }
     if (as_source) {
       st.sb.alloc((st.npad + kPrefetchRows) * st.ka, s);   // padding rows: read by the last prefetch only
       hipLaunchKernelGGL(k_stage_split, dim3(ceil_div(st.npad, blk)), dim3(blk), 0, s, X, n, d, st.npad,
-                         st.ka, center, c, 1, st.sb.p);
+                         st.ka, center, c, 1, (const int64_t*)st.perm.p, st.sb.p);
       KRR_LAUNCH_CHECK();
     }
   }
 }
 
 __global__ void k_stage_vec(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rp,
-                            double* __restrict__ o64, float* __restrict__ o32) {
+                            const int64_t* __restrict__ perm, double* __restrict__ o64, float* __restrict__ o32) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npad * Rp) return;
   int64_t i = idx / Rp;
   int c = (int)(idx % Rp);
-  double v = (i < n && c < R) ? V[i * R + c] : 0.0;
+  double v = (i < n && c < R) ? V[(perm ? perm[i] : i) * R + c] : 0.0;
   if (o64) o64[idx] = v;
   if (o32) o32[idx] = (float)v;
 }
 
 void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
-                   hipStream_t s) {
+                   hipStream_t s, const int64_t* perm) {
   sv.npad = npad;
   sv.Rreal = R;
   // column chunks are at most 8 wide; FP64 with more than 8 columns pads to 16 for the matrix-core kernel
@@ -215,7 +222,7 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
   } else {
     if (sv.v32.n != cap) sv.v32.alloc(cap, s);
   }
-  hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R,
+  hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R, perm,
                      sv.v64.p, sv.v32.p);
   KRR_LAUNCH_CHECK();
 }
@@ -261,7 +268,8 @@ struct ShiftArg {
 
 __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpad, int Rp, int Rout,
                              int deriv, int64_t m, int R, int has_shift, ShiftArg sh,
-                             const double* __restrict__ Vraw, double* __restrict__ U, int64_t ldu) {
+                             const double* __restrict__ Vraw, const int64_t* __restrict__ perm,
+                             double* __restrict__ U, int64_t ldu) {
   const int Rcols = deriv == 2 ? 2 * R : R;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * Rcols) return;
@@ -276,8 +284,9 @@ __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpa
   // unrolled so that sixteen loads are in flight at once; the additions keep their order
 #pragma unroll 16
   for (int p = 0; p < S; ++p) acc += part[((int64_t)p * mpad + i) * Rout + pc];
-  if (has_shift && kcol) acc += sh.v[oc] * Vraw[i * R + oc];
-  U[i * ldu + oc] = acc;
+  const int64_t oi = perm ? perm[i] : i;   // staged row i is the caller's row oi
+  if (has_shift && kcol) acc += sh.v[oc] * Vraw[oi * R + oc];
+  U[oi * ldu + oc] = acc;
 }
 
 // ------------------------------------------------------------------ variants and launcher
@@ -638,6 +647,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     gz = (int)ceil_div(R, RC);   // real columns only (Rp is padded to 8)
     KRR_REQUIRE(Rp % RC == 0, "internal: column chunk does not divide the padded column count");
   }
+  KRR_REQUIRE(!block || (!T.perm.p && !S.perm.p), "internal: spatially ordered operators take one column");
+  // exact far-tile culling: only the symmetric form of an operator staged in spatial order skips work
+  // (cull_masks returns nullptr when automatic mode finds too little to skip)
+  const uint16_t* cmask = (sym && T.perm.p && T.box16.p && cull_mode() != 2) ? cull_masks(T, NF, s) : nullptr;
   const int64_t gx = T.npad / rows;
   const int64_t nsrc = S.npad;
   const int RpK = block ? Rpart : Rp;                  // row width of the K part in `part`
@@ -656,7 +669,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     if (f64m) return launch_kmv_f64_mfma(D, NRG, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP32) return launch_kmv_f32(D, TM, RC, DV, g, T.x32.p, S.x32.p, V.v32.p, part.p, s);
-    if (sym) return launch_kmv_mixed_sym(T.ka / 32, NF, g, T.sa.p, S.sb.p, V.v32.p, part.p, s);
+    if (sym) return launch_kmv_mixed_sym(T.ka / 32, NF, g, T.sa.p, S.sb.p, V.v32.p, part.p, s, g.occ ? nullptr : cmask);
     bool ok = true;
     for (int c = 0; c < R && ok; ++c) {
       ok = launch_kmv_mixed(T.ka / 32, NF, DV, form, g, T.sa.p, S.sb.p, V.v32.p, c, part.p, s);
@@ -724,7 +737,8 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   }
   const size_t need = (size_t)split * T.npad * RoutK;
   if (part.n < need) part.alloc(need, s);
-  t_last = KmvLaunchInfo{variant, (int)(sym ? g.E : src_len), sym ? 1 : 0};
+  t_last = KmvLaunchInfo{variant, (int)(sym ? g.E : src_len), sym ? 1 : 0, cmask ? 1 : 0, T.npad, NF};
+  if (cmask) cull_reset_counters(s);
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[0], s));
   const bool ok = run(g);
   if (kev) KRR_CHECK_HIP(hipEventRecord(kev[1], s));
@@ -737,7 +751,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int Rcols = deriv == 2 ? 2 * R : R;
   const int64_t tot = T.n * Rcols;
   hipLaunchKernelGGL(k_kmv_finish, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, part.p, (int)split,
-                     T.npad, RpK, RoutK, deriv, T.n, R, has_shift, sh, Vraw, U, ldu);
+                     T.npad, RpK, RoutK, deriv, T.n, R, has_shift, sh, Vraw, (const int64_t*)T.perm.p, U, ldu);
   KRR_LAUNCH_CHECK();
 }
 

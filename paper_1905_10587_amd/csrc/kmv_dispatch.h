@@ -42,8 +42,9 @@ bool launch_kmv_mixed(int NCH, int NF, int DV, int form, const KmvGrid& g, const
 int mixed_max_nf(int nch);
 bool mixed_has_pp(int nch);
 // Symmetric square product K(X, X) v, one column (NCH <= 4, NF in {4, 8}; NCH > 2: NF 4 only).
+// cmask: skip masks of exact far-tile culling (points staged in spatial order), or nullptr.
 bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                          const float* v, double* part, hipStream_t s);
+                          const float* v, double* part, hipStream_t s, const uint16_t* cmask = nullptr);
 // Block MVM (many right-hand sides): NCH in {1,2,3,4}, (NT, NRC) with NT * NRC <= 8, NS in {3, 6}.
 // k32: the K.V contraction on v_mfma_f32_16x16x32_bf16 (32 sources per step) instead of 16x16x16.
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,

@@ -862,11 +862,19 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__
 // tile the 16 partials of a source (4 waves x 4 lane groups) are added in FP64 in a fixed order.
 // Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle in
 // column order.
-template <int NCH, int NF>
+//
+// CULL (points staged in spatial order): cmask[g * ngs + j] holds one bit per 16-source step of the
+// 256-source group j for the target group g of 16 NF points (a wave's targets); a set bit means every kernel
+// value of that step is exactly zero in FP32, so its exp/FMA work is skipped (the MFMA pipeline still runs).
+// Adding exact zeros changes no sum, so the result is bit for bit that of the unculled kernel.  The skipped
+// steps are counted (ccount[0]: diagonal super-tiles, ccount[1]: the others).
+template <int NCH, int NF, bool CULL>
 // (two resident blocks per CU: the register budget is held to 256 per lane; NF 8 spills a few values)
 __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restrict__ A, const uint4* __restrict__ B,
                                                        const float* __restrict__ v, int Rp, int E, int NS,
-                                                       int64_t npad, double* __restrict__ part, int Rout) {
+                                                       int64_t npad, double* __restrict__ part, int Rout,
+                                                       const uint16_t* __restrict__ cmask, int64_t ngs,
+                                                       unsigned long long* __restrict__ ccount) {
   static_assert(NF >= 2, "the pipeline needs two fragments per step");
   constexpr int KV = NCH * 4;
   constexpr int RS = KV + 1;
@@ -923,9 +931,12 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
   };
   auto vload = [&](int64_t j0) -> float { return tid < TS ? v[(j0 + tid) * Rp] : kZero; };
 
-  // one LDS tile: row sums into a32; with COL, per-step column partials into cb[wave][step * 16 + r16]
-  auto compute = [&](const uint4* sb, const float* sv, float (*cb)[TS], auto colflag) {
+  // one LDS tile: row sums into a32; with COL, per-step column partials into cb[wave][step * 16 + r16];
+  // SKIP: bit st of sk set means step st is culled (its exp/FMA work skipped); without SKIP the step loop has
+  // no branches (tiles with nothing to skip run the same code as the unculled kernel)
+  auto compute = [&](const uint4* sb, const float* sv, float (*cb)[TS], auto colflag, auto skipflag, unsigned sk) {
     constexpr bool COL = decltype(colflag)::value;
+    constexpr bool SKIP = decltype(skipflag)::value;
     bf16x8 b[NCH], bn[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) b[ch] = __builtin_bit_cast(bf16x8, sb[r16 * RS + ch * 4 + kq]);
@@ -942,6 +953,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
       for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, sb[rn * RS + ch * 4 + kq]);
       const float vn = sv[rn];
       float cs[4] = {0.f, 0.f, 0.f, 0.f};
+      const bool skip = SKIP && ((sk >> st) & 1u);
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         f32x4 q2 = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -955,11 +967,13 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
             q2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f + 2 - NF >= 0 ? f + 2 - NF : 0][ch], bn[ch], q2, 0,
                                                          0, 0);
         }
+        if (!skip) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float ex = __builtin_amdgcn_exp2f(q0[e]);
-          a32[f][e] = __builtin_fmaf(ex, vj, a32[f][e]);
-          if (COL) cs[e] = __builtin_fmaf(ex, vt[f][e], cs[e]);
+          for (int e = 0; e < 4; ++e) {
+            const float ex = __builtin_amdgcn_exp2f(q0[e]);
+            a32[f][e] = __builtin_fmaf(ex, vj, a32[f][e]);
+            if (COL) cs[e] = __builtin_fmaf(ex, vt[f][e], cs[e]);
+          }
         }
         q0 = q1;
         q1 = q2;
@@ -991,6 +1005,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     int64_t row0 = 0;
+    unsigned long long nskip = 0;
     for (int k = 0; k < total; ++k) {
       const int tt = k / ntile;
       const int t = k - tt * ntile;
@@ -1021,7 +1036,24 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
       double* dst = part + (int64_t)r * npad + s0 + (int64_t)t * TS + (tid < TS ? tid : 0);   // dense partials
       double prev = 0.0;
       if (COL && tid < TS && tt > 0) prev = *dst;
-      compute(odd ? sb1 : sb0, odd ? sv1 : sv0, odd ? cb1 : cb0, colflag);
+      unsigned sk = 0;
+      if (CULL) {   // this wave's skip bits for the tile's steps (one scalar value per wave)
+        const int64_t j0 = s0 + (int64_t)t * TS;
+        const unsigned m16 = cmask[(row0 / (16 * NF)) * ngs + j0 / 256];
+        sk = __builtin_amdgcn_readfirstlane((m16 >> ((j0 % 256) / 16)) & ((1u << SPT) - 1u));
+        nskip += (unsigned long long)__builtin_popcount(sk);
+      }
+      if (!CULL || sk == 0) {
+        compute(odd ? sb1 : sb0, odd ? sv1 : sv0, odd ? cb1 : cb0, colflag, std::false_type{}, 0u);
+      } else if (sk == (1u << SPT) - 1u) {   // the whole tile is culled: its column partials are zero
+        if (COL) {
+          float (*cb)[TS] = odd ? cb1 : cb0;
+#pragma unroll
+          for (int st = 0; st < SPT; ++st) cb[wave * 4 + kq][st * 16 + r16] = 0.0f;
+        }
+      } else {
+        compute(odd ? sb1 : sb0, odd ? sv1 : sv0, odd ? cb1 : cb0, colflag, std::true_type{}, sk);
+      }
       if (t % TPF == TPF - 1 || t == ntile - 1) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -1056,6 +1088,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
           }
       }
     }
+    if (CULL && lane == 0 && nskip) atomicAdd(ccount + (diag ? 0 : 1), nskip);
   };
   if (diag) run(std::false_type{});
   else run(std::true_type{});

@@ -72,24 +72,31 @@ bool mixed_has_pp(int nch) { return nch <= 4; }
 
 template <int NCH, int NF>
 static void gos(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const float* v, double* part,
-                hipStream_t s) {
+                const uint16_t* cmask, hipStream_t s) {
   if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_mixed_sym<NCH, NF>, 256, 0));
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_mixed_sym<NCH, NF, false>, 256, 0));
     return;
   }
-  hipLaunchKernelGGL((k_kmv_mixed_sym<NCH, NF>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
-                     reinterpret_cast<const uint4*>(B), v, g.Rp, g.E, g.NS, g.mpad, part, g.Rout);
+  const int64_t ngs = g.mpad / 256;
+  if (cmask)
+    hipLaunchKernelGGL((k_kmv_mixed_sym<NCH, NF, true>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                       reinterpret_cast<const uint4*>(B), v, g.Rp, g.E, g.NS, g.mpad, part, g.Rout, cmask, ngs,
+                       cull_counters());
+  else
+    hipLaunchKernelGGL((k_kmv_mixed_sym<NCH, NF, false>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                       reinterpret_cast<const uint4*>(B), v, g.Rp, g.E, g.NS, g.mpad, part, g.Rout, nullptr, ngs,
+                       nullptr);
 }
 
 bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
-                          const float* v, double* part, hipStream_t s) {
+                          const float* v, double* part, hipStream_t s, const uint16_t* cmask) {
   switch (NCH * 16 + NF) {
-    case 1 * 16 + 4: gos<1, 4>(g, A, B, v, part, s); return true;
-    case 1 * 16 + 8: gos<1, 8>(g, A, B, v, part, s); return true;
-    case 2 * 16 + 4: gos<2, 4>(g, A, B, v, part, s); return true;
-    case 2 * 16 + 8: gos<2, 8>(g, A, B, v, part, s); return true;
-    case 3 * 16 + 4: gos<3, 4>(g, A, B, v, part, s); return true;
-    case 4 * 16 + 4: gos<4, 4>(g, A, B, v, part, s); return true;
+    case 1 * 16 + 4: gos<1, 4>(g, A, B, v, part, cmask, s); return true;
+    case 1 * 16 + 8: gos<1, 8>(g, A, B, v, part, cmask, s); return true;
+    case 2 * 16 + 4: gos<2, 4>(g, A, B, v, part, cmask, s); return true;
+    case 2 * 16 + 8: gos<2, 8>(g, A, B, v, part, cmask, s); return true;
+    case 3 * 16 + 4: gos<3, 4>(g, A, B, v, part, cmask, s); return true;
+    case 4 * 16 + 4: gos<4, 4>(g, A, B, v, part, cmask, s); return true;
   }
   return false;
 }

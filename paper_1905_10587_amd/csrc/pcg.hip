@@ -300,11 +300,13 @@ struct Operator {
     n = n_;
     prec = prec_;
     R = R_;
-    stage_points(S, X, n, d, eps, prec, center, true, true, s);
+    // one-column mixed operators may be staged in spatial order for exact far-tile culling
+    const bool sort = prec == KRR_MIXED && R == 1 && cull_wanted(X, n, d, eps, s);
+    stage_points(S, X, n, d, eps, prec, center, true, true, s, sort);
   }
   // out = (K + diag(shift)) v   (shift may be null)
   void apply(const double* v, const double* shift, double* out, hipStream_t s, const hipEvent_t* kev = nullptr) {
-    stage_vectors(V, v, n, S.npad, R, prec, s);
+    stage_vectors(V, v, n, S.npad, R, prec, s, S.perm.p);
     kmv_launch(S, S, V, 0, shift, v, prec, out, R, s, -1, &ws, kev);
   }
 };
