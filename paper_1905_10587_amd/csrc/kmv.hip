@@ -360,7 +360,8 @@ void kmv_set_tuned(int prec, int d, int R, int64_t n, bool square, KmvChoice c) 
 }
 
 int kmv_num_variants(int prec, int R) {
-  if (rclass(prec, R) == 3) return 13;   // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile
+  // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile (64 targets), 13 shared tile (128 targets)
+  if (rclass(prec, R) == 3) return 14;
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
   // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
   // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2)
@@ -591,8 +592,10 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
   bool k32 = false, shared = false;
+  int shared_fw = 1;   // fragments per wave of the shared-tile form
   if (block) {
-    shared = variant == 12;
+    shared = variant >= 12;
+    shared_fw = variant == 13 ? 2 : 1;
     const int vb = shared ? 1 : variant % 6;
     k32 = variant >= 6;
     int nrc_max = 1;
@@ -601,7 +604,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     NRC = std::min(kBlockNRC[vb], nrc_max);
     stage_vectors_block(V, Vraw, S.n, S.npad, R, shared ? 32 : 16 * NRC, prec == KRR_MIXED ? 2 : 3, s);
     Rpart = V.Rb;
-    rows = shared ? 64 : 64 * NT;
+    rows = shared ? 64 * shared_fw : 64 * NT;
     gz = shared ? (int)ceil_div(V.Rb, 128) : V.Rb / (16 * NRC);   // shared form: 128 columns per block
   } else if (prec == KRR_MIXED) {
     const int nch = T.ka / 32;
@@ -660,7 +663,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   DevBuf<double>& part = ws ? *ws : own;
   auto run = [&](const KmvGrid& g) -> bool {
     if (block && shared)
-      return launch_kmv_block_shared(T.ka / 32, prec == KRR_MIXED ? 3 : 6, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
+      return launch_kmv_block_shared(T.ka / 32, prec == KRR_MIXED ? 3 : 6, shared_fw, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
                                      prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
     if (block)
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,

@@ -42,24 +42,30 @@ static void gob(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const ui
   if (NT == 2 && NRC == 4) { KRR_BNS(NCH, 2, 4) } if (NT == 4 && NRC == 1) { KRR_BNS(NCH, 4, 1) } \
   if (NT == 4 && NRC == 2) { KRR_BNS(NCH, 4, 2) }
 
-template <int NCH, int NS>
+template <int NCH, int NS, int FW>
 static void gobs(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm,
                  const uint16_t* Vl, double* part, hipStream_t s) {
   if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32s<NCH, NS>, 256, 0));
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32s<NCH, NS, FW>, 256, 0));
     return;
   }
-  hipLaunchKernelGGL((k_kmv_block32s<NCH, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+  hipLaunchKernelGGL((k_kmv_block32s<NCH, NS, FW>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
                      reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint2*>(Vh),
                      reinterpret_cast<const uint2*>(Vm), reinterpret_cast<const uint2*>(Vl), g.Rp, g.src_len, g.n_src,
                      part, g.mpad, g.Rout);
 }
 
-bool launch_kmv_block_shared(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+bool launch_kmv_block_shared(int NCH, int NS, int FW, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                              const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s) {
-#define KRR_BSH(C) \
-  if (NCH == C) { if (NS == 3) gobs<C, 3>(g, A, B, Vh, Vm, Vl, part, s); else gobs<C, 6>(g, A, B, Vh, Vm, Vl, part, s); return true; }
-  if (NS != 3 && NS != 6) return false;
+#define KRR_BSH(C)                                                                     \
+  if (NCH == C) {                                                                      \
+    if (NS == 3 && FW == 1) gobs<C, 3, 1>(g, A, B, Vh, Vm, Vl, part, s);               \
+    else if (NS == 3) gobs<C, 3, 2>(g, A, B, Vh, Vm, Vl, part, s);                     \
+    else if (FW == 1) gobs<C, 6, 1>(g, A, B, Vh, Vm, Vl, part, s);                     \
+    else gobs<C, 6, 2>(g, A, B, Vh, Vm, Vl, part, s);                                  \
+    return true;                                                                       \
+  }
+  if ((NS != 3 && NS != 6) || (FW != 1 && FW != 2)) return false;
   KRR_BSH(1) KRR_BSH(2) KRR_BSH(3) KRR_BSH(4)
 #undef KRR_BSH
   return false;

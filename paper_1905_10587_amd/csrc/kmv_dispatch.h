@@ -50,8 +50,9 @@ bool launch_kmv_mixed_sym(int NCH, int NF, const KmvGrid& g, const uint16_t* A, 
 bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid& g, const uint16_t* A,
                       const uint16_t* B, const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part,
                       hipStream_t s);
-// Shared-tile block MVM: 64 targets x 128 right-hand sides per block (V staged with a multiple of 32 columns).
-bool launch_kmv_block_shared(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
+// Shared-tile block MVM: 64 FW targets x 128 right-hand sides per block (V staged with a multiple of 32 columns),
+// FW in {1, 2} fragments evaluated per wave.
+bool launch_kmv_block_shared(int NCH, int NS, int FW, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                              const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
 
 }  // namespace krr

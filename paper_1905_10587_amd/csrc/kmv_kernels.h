@@ -1336,22 +1336,23 @@ __global__ __launch_bounds__(256) void k_kmv_block32(const uint4* __restrict__ A
 }
 
 
-// Block MVM, shared-tile form: a block covers 64 targets (four fragments of 16) and 128 right-hand sides
-// (grid.z walks the rest); wave w evaluates the cross term and exp2 of fragment w only, splits it into BF16
-// parts and stores them in LDS in the A-operand layout of the K.V MFMA, and after one barrier every wave
-// contracts all four fragments with its own 32 right-hand sides.  The columns are padded to a multiple of
+// Block MVM, shared-tile form: a block covers 64 FW targets (4 FW fragments of 16) and 128 right-hand sides
+// (grid.z walks the rest); wave w evaluates the cross term and exp2 of its FW fragments only, splits them into
+// BF16 parts and stores them in LDS in the A-operand layout of the K.V MFMA, and after one barrier every wave
+// contracts all 4 FW fragments with its own 32 right-hand sides.  Every V value a wave loads feeds 4 FW
+// fragments, so FW = 2 halves the V traffic per pair of FW = 1.  The columns are padded to a multiple of
 // 32 only: a wave whose 32 columns lie beyond the padded count still evaluates its fragment for the others
 // but loads, contracts and stores nothing.  The exp/split work is done once per
 // block instead of once per 32-column group.  Accumulation order per (fragment, column group) is that of
 // k_kmv_block32<NCH, 4, 2, NS>.
-template <int NCH, int NS>
+template <int NCH, int NS, int FW>
 __global__ __launch_bounds__(256) void k_kmv_block32s(const uint4* __restrict__ A, const uint4* __restrict__ B,
                                                       const uint2* __restrict__ Vh, const uint2* __restrict__ Vm,
                                                       const uint2* __restrict__ Vl, int Rp, int64_t src_len,
                                                       int64_t n_src, double* __restrict__ part, int64_t mpad,
                                                       int Rout) {
   constexpr int KV = NCH * 4;
-  constexpr int NT = 4, NRC = 2, NP = NS == 6 ? 3 : 2;
+  constexpr int NT = 4 * FW, NRC = 2, NP = NS == 6 ? 3 : 2;
   __shared__ uint4 ps[2][NT][NP][64];   // exp'd fragments, double buffered: [step parity][fragment][part][lane]
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1363,9 +1364,12 @@ __global__ __launch_bounds__(256) void k_kmv_block32s(const uint4* __restrict__ 
   const int64_t jb = (int64_t)blockIdx.y * src_len;
   const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
 
-  bf16x8 tg[NCH];
+  bf16x8 tg[FW][NCH];
 #pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) tg[ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * wave + r16) * KV + ch * 4 + kq]);
+  for (int f = 0; f < FW; ++f)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      tg[f][ch] = __builtin_bit_cast(bf16x8, A[(row0 + 16 * (wave * FW + f) + r16) * KV + ch * 4 + kq]);
 
   double acc[NT][NRC][4];
 #pragma unroll
@@ -1403,14 +1407,15 @@ __global__ __launch_bounds__(256) void k_kmv_block32s(const uint4* __restrict__ 
           }
         }
       }
-      {   // this wave's fragment: cross term, exp2, BF16 splits -> LDS
-        const uint4* bp = B + (j + r16) * KV + kq;
+      const uint4* bp = B + (j + r16) * KV + kq;
+#pragma unroll
+      for (int f = 0; f < FW; ++f) {   // this wave's fragments: cross term, exp2, BF16 splits -> LDS
         f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-          qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[ch * 4]), tg[ch], qa, 0, 0, 0);
-          qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[16 * KV + ch * 4]), tg[ch], qb,
-                                                      0, 0, 0);
+          qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[ch * 4]), tg[f][ch], qa, 0, 0, 0);
+          qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, bp[16 * KV + ch * 4]), tg[f][ch],
+                                                      qb, 0, 0, 0);
         }
         bf16x8 ph, pm, pl;
 #pragma unroll
@@ -1427,9 +1432,9 @@ __global__ __launch_bounds__(256) void k_kmv_block32s(const uint4* __restrict__ 
             pl[e] = lo[0]; pl[e + 1] = lo[1];
           }
         }
-        ps[buf][wave][0][lane] = __builtin_bit_cast(uint4, ph);
-        ps[buf][wave][1][lane] = __builtin_bit_cast(uint4, pm);
-        if (NS == 6) ps[buf][wave][2][lane] = __builtin_bit_cast(uint4, pl);
+        ps[buf][wave * FW + f][0][lane] = __builtin_bit_cast(uint4, ph);
+        ps[buf][wave * FW + f][1][lane] = __builtin_bit_cast(uint4, pm);
+        if (NS == 6) ps[buf][wave * FW + f][2][lane] = __builtin_bit_cast(uint4, pl);
       }
       __syncthreads();   // the other buffer is rewritten only after the next barrier
       if (live) {
