@@ -239,6 +239,8 @@ typedef struct {
   double lam_min_est;     /* smallest and largest eigenvalue of column 0's Lanczos tridiagonal (Ritz values */
   double lam_max_est;     /* of the preconditioned operator; kappa_est is their ratio; 0 if none), built from
                              the CG coefficients up to the first claim of convergence of column 0 */
+  int32_t n_graph_cycles; /* graph-captured cycles launched (krr_set_pcg_mode) */
+  int32_t n_graph_iters;  /* iterations whose status came from a captured cycle */
 } krr_solve_stats;
 
 /*
@@ -255,6 +257,23 @@ typedef struct {
  *   residuals;  stats [host] optional (NULL);  timing != 0 records HIP-event phase times.
  *   Returns KRR_ENOCONV if some column did not reach tol within maxit.
  */
+/*
+ * Driver of krr_pcg_solve (process-wide; Algorithm 5's loop).  Both drivers launch the same kernels in the
+ * same order and return bit-identical iterates, iteration counts and residuals:
+ *   0: host loop, one host synchronisation per iteration (the next iteration's preconditioner apply and
+ *      product are enqueued before the host waits, so the GPU does not idle while the host decides);
+ *   1: graph-captured cycles: from the first scheduled replacement on (every 16 iterations when
+ *      replace_every is 0), one HIP graph runs a whole cycle of replace_every (16) iterations and, with
+ *      replacement, the check of the last one's true residual, with one host synchronisation per cycle.
+ *      The convergence claims of the recursive residuals are decided on the device; a claim or a breakdown
+ *      halts the cycle's remaining state updates, the host takes over at that iteration and runs the host
+ *      loop until the next cycle boundary;
+ *  -1: automatic (default): graph cycles when the product has at most 2^34 pair-columns (n^2 R), the host
+ *      loop otherwise.
+ * Graph cycles need replace_every <= 64 and timing == 0 (the host loop runs otherwise).
+ */
+int krr_set_pcg_mode(int32_t mode);
+
 int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps,
                   const double* Yrhs, int32_t R, const double* betas,
                   const krr_precond* P, double tol, int32_t maxit, int32_t replace_every,

@@ -27,7 +27,7 @@ import torch
 
 __all__ = ["load", "KRRError", "kernel_mv", "sketch", "qrcp", "Preconditioner", "pcg_solve", "grad",
            "KRRValLoss", "autotune", "autotune_save", "autotune_load", "set_variant", "num_variants", "kmv_variant",
-           "kmv_last_launch", "set_cull", "cull_stats", "PREC", "library_path"]
+           "kmv_last_launch", "set_cull", "cull_stats", "set_pcg_mode", "PREC", "library_path"]
 
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 _STATUS = {0: "KRR_OK", -1: "KRR_EINVAL", -2: "KRR_ENOMEM", -3: "KRR_EHIP", -4: "KRR_ENOTSPD",
@@ -53,7 +53,8 @@ class SolveStats(ctypes.Structure):
                 ("n_replace", ctypes.c_int32), ("t_total_ms", ctypes.c_double), ("t_mvm_ms", ctypes.c_double),
                 ("t_mvm_fp64_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
                 ("kappa_est", ctypes.c_double), ("t_mvm_kernel_ms", ctypes.c_double),
-                ("lam_min_est", ctypes.c_double), ("lam_max_est", ctypes.c_double)]
+                ("lam_min_est", ctypes.c_double), ("lam_max_est", ctypes.c_double),
+                ("n_graph_cycles", ctypes.c_int32), ("n_graph_iters", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +93,7 @@ _SIGS = {
     "krr_kmv_variant": ([_i32, _i32, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "krr_kmv_last_launch": ([_vp, _vp, _vp], _i32),
     "krr_set_cull": ([_i32], _i32),
+    "krr_set_pcg_mode": ([_i32], _i32),
     "krr_cull_stats": ([_vp, _vp, _vp], _i32),
 }
 
@@ -477,6 +479,13 @@ def set_cull(mode: int):
     without skipping."""
     lib = load()
     _chk(lib, lib.krr_set_cull(int(mode)))
+
+
+def set_pcg_mode(mode: int):
+    """PCG driver: -1 automatic, 0 host loop (one synchronisation per iteration), 1 graph-captured cycles of
+    replace_every iterations (one synchronisation per cycle).  Both give bit-identical results."""
+    lib = load()
+    _chk(lib, lib.krr_set_pcg_mode(int(mode)))
 
 
 def cull_stats():

@@ -3,7 +3,8 @@
 //
 //   gemm_tn:  C (ka x kb) = A^T B, A rows x ka, B rows x kb (the long dimension is the row count:
 //             W^T W and W^T X over n points).  Rows are split over the grid and the partial tiles
-//             are added in a fixed order, so the result does not depend on the launch.
+//             are added in a fixed order, so the result does not depend on the launch.  The partial
+//             tiles go to *ws when given (grown when too small; reused without allocating afterwards).
 //   syrk_tn:  C (k x k) = A^T A; only the upper block triangle is computed, the result is exactly
 //             symmetric.
 //   gemm_nn:  C (m x nb) = A B, A m x k, B k x nb; optional epilogue C = (X - A B) diag(scale)
@@ -17,7 +18,7 @@ namespace krr {
 
 template <typename TA, typename TB>
 void gemm_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, int64_t rows, int ka, int kb, double* C,
-             int64_t ldc, hipStream_t s);
+             int64_t ldc, hipStream_t s, DevBuf<double>* ws = nullptr);
 
 template <typename TA>
 void syrk_tn(const TA* A, int64_t lda, int64_t rows, int k, double* C, int64_t ldc, hipStream_t s);

@@ -236,12 +236,14 @@ int64_t tn_splits(int64_t tiles, int64_t rows, int64_t ka, int64_t kb, int64_t& 
 
 template <typename TA, typename TB, int BN, bool SYM>
 void launch_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, int64_t rows, int ka, int kb, double* C,
-               int64_t ldc, hipStream_t s) {
+               int64_t ldc, hipStream_t s, DevBuf<double>* ws) {
   const int nta = (int)ceil_div(ka, kBM), ntb = (int)ceil_div(kb, BN);
   const int64_t tiles = SYM ? (int64_t)nta * (nta + 1) / 2 : (int64_t)nta * ntb;
   int64_t chunk = 0;
   const int64_t S = tn_splits(tiles, rows, ka, kb, chunk);
-  DevBuf<double> part((size_t)S * ka * kb, s);
+  DevBuf<double> own;
+  DevBuf<double>& part = ws ? *ws : own;
+  if (part.n < (size_t)S * ka * kb) part.alloc((size_t)S * ka * kb, s);
   hipLaunchKernelGGL((k_gemm_tn<TA, TB, BN, SYM>), dim3((unsigned)tiles, (unsigned)S), dim3(256), 0, s, A, lda, B,
                      ldb, rows, ka, kb, chunk, ntb, part.p);
   KRR_LAUNCH_CHECK();
@@ -268,20 +270,20 @@ void launch_nn(const TA* A, int64_t lda, const double* B, int64_t ldb, int64_t m
 
 template <typename TA, typename TB>
 void gemm_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, int64_t rows, int ka, int kb, double* C,
-             int64_t ldc, hipStream_t s) {
+             int64_t ldc, hipStream_t s, DevBuf<double>* ws) {
   KRR_REQUIRE(rows >= 1 && ka >= 1 && kb >= 1, "gemm_tn: empty operand");
   switch (pick_bn(kb)) {
-    case 16: launch_tn<TA, TB, 16, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s); break;
-    case 32: launch_tn<TA, TB, 32, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s); break;
-    case 64: launch_tn<TA, TB, 64, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s); break;
-    default: launch_tn<TA, TB, 128, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s); break;
+    case 16: launch_tn<TA, TB, 16, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s, ws); break;
+    case 32: launch_tn<TA, TB, 32, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s, ws); break;
+    case 64: launch_tn<TA, TB, 64, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s, ws); break;
+    default: launch_tn<TA, TB, 128, false>(A, lda, B, ldb, rows, ka, kb, C, ldc, s, ws); break;
   }
 }
 
 template <typename TA>
 void syrk_tn(const TA* A, int64_t lda, int64_t rows, int k, double* C, int64_t ldc, hipStream_t s) {
   KRR_REQUIRE(rows >= 1 && k >= 1, "syrk_tn: empty operand");
-  launch_tn<TA, TA, 128, true>(A, lda, A, lda, rows, k, k, C, ldc, s);
+  launch_tn<TA, TA, 128, true>(A, lda, A, lda, rows, k, k, C, ldc, s, nullptr);
 }
 
 template <typename TA>
@@ -298,9 +300,9 @@ void gemm_nn(const TA* A, int64_t lda, const double* B, int64_t ldb, int64_t m, 
 }
 
 template void gemm_tn<double, double>(const double*, int64_t, const double*, int64_t, int64_t, int, int, double*,
-                                      int64_t, hipStream_t);
+                                      int64_t, hipStream_t, DevBuf<double>*);
 template void gemm_tn<float, double>(const float*, int64_t, const double*, int64_t, int64_t, int, int, double*,
-                                     int64_t, hipStream_t);
+                                     int64_t, hipStream_t, DevBuf<double>*);
 template void syrk_tn<double>(const double*, int64_t, int64_t, int, double*, int64_t, hipStream_t);
 template void syrk_tn<float>(const float*, int64_t, int64_t, int, double*, int64_t, hipStream_t);
 template void gemm_nn<double>(const double*, int64_t, const double*, int64_t, int64_t, int, int, double*, int64_t,

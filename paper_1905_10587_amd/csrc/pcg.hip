@@ -6,8 +6,13 @@
 // row-major.  The MVM runs in the working precision (FP64, FP32 or split-BF16 mixed); every
 // `replace_every` iterations, and whenever a column's recursive residual claims convergence, the
 // residual is recomputed as y - (K + beta I) x with the FP64 MVM (residual replacement).
-// Convergence is decided on the host from the R residual norms read back once per iteration.
+// Whether a column's recursive residual claims convergence is decided on the device (in the final kernel
+// of the residual-norm reduction); the host reads these claims with the norms and runs the true-residual
+// check, the stopping rules and the safeguards.  Two drivers run the same kernels in the same order: a host
+// loop with one synchronisation per iteration, and graph-captured cycles of `replace_every` iterations (one
+// launch and one synchronisation per cycle) that halt on the device when a claim or a breakdown needs the host.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -30,9 +35,24 @@ void validate_prec(int32_t prec);
 // part[by * R + c] over row groups, then a fixed-order sum over by.
 constexpr int kRedBlocks = 256;
 
+// Halt gate of the graph-captured cycles.  *halt is 0, or u + 1 once the status of the cycle's iteration u
+// has asked the host for a decision (a convergence claim or a breakdown); a gated kernel of stage `stage`
+// does nothing when a status of an earlier stage has halted the cycle (kernels of iteration u up to its
+// status have stage u + 1, the direction update after it u + 2).  halt == nullptr: never closed.
+struct Gate {
+  const int* halt = nullptr;
+  int stage = 0;
+  __device__ bool closed() const {
+    if (!halt) return false;
+    const int h = __hip_atomic_load(halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return h != 0 && h < stage;
+  }
+};
+
 template <int MODE>   // 0: sum a*b ; 1: sum a*a
 __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, const double* __restrict__ b,
-                                                int64_t n, int R, int CB, double* __restrict__ part) {
+                                                int64_t n, int R, int CB, double* __restrict__ part, Gate gate) {
+  if (gate.closed()) return;
   __shared__ double red[256];
   const int cl = threadIdx.x % CB;
   const int rl = threadIdx.x / CB;
@@ -59,7 +79,8 @@ __global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ a, co
 __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
                                                   const double* __restrict__ gamma, int64_t n, int R, int CB,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, Gate gate) {
+  if (gate.closed()) return;
   __shared__ double red[256];
   const int cl = threadIdx.x % CB;
   const int rl = threadIdx.x / CB;
@@ -88,10 +109,15 @@ __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double
 // Scalar work done by the final reduction kernel on the column's sum v (saves a launch per scalar step):
 //   kGamma:  gamma_c = rho_c / v for active columns (0 otherwise), breakdown flag if v <= 0 or not finite;
 //   kBeta:   beta_c = v / rho_c for active columns (0 otherwise; v is the new r^T z);
-//   kStatus: the per-iteration status for the host in one store into host-mapped memory,
-//            hs = [rr = v (R) | gamma (R) | beta of the previous iteration (R) | flags (2)].
+//   kStatus: the status of iteration it for the host, stored into host-mapped memory,
+//            hs = [rr = v (R) | gamma (R) | beta of the previous iteration (R) | claim (R) | flags (2)],
+//            claim_c = 1 when column c is active, it >= next_check_c and sqrt(v) / ||y_c|| <= tol (its
+//            recursive residual claims convergence); a claim or the breakdown flag closes the halt gate
+//            (when there is one) at this kernel's stage;
+//   kCheck:  the squared true residual norms of a check, also stored into hs (R).
+// it = *it_base + it_off (it_base may be null: it = it_off).
 struct DotEpilogue {
-  enum Mode { kNone = 0, kGamma = 1, kBeta = 2, kStatus = 3 };
+  enum Mode { kNone = 0, kGamma = 1, kBeta = 2, kStatus = 3, kCheck = 4 };
   int mode = kNone;
   const double* rho = nullptr;
   const int* active = nullptr;
@@ -99,11 +125,18 @@ struct DotEpilogue {
   double* beta = nullptr;
   int* flags = nullptr;
   double* hs = nullptr;
+  const int* next_check = nullptr;
+  const double* ynorm = nullptr;
+  double tol = 0.0;
+  const int* it_base = nullptr;
+  int it_off = 0;
+  int* halt = nullptr;
 };
 
 // out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256), then the epilogue.
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nby, int R,
-                                                      double* __restrict__ out, DotEpilogue e) {
+                                                      double* __restrict__ out, DotEpilogue e, Gate gate) {
+  if (gate.closed()) return;
   __shared__ double red[256];
   const int c = blockIdx.x;
   red[threadIdx.x] = (int)threadIdx.x < nby ? part[(int64_t)threadIdx.x * R + c] : 0.0;
@@ -127,13 +160,20 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
     if (e.active[c]) b = e.rho[c] != 0.0 ? v / e.rho[c] : 0.0;
     e.beta[c] = b;
   } else if (e.mode == DotEpilogue::kStatus) {
+    const int it = (e.it_base ? *e.it_base : 0) + e.it_off;
+    const bool claim = e.active[c] && it >= e.next_check[c] && sqrt(v) / e.ynorm[c] <= e.tol;
     e.hs[c] = v;
     e.hs[R + c] = e.gamma[c];
     e.hs[2 * R + c] = e.beta[c];
+    e.hs[3 * R + c] = claim ? 1.0 : 0.0;
+    const int broke = c == 0 ? e.flags[1] : 0;
     if (c == 0) {
-      e.hs[3 * R] = (double)e.flags[0];
-      e.hs[3 * R + 1] = (double)e.flags[1];
+      e.hs[4 * R] = (double)e.flags[0];
+      e.hs[4 * R + 1] = (double)broke;
     }
+    if (e.halt && (claim || broke)) __hip_atomic_store(e.halt, gate.stage, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if (e.mode == DotEpilogue::kCheck) {
+    e.hs[c] = v;
   }
 }
 
@@ -148,19 +188,19 @@ struct ColReducer {
   }
   // out[c] = sum_i a[i,c] * b[i,c]  (b == nullptr: sum a^2), then the epilogue's scalar step
   void dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s,
-           const DotEpilogue& e = DotEpilogue()) {
+           const DotEpilogue& e = DotEpilogue(), Gate gate = Gate()) {
     dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
-    if (b) hipLaunchKernelGGL(k_coldot<0>, grid, dim3(256), 0, s, a, b, n, R, CB, part.p);
-    else hipLaunchKernelGGL(k_coldot<1>, grid, dim3(256), 0, s, a, a, n, R, CB, part.p);
-    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out, e);
+    if (b) hipLaunchKernelGGL(k_coldot<0>, grid, dim3(256), 0, s, a, b, n, R, CB, part.p, gate);
+    else hipLaunchKernelGGL(k_coldot<1>, grid, dim3(256), 0, s, a, a, n, R, CB, part.p, gate);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, out, e, gate);
     KRR_LAUNCH_CHECK();
   }
   // x += gamma p, r -= gamma q, rr = column sums of the new r^2 (as dot(r, nullptr) after the update)
   void axpy2_rr(double* x, double* r, const double* p, const double* q, const double* gamma, int64_t n,
-                double* rr, hipStream_t s, const DotEpilogue& e) {
+                double* rr, hipStream_t s, const DotEpilogue& e, Gate gate = Gate()) {
     dim3 grid((unsigned)ceil_div(R, CB), kRedBlocks);
-    hipLaunchKernelGGL(k_axpy2_rr, grid, dim3(256), 0, s, x, r, p, q, gamma, n, R, CB, part.p);
-    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, rr, e);
+    hipLaunchKernelGGL(k_axpy2_rr, grid, dim3(256), 0, s, x, r, p, q, gamma, n, R, CB, part.p, gate);
+    hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)R), dim3(256), 0, s, part.p, kRedBlocks, R, rr, e, gate);
     KRR_LAUNCH_CHECK();
   }
 };
@@ -168,7 +208,8 @@ struct ColReducer {
 // ------------------------------------------------------------------ elementwise / scalar kernels
 // r = y - q for active columns
 __global__ void k_residual(double* __restrict__ r, const double* __restrict__ y, const double* __restrict__ q,
-                           const int* __restrict__ active, int64_t n, int R) {
+                           const int* __restrict__ active, int64_t n, int R, Gate gate) {
+  if (gate.closed()) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * R) return;
   if (active[t % R]) r[t] = y[t] - q[t];
@@ -191,7 +232,8 @@ static double* status_buffer(size_t count) {
 
 // p = z + beta p (active columns)
 __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ beta,
-                           const int* __restrict__ active, int64_t n, int R) {
+                           const int* __restrict__ active, int64_t n, int R, Gate gate) {
+  if (gate.closed()) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * R) return;
   const int c = (int)(t % R);
@@ -219,6 +261,24 @@ __global__ void k_absmax_flag(const double* __restrict__ a, int64_t cnt, int* __
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
     f |= a[i] != 0.0;
   if (f) atomicOr(flag, 1);
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) dst[t] = src[t];
+}
+
+// First and last node of a captured cycle: open the halt gate and take the cycle's starting iteration from
+// the host-mapped control words ctrl = [iteration, halt]; report the gate's final state there.
+__global__ void k_cycle_begin(int* __restrict__ halt, int* __restrict__ it_base, const double* __restrict__ ctrl) {
+  if (threadIdx.x == 0) {
+    *halt = 0;
+    *it_base = (int)ctrl[0];
+  }
+}
+
+__global__ void k_cycle_end(const int* __restrict__ halt, double* __restrict__ ctrl) {
+  if (threadIdx.x == 0) ctrl[1] = (double)*halt;
 }
 
 static unsigned nb(int64_t n) { return (unsigned)ceil_div(n, 256); }
@@ -311,6 +371,24 @@ struct Operator {
   }
 };
 
+// Driver selection (krr_set_pcg_mode): -1 automatic, 0 host loop, 1 graph-captured cycles.
+static std::atomic<int> g_pcg_mode{-1};
+void set_pcg_mode(int mode) { g_pcg_mode.store(mode); }
+
+// Iterations per captured cycle without scheduled replacements.
+constexpr int kGraphCycle = 16;
+
+// Automatic choice: graph cycles where launches and synchronisations are a visible share of an iteration
+// (products of at most 2^34 pair-columns: a few milliseconds of MVM at most).  Cycles are replace_every
+// iterations long (at most 64), or kGraphCycle without replacement.
+static bool use_graph_cycles(int64_t n, int R, int replace_every, bool timing) {
+  if (timing || replace_every > 64) return false;
+  const int mode = g_pcg_mode.load();
+  if (mode == 0) return false;
+  if (mode == 1) return true;
+  return (double)n * (double)n * (double)R <= 17179869184.0;
+}
+
 PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double* Y, int R, const double* betas,
                     const krr_precond* P, double tol, int maxit, int replace_every, int prec, double* x,
                     bool timing, hipStream_t s) {
@@ -339,8 +417,10 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     A64.init(X, n, d, eps, KRR_FP64, center.p, R, s);
     Atrue = &A64;
   }
+  WoodburyWork ww;
+  if (P) ww.prepare(*P, R, bidx.data(), s);
   DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s), p2(nR, s), q2(nR, s);
-  DevBuf<double> sc(7 * (size_t)R, s);   // rho (two buffers), pq, gamma, beta, rr, yy
+  DevBuf<double> sc(8 * (size_t)R, s);   // rho (two buffers), pq, gamma, beta, rr, yy, ||y||
   // r^T z of the current iteration and of the next one; the host swaps the two when an iteration
   // advances, so a discarded look-ahead leaves rho as it was
   double* rho = sc.p;
@@ -350,17 +430,25 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   double* beta = sc.p + 3 * R;
   double* rr = sc.p + 4 * R;
   double* yy = sc.p + 6 * R;
+  double* ynorm_d = sc.p + 7 * R;
   // current search direction and its product; the look-ahead iteration writes the other pair
   double* pp = p.p;
   double* qq = q.p;
   double* pa = p2.p;
   double* qa = q2.p;
   DevBuf<int> active(R, s), flags(2, s);
+  DevBuf<int> ictl(2 + (size_t)R, s);   // halt gate, cycle's first iteration, next_check (R)
+  int* halt_d = ictl.p;
+  int* it_base_d = ictl.p + 1;
+  int* next_check_d = ictl.p + 2;
   ColReducer red;
   red.init(R, s);
   std::vector<int> act(R, 1);
   std::vector<double> h(3 * (size_t)R);
   EventTimer tm(timing, s);
+  const bool graph_on = use_graph_cycles(n, R, replace_every, timing);
+  const int B = !graph_on ? 1 : replace_every > 0 ? replace_every : kGraphCycle;   // iterations per cycle
+  const bool cycle_check = replace_every > 0;   // a cycle ends with the scheduled check of its last iteration
 
   // ||y_c||
   red.dot(Y, nullptr, n, yy, s);
@@ -371,7 +459,16 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     ynorm[c] = std::sqrt(h[c]);
     if (!(ynorm[c] > 0)) act[c] = 0;
   }
-  KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+  std::vector<int> next_check(R, 0);
+  // device copies of the mask, the norms and the check schedule the status kernel decides claims with
+  // (copied from host vectors: the stream is synchronised before they change)
+  auto upload_state = [&]() {
+    KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    KRR_CHECK_HIP(hipMemcpyAsync(next_check_d, next_check.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+  };
+  KRR_CHECK_HIP(hipMemcpyAsync(ynorm_d, ynorm.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+  upload_state();
   // zero-rhs columns: alpha = 0
   // initial residual r = y - (K + beta I) x0 (FP64), skipped for a zero initial guess
   KRR_CHECK_HIP(hipMemsetAsync(flags.p, 0, 2 * sizeof(int), s));
@@ -385,20 +482,21 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     tm.stop();
     res.st.n_mvm_fp64++;
     KRR_CHECK_HIP(hipMemcpyAsync(r.p, Y, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R);
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, q.p, active.p, n, R, Gate());
   } else {
     KRR_CHECK_HIP(hipMemcpyAsync(r.p, Y, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
   }
-  auto precondition = [&](const double* in, double* out) {
+  auto precondition = [&](const double* in, double* out, hipStream_t st) {
     if (P) {
       tm.start(&res.st.t_precond_ms);
-      woodbury_apply(*P, in, R, bidx.data(), prec != KRR_FP64, out, s);
+      woodbury_apply(*P, in, ww, prec != KRR_FP64, out, st);
       tm.stop();
     } else {
-      KRR_CHECK_HIP(hipMemcpyAsync(out, in, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_copy, dim3(nb(nR)), dim3(256), 0, st, out, in, nR);
+      KRR_LAUNCH_CHECK();
     }
   };
-  precondition(r.p, z.p);
+  precondition(r.p, z.p, s);
   KRR_CHECK_HIP(hipMemcpyAsync(pp, z.p, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
   red.dot(r.p, z.p, n, rho, s);
 
@@ -407,7 +505,12 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // recurrence, after which the coefficients no longer describe a Lanczos process of the operator.
   std::vector<double> lanczos_g, lanczos_b;
   bool lanczos_open = true, pending_b = false;
-  double* hs = status_buffer(3 * (size_t)R + 2);
+  // host-mapped status words: one status per iteration of a cycle, the true residuals of its check, and
+  // the control words [first iteration, halt]
+  const size_t SS = 4 * (size_t)R + 2;
+  double* hs = status_buffer(B * SS + R + 2);
+  double* hcheck = hs + B * SS;
+  double* hctrl = hcheck + R;
   // Safeguards: the best iterate by true residual is kept per column.  The residual 2-norm of CG is
   // not monotone (CG minimises the A-norm of the error), so a column is only stopped (KRR_ENOCONV, best
   // iterate returned) when its true residual is not finite or exceeds 1e6 times its best, or when its
@@ -417,7 +520,8 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   DevBuf<double> xbest(nR, s);
   DevBuf<int> mask(R, s);
   std::vector<double> best_rel(R, HUGE_VAL);
-  std::vector<int> stall(R, 0), next_check(R, 0), gave_up(R, 0);
+  std::vector<int> stall(R, 0), gave_up(R, 0);
+  std::vector<char> claim(R, 0);
   const int recheck = std::max(replace_every, 5);
   auto copy_columns = [&](double* dst, const double* src, const std::vector<int>& m) {
     KRR_CHECK_HIP(hipMemcpyAsync(mask.p, m.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
@@ -450,72 +554,37 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     e.beta = beta;
     return e;
   };
-  DotEpilogue epi_status;
-  epi_status.mode = DotEpilogue::kStatus;
-  epi_status.gamma = gamma;
-  epi_status.beta = beta;
-  epi_status.flags = flags.p;
-  epi_status.hs = hs;
-  // Look-ahead: after the status of iteration `it` is enqueued, the next iteration's preconditioner
-  // apply, p update and product are enqueued too (into the second p / q buffers), and the host then waits
-  // for the status only, so the GPU is not idle while the host reads it and launches the next kernels.
-  // The look-ahead is kept when the status asks for nothing (the common case): its kernels are the ones the
-  // iteration would have launched, on the same data, so the iterates are unchanged.  It is not started
-  // before a scheduled residual replacement, and it is discarded (rho left as it was, its product's time not
-  // counted) when the status triggers a true-residual check or reports a breakdown.
-  hipEvent_t ev_status;
-  KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
-  struct EventGuard {
-    hipEvent_t e;
-    ~EventGuard() { (void)hipEventDestroy(e); }
-  } ev_guard{ev_status};
-  double discarded_ms = 0.0;
-  bool have_next = false;   // this iteration's product was enqueued by the previous look-ahead
-  bool fresh_true = false;  // the true residuals of the current x were computed by this iteration's check
-  while (any_active && it < maxit) {
-    ++it;
-    fresh_true = false;
-    // q = (K + beta I) p in the working precision
-    if (!have_next) {
-      tm.start(&res.st.t_mvm_ms);
-      Aw.apply(pp, betas, qq, s, tm.external(&res.st.t_mvm_kernel_ms));
-      tm.stop();
-    }
-    have_next = false;
-    res.st.n_mvm++;
-    red.dot(pp, qq, n, pq, s, epi_gamma(rho));
-    red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, s, epi_status);
-    KRR_CHECK_HIP(hipEventRecord(ev_status, s));
-    const size_t tmark = tm.marks();
-    const bool scheduled = replace_every > 0 && it % replace_every == 0;
-    const bool ahead = !scheduled && it < maxit;
-    if (ahead) {
-      precondition(r.p, z.p);
-      red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
-      hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
-                         (const double*)beta, (const int*)active.p, n, R);
-      KRR_LAUNCH_CHECK();
-      tm.start(&res.st.t_mvm_ms);
-      Aw.apply(pa, betas, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
-      tm.stop();
-    }
-    KRR_CHECK_HIP(hipEventSynchronize(ev_status));
-    tm.collect(tmark);
-    std::copy(hs, hs + 2 * (size_t)R, h.begin());
-    if (hs[3 * R + 1] != 0.0) {
-      tm.retarget(&discarded_ms);
-      breakdown = true;
-      break;
-    }
-    if (pending_b) lanczos_b.push_back(hs[2 * R]);   // beta of the previous iteration, column 0
+  // the status of iteration *it_base + it_off into `slot`; halt: the cycle's gate (null in the host loop)
+  auto epi_status = [&](double* slot, const int* it_base, int it_off, int* halt) {
+    DotEpilogue e;
+    e.mode = DotEpilogue::kStatus;
+    e.active = active.p;
+    e.gamma = gamma;
+    e.beta = beta;
+    e.flags = flags.p;
+    e.hs = slot;
+    e.next_check = next_check_d;
+    e.ynorm = ynorm_d;
+    e.tol = tol;
+    e.it_base = it_base;
+    e.it_off = it_off;
+    e.halt = halt;
+    return e;
+  };
+  // Reads the status of iteration `it`: Lanczos coefficients, iteration counts, the columns' claims.
+  // Returns false on a breakdown.
+  auto read_status = [&](const double* st, bool& candidate) -> bool {
+    candidate = false;
+    if (st[4 * R + 1] != 0.0) return false;
+    if (pending_b) lanczos_b.push_back(st[2 * R]);   // beta of the previous iteration, column 0
     pending_b = false;
-    std::vector<double> hrec(h.begin(), h.begin() + R);
-    if (act[0] && lanczos_open) lanczos_g.push_back(h[R]);
-    bool candidate = false;
+    if (act[0] && lanczos_open) lanczos_g.push_back(st[R]);
     for (int c = 0; c < R; ++c) {
+      h[c] = st[c];
+      claim[c] = st[3 * R + c] != 0.0;
       if (!act[c]) continue;
       res.iters[c] = it;
-      if (it >= next_check[c] && std::sqrt(h[c]) / ynorm[c] <= tol) {
+      if (claim[c]) {
         candidate = true;
         if (c == 0) lanczos_open = false;
       }
@@ -528,6 +597,241 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
                    std::chrono::duration<double, std::milli>(clk::now() - t_start).count());
       std::fflush(stderr);
     }
+    return true;
+  };
+  bool fresh_true = false;  // the true residuals of the current x were computed by this iteration's check
+  // The decisions on the squared true residual norms rrt of the current x (a check): converged columns stop,
+  // the best iterate is kept, stalled or diverging columns stop.
+  auto decide = [&](const double* rrt) {
+    bool changed = false, improved = false;
+    std::vector<int> imp(R, 0);
+    for (int c = 0; c < R; ++c) {
+      if (!act[c]) continue;
+      const double rel = std::sqrt(rrt[c]) / ynorm[c];
+      res.relres[c] = rel;
+      if (rel <= tol) {
+        act[c] = 0;
+        changed = true;
+        continue;
+      }
+      // only a column whose recursive residual claimed convergence and failed the check waits before
+      // its next check; a scheduled replacement leaves the others free to claim at the next iteration
+      if (claim[c]) {
+        next_check[c] = it + recheck;
+        ++stall[c];
+        changed = true;
+      }
+      if (rel < best_rel[c]) {
+        best_rel[c] = rel;
+        imp[c] = 1;
+        improved = true;
+      }
+      if (stall[c] >= 8 || rel > 1e6 * best_rel[c] || !std::isfinite(rel)) {
+        act[c] = 0;
+        gave_up[c] = 1;
+        changed = true;
+      }
+    }
+    if (improved) copy_columns(xbest.p, x, imp);
+    if (changed) upload_state();
+    fresh_true = true;
+  };
+  // true residual in FP64 (replaces the recursive one), then the decisions
+  auto check = [&](bool scheduled) {
+    tm.start(&res.st.t_mvm_fp64_ms);
+    Atrue->apply(x, betas, qq, s);
+    tm.stop();
+    res.st.n_mvm_fp64++;
+    if (scheduled) res.st.n_replace++;
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R, Gate());
+    red.dot(r.p, nullptr, n, rr, s);
+    KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    KRR_CHECK_HIP(hipStreamSynchronize(s));
+    tm.collect();
+    decide(h.data());
+  };
+  // the next direction after a decision: z = M^{-1} r, beta = r^T z / rho, p = z + beta p
+  auto enqueue_direction = [&](hipStream_t st, Gate gate) {
+    precondition(r.p, z.p, st);
+    red.dot(r.p, z.p, n, rho_new, st, epi_beta(rho), gate);
+    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, st, pp, z.p, beta, active.p, n, R, gate);
+    KRR_LAUNCH_CHECK();
+    std::swap(rho, rho_new);
+  };
+  hipEvent_t ev_status;
+  KRR_CHECK_HIP(hipEventCreateWithFlags(&ev_status, hipEventDisableTiming));
+  struct EventGuard {
+    hipEvent_t e;
+    ~EventGuard() { (void)hipEventDestroy(e); }
+  } ev_guard{ev_status};
+
+  // Graph-captured cycles.  A cycle starts after the host's decisions on the previous iteration and holds:
+  // the next direction, `B` iterations (the MVM, p^T q, the x / r update with the status, and, except after
+  // the last, the next direction), then, with scheduled replacements, the check of the last iteration (FP64
+  // product, r = y - (K + beta I) x, its norms).  The status kernels decide the claims on the device; a claim or a breakdown
+  // closes the halt gate, after which the remaining kernels that change the solver's state do nothing, so x,
+  // r, p and the scalars are those of the iteration that asked, exactly as the host loop leaves them.  The
+  // host then reads the statuses and continues as the host loop does.  The products of the iterations after
+  // a halt still run (on scratch buffers; their results are not used).  One graph is captured per set of
+  // buffer pointers it reads (the direction / product buffers and the parity of the two rho buffers).
+  struct CycleGraph {
+    const double *pp, *qq, *rho;
+    hipGraphExec_t exec;
+  };
+  std::vector<CycleGraph> graphs;
+  hipStream_t cs = nullptr;   // capture stream (a graph is captured on it and launched on s)
+  struct GraphGuard {
+    std::vector<CycleGraph>& g;
+    hipStream_t& cs;
+    ~GraphGuard() {
+      for (auto& c : g) (void)hipGraphExecDestroy(c.exec);
+      if (cs) (void)hipStreamDestroy(cs);
+    }
+  } graph_guard{graphs, cs};
+  auto cycle_graph = [&]() -> hipGraphExec_t {
+    for (auto& c : graphs)
+      if (c.pp == pp && c.qq == qq && c.rho == rho) return c.exec;
+    if (!cs) KRR_CHECK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    KRR_CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    double* rho0 = rho;
+    double* rho_new0 = rho_new;
+    try {
+      hipLaunchKernelGGL(k_cycle_begin, dim3(1), dim3(64), 0, cs, halt_d, it_base_d, (const double*)hctrl);
+      enqueue_direction(cs, Gate());
+      for (int u = 0; u < B; ++u) {
+        Aw.apply(pp, betas, qq, cs);
+        red.dot(pp, qq, n, pq, cs, epi_gamma(rho), Gate{halt_d, u + 1});
+        red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, cs, epi_status(hs + u * SS, it_base_d, u + 1, halt_d),
+                     Gate{halt_d, u + 1});
+        if (u + 1 < B) enqueue_direction(cs, Gate{halt_d, u + 2});
+      }
+      if (cycle_check) {
+        Atrue->apply(x, betas, qq, cs);
+        hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, cs, r.p, Y, qq, active.p, n, R,
+                           Gate{halt_d, B});
+        DotEpilogue ec;
+        ec.mode = DotEpilogue::kCheck;
+        ec.hs = hcheck;
+        red.dot(r.p, nullptr, n, rr, cs, ec, Gate{halt_d, B});
+      }
+      hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, cs, (const int*)halt_d, hctrl);
+      KRR_LAUNCH_CHECK();
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      rho = rho0;
+      rho_new = rho_new0;
+      throw;
+    }
+    rho = rho0;   // the capture only recorded the launches; the host's pointers advance when a cycle runs
+    rho_new = rho_new0;
+    KRR_CHECK_HIP(hipStreamEndCapture(cs, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    KRR_CHECK_HIP(ie);
+    graphs.push_back(CycleGraph{pp, qq, rho, exec});
+    return exec;
+  };
+
+  // Host loop.  Look-ahead: after iteration i's status kernel the host also enqueues iteration i+1's
+  // preconditioner apply, p update and product (into the second p / q buffers), and then waits for the status
+  // only, so the GPU is not idle while the host reads it and launches the next kernels.  The look-ahead is
+  // kept when the status asks for nothing (the common case): its kernels are the ones the iteration would
+  // have launched, on the same data, so the iterates are unchanged.  It is not started before a scheduled
+  // residual replacement, and it is discarded (rho left as it was, its product's time not counted) when the
+  // status reports a claim or a breakdown.  With graphs on, every B iterations (at the scheduled replacements,
+  // else every kGraphCycle iterations; no look-ahead there) the loop hands over to a captured cycle when a
+  // whole cycle fits before maxit, and takes over again after a cycle that halted, until the next such point.
+  double discarded_ms = 0.0;
+  bool have_next = false;   // this iteration's product was enqueued by the previous look-ahead
+  bool need_dir = false;    // the next direction after a decision has not been enqueued yet
+  while (any_active && it < maxit) {
+    if (graph_on && need_dir && it % B == 0 && it + B <= maxit) {
+      hipGraphExec_t exec = cycle_graph();
+      hctrl[0] = (double)it;
+      hctrl[1] = 0.0;
+      KRR_CHECK_HIP(hipGraphLaunch(exec, s));
+      KRR_CHECK_HIP(hipEventRecord(ev_status, s));
+      KRR_CHECK_HIP(hipEventSynchronize(ev_status));
+      res.st.n_graph_cycles++;
+      need_dir = false;
+      fresh_true = false;
+      std::swap(rho, rho_new);   // the cycle's first direction
+      pending_b = act[0] && lanczos_open;
+      const int halt = (int)hctrl[1];
+      KRR_REQUIRE(halt >= 0 && halt <= B, "internal: cycle halt word out of range");
+      const int nu = halt ? halt : B;   // iterations whose status is valid
+      bool candidate = false;
+      for (int u = 0; u < nu; ++u) {
+        ++it;
+        res.st.n_mvm++;
+        res.st.n_graph_iters++;
+        if (!read_status(hs + u * SS, candidate)) {
+          breakdown = true;
+          break;
+        }
+        KRR_REQUIRE(!candidate || u + 1 == nu, "internal: a claim did not halt the cycle");
+        if (u + 1 < nu) {   // this iteration's next direction ran
+          std::swap(rho, rho_new);
+          pending_b = act[0] && lanczos_open;
+        }
+      }
+      if (breakdown) break;
+      if (cycle_check && (halt == 0 || halt == B)) {   // the check of the last (scheduled) iteration ran
+        res.st.n_mvm_fp64++;
+        res.st.n_replace++;
+        decide(hcheck);
+      } else if (candidate) {
+        check(false);   // a claim that the cycle's own check does not cover
+      }
+      any_active = false;
+      for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
+      if (!any_active || it >= maxit) break;
+      need_dir = true;
+      continue;
+    }
+    if (need_dir) {
+      enqueue_direction(s, Gate());
+      pending_b = act[0] && lanczos_open;   // read with the next iteration's status
+      need_dir = false;
+    }
+    ++it;
+    fresh_true = false;
+    // q = (K + beta I) p in the working precision
+    if (!have_next) {
+      tm.start(&res.st.t_mvm_ms);
+      Aw.apply(pp, betas, qq, s, tm.external(&res.st.t_mvm_kernel_ms));
+      tm.stop();
+    }
+    have_next = false;
+    res.st.n_mvm++;
+    red.dot(pp, qq, n, pq, s, epi_gamma(rho));
+    red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, s, epi_status(hs, nullptr, it, nullptr));
+    KRR_CHECK_HIP(hipEventRecord(ev_status, s));
+    const size_t tmark = tm.marks();
+    const bool scheduled = replace_every > 0 && it % replace_every == 0;
+    const bool handover = graph_on && it % B == 0;   // a cycle may start after this iteration
+    const bool ahead = !scheduled && !handover && it < maxit;
+    if (ahead) {
+      precondition(r.p, z.p, s);
+      red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
+      hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
+                         (const double*)beta, (const int*)active.p, n, R);
+      KRR_LAUNCH_CHECK();
+      tm.start(&res.st.t_mvm_ms);
+      Aw.apply(pa, betas, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
+      tm.stop();
+    }
+    KRR_CHECK_HIP(hipEventSynchronize(ev_status));
+    tm.collect(tmark);
+    bool candidate = false;
+    if (!read_status(hs, candidate)) {
+      tm.retarget(&discarded_ms);
+      breakdown = true;
+      break;
+    }
     if (ahead && !candidate) {   // keep the look-ahead: it is the next iteration's direction and product
       std::swap(pp, pa);
       std::swap(qq, qa);
@@ -537,60 +841,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       continue;
     }
     if (ahead) tm.retarget(&discarded_ms);   // discard it: the true-residual check below replaces r first
-    if (candidate || scheduled) {
-      // true residual in FP64 (replaces the recursive one)
-      tm.start(&res.st.t_mvm_fp64_ms);
-      Atrue->apply(x, betas, qq, s);
-      tm.stop();
-      res.st.n_mvm_fp64++;
-      if (scheduled) res.st.n_replace++;
-      hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R);
-      red.dot(r.p, nullptr, n, rr, s);
-      KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-      KRR_CHECK_HIP(hipStreamSynchronize(s));
-      tm.collect();
-      bool changed = false, improved = false;
-      std::vector<int> imp(R, 0);
-      for (int c = 0; c < R; ++c) {
-        if (!act[c]) continue;
-        const double rel = std::sqrt(h[c]) / ynorm[c];
-        res.relres[c] = rel;
-        if (rel <= tol) {
-          act[c] = 0;
-          changed = true;
-          continue;
-        }
-        // only a column whose recursive residual claimed convergence and failed the check waits before
-        // its next check; a scheduled replacement leaves the others free to claim at the next iteration
-        const bool was_candidate = it >= next_check[c] && std::sqrt(hrec[c]) / ynorm[c] <= tol;
-        if (was_candidate) {
-          next_check[c] = it + recheck;
-          ++stall[c];
-        }
-        if (rel < best_rel[c]) {
-          best_rel[c] = rel;
-          imp[c] = 1;
-          improved = true;
-        }
-        if (stall[c] >= 8 || rel > 1e6 * best_rel[c] || !std::isfinite(rel)) {
-          act[c] = 0;
-          gave_up[c] = 1;
-          changed = true;
-        }
-      }
-      if (improved) copy_columns(xbest.p, x, imp);
-      if (changed) KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
-      fresh_true = true;
-    }
+    if (candidate || scheduled) check(scheduled);
     any_active = false;
     for (int c = 0; c < R; ++c) any_active |= act[c] != 0;
     if (!any_active || it >= maxit) break;   // no next direction is needed after the last iteration
-    precondition(r.p, z.p);
-    red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
-    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, s, pp, z.p, beta, active.p, n, R);
-    KRR_LAUNCH_CHECK();
-    std::swap(rho, rho_new);
-    pending_b = act[0] && lanczos_open;   // read with the next iteration's status
+    need_dir = true;
   }
   // final true residuals for columns still active (maxit or breakdown); stopped columns return their
   // best iterate
@@ -599,7 +854,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   if (unfinished && !fresh_true) {   // (after a check in the last iteration its residuals are current)
     Atrue->apply(x, betas, qq, s);
     res.st.n_mvm_fp64++;
-    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R);
+    hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R, Gate());
     red.dot(r.p, nullptr, n, rr, s);
     KRR_CHECK_HIP(hipMemcpyAsync(h.data(), rr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
     KRR_CHECK_HIP(hipStreamSynchronize(s));
@@ -680,6 +935,14 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
 }
 
 }  // namespace krr
+
+extern "C" int krr_set_pcg_mode(int32_t mode) {
+  return krr::guarded([&] {
+    KRR_REQUIRE(mode >= -1 && mode <= 1, "mode must be -1 (automatic), 0 (host loop) or 1 (graph cycles)");
+    krr::set_pcg_mode(mode);
+    return (int)KRR_OK;
+  });
+}
 
 extern "C" int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps, const double* Yrhs, int32_t R,
                              const double* betas, const krr_precond* P, double tol, int32_t maxit,

@@ -34,4 +34,17 @@ int beta_index(const krr_precond& P, double beta);   // -1 if absent
 void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
                     hipStream_t s);
 
+// The buffers of the apply for one set of R columns and their betas, allocated and filled once by prepare();
+// applies through it launch kernels only (no allocation, no host copy), so they can be captured in a graph.
+struct WoodburyWork {
+  int R = 0;
+  std::vector<int> bidx_host;
+  DevBuf<double> partial, t, z;           // one column: W^T x partial sums, t = W^T x, z = G t
+  DevBuf<double> invb, T, Zall, Z, tn;    // several columns: 1 / beta, W^T X, G_b T for every beta, selection,
+  DevBuf<int> bidx;                       // the row-split partial tiles of W^T X, beta index per column
+  void prepare(const krr_precond& P, int R_, const int* bidx_host_, hipStream_t s);
+};
+void woodbury_apply(const krr_precond& P, const double* x, WoodburyWork& w, bool use32, double* out,
+                    hipStream_t s);
+
 }  // namespace krr

@@ -201,36 +201,59 @@ static int64_t woodbury_column_scratch(const krr_precond& P) {
   return ceil_div(P.n, kWRows) * (int64_t)P.kept + 2 * (int64_t)P.kept;
 }
 
-void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
+void WoodburyWork::prepare(const krr_precond& P, int R_, const int* bidx_host_, hipStream_t s) {
+  R = R_;
+  bidx_host.assign(bidx_host_, bidx_host_ + R);
+  const int kept = P.kept;
+  if (R == 1) {
+    partial.alloc((size_t)ceil_div(P.n, kWRows) * kept, s);
+    t.alloc(kept, s);
+    z.alloc(kept, s);
+    return;
+  }
+  const int nbeta = (int)P.betas.size();
+  std::vector<double> ib(R);
+  for (int r = 0; r < R; ++r) ib[r] = 1.0 / P.betas[bidx_host[r]];
+  invb.alloc(R, s);
+  bidx.alloc(R, s);
+  KRR_CHECK_HIP(hipMemcpyAsync(invb.p, ib.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+  KRR_CHECK_HIP(hipMemcpyAsync(bidx.p, bidx_host.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+  KRR_CHECK_HIP(hipStreamSynchronize(s));   // the host vectors above are temporaries
+  T.alloc((size_t)kept * R, s);
+  Zall.alloc((size_t)nbeta * kept * R, s);
+  Z.alloc((size_t)kept * R, s);
+}
+
+void woodbury_apply(const krr_precond& P, const double* x, WoodburyWork& w, bool use32, double* out,
                     hipStream_t s) {
   const int kept = P.kept;
   const int64_t n = P.n;
+  const int R = w.R;
   KRR_REQUIRE(!use32 || P.W32.p, "preconditioner was built without an FP32 factor");
   if (R == 1) {
-    DevBuf<double> partial((size_t)ceil_div(n, kWRows) * kept, s), t(kept, s), z(kept, s);
-    woodbury_one_column(P, x, 1, bidx_host[0], use32, out, 1, partial.p, t.p, z.p, s);
+    woodbury_one_column(P, x, 1, w.bidx_host[0], use32, out, 1, w.partial.p, w.t.p, w.z.p, s);
     return;
   }
   // Block form (FP64 matrix cores; the FP32 factor's products are exact in FP64): T = W^T X, summed over row
   // splits in a fixed order; Z_b = G_b T for each beta; column r takes Z_{beta_r}; out = (X - W Z) diag(1/beta).
   const int nbeta = (int)P.betas.size();
-  std::vector<double> ib(R);
-  for (int r = 0; r < R; ++r) ib[r] = 1.0 / P.betas[bidx_host[r]];
-  DevBuf<double> invb(R, s);
-  DevBuf<int> bidx(R, s);
-  KRR_CHECK_HIP(hipMemcpyAsync(invb.p, ib.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
-  KRR_CHECK_HIP(hipMemcpyAsync(bidx.p, bidx_host, sizeof(int) * R, hipMemcpyHostToDevice, s));
-  DevBuf<double> T((size_t)kept * R, s), Zall((size_t)nbeta * kept * R, s), Z((size_t)kept * R, s);
-  if (use32) gemm_tn<float, double>(P.W32.p, kept, x, R, n, kept, R, T.p, R, s);
-  else gemm_tn<double, double>(P.W64.p, kept, x, R, n, kept, R, T.p, R, s);
+  if (use32) gemm_tn<float, double>(P.W32.p, kept, x, R, n, kept, R, w.T.p, R, s, &w.tn);
+  else gemm_tn<double, double>(P.W64.p, kept, x, R, n, kept, R, w.T.p, R, s, &w.tn);
   for (int b = 0; b < nbeta; ++b) {
     const double* G = use32 ? P.G32[b].p : P.G64[b].p;
-    gemm_nn<double>(G, kept, T.p, R, kept, kept, R, Zall.p + (int64_t)b * kept * R, R, nullptr, 0, nullptr, s);
+    gemm_nn<double>(G, kept, w.T.p, R, kept, kept, R, w.Zall.p + (int64_t)b * kept * R, R, nullptr, 0, nullptr, s);
   }
-  hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, Zall.p, kept, R, bidx.p, Z.p);
+  hipLaunchKernelGGL(k_select_z, dim3(nblk((int64_t)kept * R)), dim3(256), 0, s, w.Zall.p, kept, R, w.bidx.p, w.Z.p);
   KRR_LAUNCH_CHECK();
-  if (use32) gemm_nn<float>(P.W32.p, kept, Z.p, R, n, kept, R, out, R, x, R, invb.p, s);
-  else gemm_nn<double>(P.W64.p, kept, Z.p, R, n, kept, R, out, R, x, R, invb.p, s);
+  if (use32) gemm_nn<float>(P.W32.p, kept, w.Z.p, R, n, kept, R, out, R, x, R, w.invb.p, s);
+  else gemm_nn<double>(P.W64.p, kept, w.Z.p, R, n, kept, R, out, R, x, R, w.invb.p, s);
+}
+
+void woodbury_apply(const krr_precond& P, const double* x, int R, const int* bidx_host, bool use32, double* out,
+                    hipStream_t s) {
+  WoodburyWork w;
+  w.prepare(P, R, bidx_host, s);
+  woodbury_apply(P, x, w, use32, out, s);
 }
 
 // ------------------------------------------------------------------ build
