@@ -212,8 +212,9 @@ int krr_precond_apply(const krr_precond* P, const double* x, int32_t R, const do
  * krr_precond_apply without device allocation, for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid hipMalloc).  Same arguments and result as
  * krr_precond_apply; the columns are applied one at a time with the one-column kernels, so for R > 1 the
- * rounding differs from krr_precond_apply's several-column products.  Scratch (ceil(n / 256) * kept + 2 * kept
- * doubles: the W^T x partial sums, t and z) lives in a 64 MiB device array that the library holds on every
+ * rounding differs from krr_precond_apply's several-column products.  Scratch (at most
+ * max(256, ceil(n / 256)) * kept + 2 * kept doubles: the W^T x partial sums, t and z) lives in a 64 MiB
+ * device array that the library holds on every
  * GPU it runs on until the process ends; larger preconditioners return KRR_EINVAL before any GPU work.
  * Nothing is allocated and no library routine that allocates is called.  All calls on one GPU share that
  * array: calls that overlap in time on one GPU (other streams, other threads) race and must be serialised by

@@ -710,6 +710,14 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     src_len = std::max<int64_t>(round_up(split_req, 256), round_up(ceil_div(nsrc, smax), 256));
     split = ceil_div(nsrc, src_len);
   }
+  // Small one-column FP64 products: when splits of 256 sources leave CUs idle, the sources are split in
+  // multiples of 64 (the direct kernel's 64-point tile form) for about two blocks per CU.
+  if (prec == KRR_FP64 && !sym && !f64m && !block && R == 1 && DV == 0 && TM == 1 && split_req <= 0 &&
+      D <= 16 && per_split * split < device_cus()) {
+    const int64_t sp = std::min<int64_t>(std::max<int64_t>(1, nsrc / 64), ceil_div(2 * device_cus(), per_split));
+    src_len = round_up(ceil_div(nsrc, sp), 64);
+    split = ceil_div(nsrc, src_len);
+  }
   KmvGrid g{dim3((unsigned)gx, (unsigned)split, (unsigned)gz), src_len, nsrc, T.npad, RpK, RoutK};
   if (sym) {
     KRR_REQUIRE(RoutK == 1, "internal: the symmetric kernels write dense one-column partials");

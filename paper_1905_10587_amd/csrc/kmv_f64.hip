@@ -4,15 +4,15 @@
 
 namespace krr {
 
-template <int D, int TM, int RC, int DV>
+template <int D, int TM, int RC, int DV, int TSX = 0>
 static void go64(const KmvGrid& g, const double* xt, const double* xs, const double* v, double neg_c,
                  double* part, hipStream_t s) {
   if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64<D, TM, RC, DV>, 256, 0));
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64<D, TM, RC, DV, TSX>, 256, 0));
     return;
   }
-  hipLaunchKernelGGL((k_kmv_f64<D, TM, RC, DV>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
-                     neg_c, part, g.mpad, g.Rout);
+  hipLaunchKernelGGL((k_kmv_f64<D, TM, RC, DV, TSX>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len,
+                     g.n_src, neg_c, part, g.mpad, g.Rout);
 }
 
 #define KRR_DV(D, TM, RC)                                   \
@@ -81,6 +81,18 @@ bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const 
 
 bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const double* xt, const double* xs,
                     const double* v, double neg_c, double* part, hipStream_t s) {
+  if (g.src_len % 256 != 0) {   // short source splits: the 64-point tile form (one column, K only, D <= 16)
+    if (TM != 1 || RC != 1 || DV != 0 || g.src_len % 64 != 0) return false;
+    switch (D) {
+      case 2: go64<2, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+      case 3: go64<3, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+      case 4: go64<4, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+      case 6: go64<6, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+      case 8: go64<8, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+      case 16: go64<16, 1, 1, 0, 64>(g, xt, xs, v, neg_c, part, s); return true;
+    }
+    return false;
+  }
   switch (D) {
     case 2: KRR_TM3(2) break;
     case 3: KRR_TM3(3) break;

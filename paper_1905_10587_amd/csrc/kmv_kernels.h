@@ -47,14 +47,16 @@ struct DirectTile {
   static constexpr int TS = D <= 16 ? 256 : (D <= 32 ? 128 : 64);
 };
 
-template <int D, int TM, int RC, int DV>
+// TSX != 0: source tiles of TSX points (the short-split form for small products, whose source splits are
+// multiples of TSX rather than of 256).
+template <int D, int TM, int RC, int DV, int TSX = 0>
 __global__ __launch_bounds__(256) void k_kmv_f64(const double* __restrict__ xt, const double* __restrict__ xs,
                                                  const double* __restrict__ v, int Rp, int64_t src_len,
                                                  int64_t n_src, double neg_c, double* __restrict__ part,
                                                  int64_t mpad, int Rout) {
   // neg_c = -log2(e) / eps: the exponent q = neg_c * D^2 is the base-2 exponent of the kernel value
   constexpr int NO = DV == 2 ? 2 : 1;
-  constexpr int TS = DirectTile<D>::TS * 8 / (RC > 8 ? RC : 8);   // wide column chunks: shorter tiles
+  constexpr int TS = TSX ? TSX : DirectTile<D>::TS * 8 / (RC > 8 ? RC : 8);   // wide column chunks: shorter tiles
   __shared__ double sx[TS * D];
   __shared__ double sv[TS * RC];
   const int64_t ibase = (int64_t)blockIdx.x * (256 * TM) + threadIdx.x;

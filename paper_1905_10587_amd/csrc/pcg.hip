@@ -133,20 +133,9 @@ struct DotEpilogue {
   int* halt = nullptr;
 };
 
-// out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256), then the epilogue.
-__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nby, int R,
-                                                      double* __restrict__ out, DotEpilogue e, Gate gate) {
-  if (gate.closed()) return;
-  __shared__ double red[256];
-  const int c = blockIdx.x;
-  red[threadIdx.x] = (int)threadIdx.x < nby ? part[(int64_t)threadIdx.x * R + c] : 0.0;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double v = red[0];
+// The epilogue of column c's sum v (thread-level; out[c] = v first).
+__device__ __forceinline__ void dot_epilogue(const DotEpilogue& e, const Gate& gate, int c, int R, double v,
+                                             double* __restrict__ out) {
   out[c] = v;
   if (e.mode == DotEpilogue::kGamma) {
     double g = 0.0;
@@ -166,7 +155,7 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
     e.hs[R + c] = e.gamma[c];
     e.hs[2 * R + c] = e.beta[c];
     e.hs[3 * R + c] = claim ? 1.0 : 0.0;
-    const int broke = c == 0 ? e.flags[1] : 0;
+    const int broke = c == 0 ? __hip_atomic_load(e.flags + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (c == 0) {
       e.hs[4 * R] = (double)e.flags[0];
       e.hs[4 * R + 1] = (double)broke;
@@ -174,6 +163,127 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
     if (e.halt && (claim || broke)) __hip_atomic_store(e.halt, gate.stage, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else if (e.mode == DotEpilogue::kCheck) {
     e.hs[c] = v;
+  }
+}
+
+// out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256), then the epilogue.
+__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nby, int R,
+                                                      double* __restrict__ out, DotEpilogue e, Gate gate) {
+  if (gate.closed()) return;
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  red[threadIdx.x] = (int)threadIdx.x < nby ? part[(int64_t)threadIdx.x * R + c] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dot_epilogue(e, gate, c, R, red[0], out);
+}
+
+// ------------------------------------------------------------------ one-block forms for small problems
+// For n * R <= kSmallElems one workgroup of 1024 threads does a whole reduction step, so that an iteration
+// needs two launches besides the MVM and the preconditioner.  Threads: CB columns x (1024 / CB) rows per
+// column group; per column a fixed-order LDS tree over the rows' partial sums.
+constexpr int kSmallThreads = 1024;
+constexpr int64_t kSmallElems = 16384;
+
+// red: 1024 doubles; returns (at rl == 0) the sum over all threads of the column lane cl.  One column: a
+// butterfly within each wave, then the 16 wave sums in order; several: a fixed-order LDS tree per column.
+__device__ __forceinline__ double block_colsum(double* red, double s, int CB) {
+  const int t = threadIdx.x;
+  if (CB == 1) {
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSmallThreads / 64; ++w) v += red[w];
+    __syncthreads();
+    return v;
+  }
+  const int rl = t / CB;
+  red[t] = s;
+  __syncthreads();
+  for (int w = (kSmallThreads / CB) / 2; w > 0; w >>= 1) {
+    if (rl < w) red[t] += red[t + w * CB];
+    __syncthreads();
+  }
+  const double v = red[t];
+  __syncthreads();
+  return v;
+}
+
+// One iteration's update after its product q = A p: gamma = rho / p^T q (the kGamma epilogue, with the
+// breakdown flag), x += gamma p, r -= gamma q, rr = r^T r, and the status (the kStatus epilogue ee).
+__global__ __launch_bounds__(kSmallThreads) void k_step_small(double* __restrict__ x, double* __restrict__ r,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ q, int64_t n, int R,
+                                                              int CB, double* __restrict__ pq,
+                                                              double* __restrict__ rr, DotEpilogue eg,
+                                                              DotEpilogue es, Gate gate) {
+  if (gate.closed()) return;
+  __shared__ double red[kSmallThreads];
+  const int cl = threadIdx.x % CB;
+  const int rl = threadIdx.x / CB;
+  const int rows = kSmallThreads / CB;
+  for (int c0 = 0; c0 < R; c0 += CB) {
+    const int c = c0 + cl;
+    double s = 0.0;
+    if (c < R)
+      for (int64_t i = rl; i < n; i += rows) s = __builtin_fma(p[i * R + c], q[i * R + c], s);
+    const double v = block_colsum(red, s, CB);
+    if (rl == 0 && c < R) dot_epilogue(eg, gate, c, R, v, pq);
+  }
+  __syncthreads();   // every column's gamma and the breakdown flag are written
+  for (int c0 = 0; c0 < R; c0 += CB) {
+    const int c = c0 + cl;
+    double s = 0.0;
+    if (c < R) {
+      const double g = eg.gamma[c];
+      for (int64_t i = rl; i < n; i += rows) {
+        const int64_t t = i * R + c;
+        x[t] = __builtin_fma(g, p[t], x[t]);
+        const double u = __builtin_fma(-g, q[t], r[t]);
+        r[t] = u;
+        s = __builtin_fma(u, u, s);
+      }
+    }
+    const double v = block_colsum(red, s, CB);
+    if (rl == 0 && c < R) dot_epilogue(es, gate, c, R, v, rr);
+  }
+}
+
+// The next direction after z = M^{-1} r: rho_new = r^T z and beta = rho_new / rho (the kBeta epilogue eb),
+// then pout = z + beta pin for active columns, pin for the others (pout may be pin).
+__global__ __launch_bounds__(kSmallThreads) void k_dir_small(const double* __restrict__ r,
+                                                             const double* __restrict__ z, const double* pin,
+                                                             double* pout, const int* __restrict__ active,
+                                                             int64_t n, int R, int CB, double* __restrict__ rho_new,
+                                                             DotEpilogue eb, Gate gate) {
+  if (gate.closed()) return;
+  __shared__ double red[kSmallThreads];
+  const int cl = threadIdx.x % CB;
+  const int rl = threadIdx.x / CB;
+  const int rows = kSmallThreads / CB;
+  for (int c0 = 0; c0 < R; c0 += CB) {
+    const int c = c0 + cl;
+    double s = 0.0;
+    if (c < R)
+      for (int64_t i = rl; i < n; i += rows) s = __builtin_fma(r[i * R + c], z[i * R + c], s);
+    const double v = block_colsum(red, s, CB);
+    if (rl == 0 && c < R) dot_epilogue(eb, gate, c, R, v, rho_new);
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < R; c0 += CB) {
+    const int c = c0 + cl;
+    if (c >= R) continue;
+    const double b = eb.beta[c];
+    const bool act = active[c] != 0;
+    for (int64_t i = rl; i < n; i += rows) {
+      const int64_t t = i * R + c;
+      pout[t] = act ? __builtin_fma(b, pin[t], z[t]) : pin[t];
+    }
   }
 }
 
@@ -650,12 +760,47 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     tm.collect();
     decide(h.data());
   };
-  // the next direction after a decision: z = M^{-1} r, beta = r^T z / rho, p = z + beta p
-  auto enqueue_direction = [&](hipStream_t st, Gate gate) {
+  // Small problems run each reduction step as one workgroup (k_step_small, k_dir_small), larger ones as the
+  // two-stage column reductions; both drivers take the same choice.
+  const bool small = (int64_t)n * R <= kSmallElems;
+  int CBs = 1;
+  while (CBs * 2 <= R && CBs < 64) CBs *= 2;
+  // one iteration's update after its product q = A p: gamma, x += gamma p, r -= gamma q, and its status
+  auto step = [&](hipStream_t st, const DotEpilogue& es, Gate gate) {
+    if (small) {
+      hipLaunchKernelGGL(k_step_small, dim3(1), dim3(kSmallThreads), 0, st, x, r.p, (const double*)pp,
+                         (const double*)qq, n, R, CBs, pq, rr, epi_gamma(rho), es, gate);
+      KRR_LAUNCH_CHECK();
+    } else {
+      red.dot(pp, qq, n, pq, st, epi_gamma(rho), gate);
+      red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, st, es, gate);
+    }
+  };
+  // z = M^{-1} r, rho_new = r^T z, beta = rho_new / rho, pout = z + beta pin (pin for inactive columns)
+  auto direction = [&](hipStream_t st, double* pin, double* pout, Gate gate) {
     precondition(r.p, z.p, st);
-    red.dot(r.p, z.p, n, rho_new, st, epi_beta(rho), gate);
-    hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, st, pp, z.p, beta, active.p, n, R, gate);
+    if (small) {
+      hipLaunchKernelGGL(k_dir_small, dim3(1), dim3(kSmallThreads), 0, st, (const double*)r.p, (const double*)z.p,
+                         (const double*)pin, pout, (const int*)active.p, n, R, CBs, rho_new, epi_beta(rho), gate);
+    } else {
+      red.dot(r.p, z.p, n, rho_new, st, epi_beta(rho), gate);
+      if (pout == pin)
+        hipLaunchKernelGGL(k_update_p, dim3(nb(nR)), dim3(256), 0, st, pin, z.p, beta, active.p, n, R, gate);
+      else
+        hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, st, pout, (const double*)pin,
+                           (const double*)z.p, (const double*)beta, (const int*)active.p, n, R);
+    }
     KRR_LAUNCH_CHECK();
+  };
+  // the step (do_step, with its status es) and then the next direction pout = z + beta pin (do_dir)
+  auto step_dir = [&](hipStream_t st, bool do_step, const DotEpilogue& es, Gate gstep, bool do_dir, double* pin,
+                      double* pout, Gate gdir) {
+    if (do_step) step(st, es, gstep);
+    if (do_dir) direction(st, pin, pout, gdir);
+  };
+  // the next direction after a decision, in place
+  auto enqueue_direction = [&](hipStream_t st, Gate gate) {
+    step_dir(st, false, DotEpilogue(), Gate(), true, pp, pp, gate);
     std::swap(rho, rho_new);
   };
   hipEvent_t ev_status;
@@ -701,10 +846,9 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       enqueue_direction(cs, Gate());
       for (int u = 0; u < B; ++u) {
         Aw.apply(pp, betas, qq, cs);
-        red.dot(pp, qq, n, pq, cs, epi_gamma(rho), Gate{halt_d, u + 1});
-        red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, cs, epi_status(hs + u * SS, it_base_d, u + 1, halt_d),
-                     Gate{halt_d, u + 1});
-        if (u + 1 < B) enqueue_direction(cs, Gate{halt_d, u + 2});
+        step_dir(cs, true, epi_status(hs + u * SS, it_base_d, u + 1, halt_d), Gate{halt_d, u + 1}, u + 1 < B, pp,
+                 pp, Gate{halt_d, u + 2});
+        if (u + 1 < B) std::swap(rho, rho_new);
       }
       if (cycle_check) {
         Atrue->apply(x, betas, qq, cs);
@@ -807,19 +951,14 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     }
     have_next = false;
     res.st.n_mvm++;
-    red.dot(pp, qq, n, pq, s, epi_gamma(rho));
-    red.axpy2_rr(x, r.p, pp, qq, gamma, n, rr, s, epi_status(hs, nullptr, it, nullptr));
-    KRR_CHECK_HIP(hipEventRecord(ev_status, s));
-    const size_t tmark = tm.marks();
     const bool scheduled = replace_every > 0 && it % replace_every == 0;
     const bool handover = graph_on && it % B == 0;   // a cycle may start after this iteration
     const bool ahead = !scheduled && !handover && it < maxit;
+    step(s, epi_status(hs, nullptr, it, nullptr), Gate());
+    KRR_CHECK_HIP(hipEventRecord(ev_status, s));
+    const size_t tmark = tm.marks();
     if (ahead) {
-      precondition(r.p, z.p, s);
-      red.dot(r.p, z.p, n, rho_new, s, epi_beta(rho));
-      hipLaunchKernelGGL(k_update_p_to, dim3(nb(nR)), dim3(256), 0, s, pa, (const double*)pp, (const double*)z.p,
-                         (const double*)beta, (const int*)active.p, n, R);
-      KRR_LAUNCH_CHECK();
+      direction(s, pp, pa, Gate());
       tm.start(&res.st.t_mvm_ms);
       Aw.apply(pa, betas, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
       tm.stop();

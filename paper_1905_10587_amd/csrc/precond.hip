@@ -67,16 +67,22 @@ __global__ void k_add_diag(const double* __restrict__ M, int k, double beta, dou
 static unsigned nblk(int64_t n, int b = 256) { return (unsigned)ceil_div(n, b); }
 
 // ------------------------------------------------------------------ Woodbury apply kernels (one column)
-constexpr int kWRows = 256;   // rows per block in the W^T x pass
+constexpr int kWRows = 256;   // rows per block in the W^T x pass (at most)
+
+// Rows per block of the W^T x pass: kWRows, fewer for small n so that the pass still has a few hundred blocks
+// (a multiple of 4, at least 16).
+static int wt_rows(int64_t n) {
+  return (int)std::min<int64_t>(kWRows, std::max<int64_t>(16, round_up(ceil_div(n, 256), 4)));
+}
 
 // partial[b, c] = sum_{i in row block b} W[i, c] x[i]  (products and sums in FP64; W read once).
 // Grid: row blocks x column chunks of 256, so that the pass has several blocks per CU at n ~ 1e5.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_wt_partial(const TW* __restrict__ W, int64_t n, int kept,
-                                                    const double* __restrict__ x, int ldx,
+                                                    const double* __restrict__ x, int ldx, int rows,
                                                     double* __restrict__ partial) {
-  const int64_t i0 = (int64_t)blockIdx.x * kWRows;
-  const int64_t i1 = i0 + kWRows < n ? i0 + kWRows : n;
+  const int64_t i0 = (int64_t)blockIdx.x * rows;
+  const int64_t i1 = i0 + rows < n ? i0 + rows : n;
   const int c = blockIdx.y * 256 + threadIdx.x;
   if (c >= kept) return;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -169,19 +175,21 @@ int beta_index(const krr_precond& P, double beta) {
 }
 
 // One column of Algorithm 4 with caller-provided buffers: x and out are columns of n x R row-major blocks
-// (strides ldx, ldo); partial holds ceil(n / 256) x kept doubles, t and z kept doubles each.  Every slot of
+// (strides ldx, ldo); partial holds ceil(n / wt_rows(n)) x kept doubles (at most max(256, ceil(n / 256)) x kept),
+// t and z kept doubles each.  Every slot of
 // partial is written before it is read, so the buffers need no clearing.
 static void woodbury_one_column(const krr_precond& P, const double* x, int ldx, int b, bool use32, double* out,
                                 int ldo, double* partial, double* t, double* z, hipStream_t s) {
   const int kept = P.kept;
   const int64_t n = P.n;
   const double* G = use32 ? P.G32[b].p : P.G64[b].p;
-  const int nb = (int)ceil_div(n, kWRows);
+  const int rows = wt_rows(n);
+  const int nb = (int)ceil_div(n, rows);
   const dim3 gw((unsigned)nb, nblk(kept));
   if (use32)
-    hipLaunchKernelGGL(k_wt_partial<float>, gw, dim3(256), 0, s, P.W32.p, n, kept, x, ldx, partial);
+    hipLaunchKernelGGL(k_wt_partial<float>, gw, dim3(256), 0, s, P.W32.p, n, kept, x, ldx, rows, partial);
   else
-    hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, ldx, partial);
+    hipLaunchKernelGGL(k_wt_partial<double>, gw, dim3(256), 0, s, P.W64.p, n, kept, x, ldx, rows, partial);
   hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)kept), dim3(256), 0, s, partial, nb, kept, t);
   hipLaunchKernelGGL(k_sym_gemv, dim3(nblk(kept, 4)), dim3(256), 0, s, G, kept, t, z);
   // two rows per wave and at most 2048 blocks (measured best among 1, 2, 4 rows and 1024-8192 blocks)
@@ -198,7 +206,7 @@ static void woodbury_one_column(const krr_precond& P, const double* x, int ldx, 
 
 // Doubles of scratch one column of woodbury_one_column needs.
 static int64_t woodbury_column_scratch(const krr_precond& P) {
-  return ceil_div(P.n, kWRows) * (int64_t)P.kept + 2 * (int64_t)P.kept;
+  return ceil_div(P.n, wt_rows(P.n)) * (int64_t)P.kept + 2 * (int64_t)P.kept;
 }
 
 void WoodburyWork::prepare(const krr_precond& P, int R_, const int* bidx_host_, hipStream_t s) {
@@ -206,7 +214,7 @@ void WoodburyWork::prepare(const krr_precond& P, int R_, const int* bidx_host_, 
   bidx_host.assign(bidx_host_, bidx_host_ + R);
   const int kept = P.kept;
   if (R == 1) {
-    partial.alloc((size_t)ceil_div(P.n, kWRows) * kept, s);
+    partial.alloc((size_t)ceil_div(P.n, wt_rows(P.n)) * kept, s);
     t.alloc(kept, s);
     z.alloc(kept, s);
     return;
@@ -676,11 +684,11 @@ extern "C" int krr_precond_apply_noalloc(const krr_precond* P, const double* x, 
     const int64_t need = krr::woodbury_column_scratch(*P);
     KRR_REQUIRE((size_t)need * sizeof(double) <= krr::noalloc_scratch_bytes(),
                 "krr_precond_apply_noalloc: this preconditioner needs " + std::to_string(need * 8) +
-                    " bytes of scratch (ceil(n/256) * kept + 2 * kept doubles); the library's scratch holds " +
+                    " bytes of scratch (ceil(n / rows) * kept + 2 * kept doubles, rows = min(256, max(16, ~n / 256))); the library's scratch holds " +
                     std::to_string(krr::noalloc_scratch_bytes()) + " bytes");
     double* base = static_cast<double*>(krr::noalloc_scratch());
     double* partial = base;
-    double* t = partial + krr::ceil_div(P->n, krr::kWRows) * P->kept;
+    double* t = partial + krr::ceil_div(P->n, krr::wt_rows(P->n)) * P->kept;
     double* z = t + P->kept;
     hipStream_t s = (hipStream_t)stream;
     for (int r = 0; r < R; ++r) krr::woodbury_one_column(*P, x + r, R, bidx[r], use32, out + r, R, partial, t, z, s);
