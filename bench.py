@@ -51,13 +51,18 @@ def peak_mixed(d, sym):
     return (2.0 if sym else 1.0) * 256 * SIMD_CYCLES / ((64 if sym else 48) + 16 * nch)
 
 
-def peak_direct(d, prec, sym):
+def peak_direct(d, prec, sym, variant=None):
     """VALU bound of the FP32 / FP64 forms (one lane-slot per VALU instruction, exp2 in FP32 counted as two):
     FP32 per pair d subtractions + d FMAs + exp + one FMA; FP64 per pair d subtractions + d FMAs + a
-    16-instruction exp2 (reduction, degree-11 polynomial, scaling) + one FMA, + one more FMA in the symmetric
-    form, whose evaluated pair serves two pairs of the product."""
+    16-instruction exp2 (scaling by -log2(e)/eps, reduction, degree-10 polynomial, 2^n) + one FMA, + one more
+    FMA in the symmetric form, whose evaluated pair serves two pairs of the product.  The FP64 symmetric forms
+    with the cross term on the matrix cores (variants 5, 6) issue 19 VALU instructions per evaluated pair
+    whatever d (q from the two norms and the cross term: 2; exp2 without the scaling: 15; row and column FMAs:
+    2); their D/4 MFMAs per 256 pairs run on the matrix cores."""
     if prec == "fp32":
         return SLOTS / (2 * d + 3)
+    if sym and variant is not None and variant >= 5:
+        return 2.0 * SLOTS / 19
     return (2.0 * SLOTS / (2 * d + 18)) if sym else SLOTS / (2 * d + 17)
 # Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
 # for roofline.traffic only while these hash to the value recorded with it.
@@ -276,8 +281,10 @@ def mvm_roofline(prec, d, R, n, avg_ms, launches, variant, sym, traffic):
         form = "symmetric form (exp + 2 FMA per evaluated pair, two pairs each)" if sym else \
             "direct form (exp + FMA per pair)"
     else:
-        peak = ser = peak_direct(d, prec, sym)
+        peak = ser = peak_direct(d, prec, sym, variant)
         form = f"{'symmetric' if sym else 'direct'} form, {prec} VALU ops per pair"
+        if prec == "fp64" and sym and variant is not None and variant >= 5:
+            form = "symmetric form, cross term on the FP64 matrix cores, 19 VALU ops per evaluated pair"
     rec = {"bound": "alu", "kernel": f"{prec} MVM, variant {variant}, {form}, d={d}",
            "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2), "unit": "Tpairs/s",
            "frac": round(achieved / peak, 3), "traffic": traffic,
@@ -595,6 +602,31 @@ def solve_bench(a, wl, Xg, Yg, sk, betas_col, prec, replace_every, krr, torch):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     P, alpha, its, rel, st, status, t_build, t_step = results[-1]
+    pcg_drivers = None
+    if not adjoint and float(wl.n) * wl.n * len(betas_col) <= 2.0 ** 34:
+        # after the timed region: the same solve under each PCG driver (phase timers off), the second of two
+        # calls timed (the first captures the graphs), and whether the two return the same bits
+        pcg_drivers = {}
+        ref = None
+        try:
+            for mode, name in ((0, "host_loop"), (1, "graph_cycles")):
+                krr.set_pcg_mode(mode)
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    al, its2, _, st2, _ = krr.pcg_solve(Xg, Yg, wl.eps, betas_col, P, tol=wl.tol, maxit=a.maxit,
+                                                        replace_every=replace_every, prec=prec)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                pcg_drivers[name] = {"solve_ms": round(1e3 * dt, 2), "iterations": max(its2),
+                                     "us_per_iteration": round(1e6 * dt / max(max(its2), 1), 1),
+                                     "graph_cycles": st2["n_graph_cycles"]}
+                if ref is None:
+                    ref = al.clone()
+                else:
+                    pcg_drivers["bit_identical"] = bool(torch.equal(ref, al))
+        finally:
+            krr.set_pcg_mode(-1)
     if a.save_alpha:
         import numpy as np
         np.save(a.save_alpha, alpha.cpu().numpy())
@@ -670,6 +702,8 @@ def solve_bench(a, wl, Xg, Yg, sk, betas_col, prec, replace_every, krr, torch):
             e["relres_max"] = max(e["relres_max"], float(rel[c]))
         out["columns_by_beta"] = by_beta
         out["ms_per_iteration"] = round(1e3 * (t_step - t_build) / max(max(its), 1), 1)
+    if pcg_drivers is not None:
+        out["pcg_drivers"] = pcg_drivers
     if adjoint:
         sts = grad_out.pop("stats")
         out["gradient"] = {**{k: v for k, v in grad_out.items()},

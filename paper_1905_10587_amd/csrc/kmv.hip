@@ -364,11 +364,12 @@ int kmv_num_variants(int prec, int R) {
   if (rclass(prec, R) == 3) return 14;
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
   // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
-  // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2)
+  // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2),
+  // 5..6 symmetric with the cross term on the FP64 matrix cores (4, 2 target fragments per wave; else variant 2)
   // FP64 several columns: 0..2 direct (TM 1, 2, 4; R >= 16: TM 1 with 16 / 32-column chunks), 3 the FP64
   // matrix-core form (d <= 16, K only; else variant 1)
   if (prec == KRR_MIXED) return 12;
-  if (prec == KRR_FP64) return rclass(prec, R) == 1 ? 5 : 4;
+  if (prec == KRR_FP64) return rclass(prec, R) == 1 ? 7 : 4;
   return 3;
 }
 
@@ -400,7 +401,10 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
     if (nch <= 4) return 8;
     return mixed_max_nf(nch) >= 2 ? 1 : 0;
   }
-  if (kmv_is_symmetric(prec, d, R, 0, square, 4)) return 4;   // FP64 symmetric square product, TM 4
+  // FP64 symmetric square product with the cross term on the matrix cores: 4 target fragments per wave up to
+  // d = 4, 2 above (n = 1e6, d = 4: 332 ms against 397 ms for the direct symmetric form; d = 6: 98 ms against
+  // 116 ms; d = 16, n = 2e5: 21 ms against 32 ms)
+  if (kmv_is_symmetric(prec, d, R, 0, square, 5)) return padded_dim(d) <= 4 ? 5 : 6;
   if (padded_dim(d) >= 32) return 0;
   // FP64, more than 8 columns: the matrix-core kernel evaluates each pair once for up to 128 columns
   // (n = 2e5, d = 6: 2.05x faster than the 32-column chunks at R = 128, 1.14x at R = 16)
@@ -585,6 +589,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   int gz, TM = 1, NF = 1, RC = R == 1 ? 1 : R <= 4 ? 4 : 8;
   int form = 0;   // mixed single-column kernel form
   bool sym = false;   // symmetric square product (mixed, one column)
+  bool f64sm = false; // FP64 symmetric form with the cross term on the matrix cores
   const int D = T.dpad;
   // FP64 many-column product on the FP64 matrix cores (variant 3 of FP64 with R > 1)
   const bool f64m = kmv_f64_uses_mfma(prec, T.d, R, deriv, variant) && Rp % 16 == 0;
@@ -637,16 +642,18 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     int var = variant;
     if (prec == KRR_FP64 && var >= 3) {
       sym = kmv_is_symmetric(prec, T.d, R, deriv, &T == &S, var);
-      if (!sym) var -= 2;
+      f64sm = sym && var >= 5;
+      if (f64sm) NF = var == 5 ? 4 : 2;   // target fragments per wave of the matrix-core form
+      if (!sym) var = var >= 5 ? 2 : var - 2;
     }
-    TM = sym ? (var == 3 ? 2 : 4) : D >= 32 ? 1 : kTM[var];
+    TM = f64sm ? 1 : sym ? (var == 3 ? 2 : 4) : D >= 32 ? 1 : kTM[var];
     // many right-hand sides in FP64: wide column chunks (the exp of a pair is shared by RC columns)
     // (a chunk must not run past the padded column count Rp: RC divides Rp)
     if (prec == KRR_FP64 && !sym && DV == 0 && D <= 16 && R >= 16 && Rp % 16 == 0) {
       RC = R >= 32 && Rp % 32 == 0 ? 32 : 16;
       TM = 1;
     }
-    rows = 256 * TM;
+    rows = f64sm ? 64 * NF : 256 * TM;
     gz = (int)ceil_div(R, RC);   // real columns only (Rp is padded to 8)
     KRR_REQUIRE(Rp % RC == 0, "internal: column chunk does not divide the padded column count");
   }
@@ -668,6 +675,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     if (block)
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
+    if (f64sm) return launch_kmv_f64_symm(D, NF, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64 && sym) return launch_kmv_f64_sym(D, TM, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (f64m) return launch_kmv_f64_mfma(D, NRG, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);

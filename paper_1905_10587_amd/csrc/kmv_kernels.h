@@ -301,6 +301,144 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
   else run(std::true_type{});
 }
 
+// Symmetric FP64 form with the cross term on the FP64 matrix cores (v_mfma_f64_16x16x4f64: exact products,
+// FP64 sums): q = c'|x_i|^2 + c'|x_j|^2 - 2c' x_i.x_j with c' = neg_c, so a pair costs two VALU operations
+// for q, the FP64 exp2 and the row and column FMAs, whatever D (the direct form adds D subtractions and D
+// FMAs).  The cancellation in |x_i|^2 + |x_j|^2 - 2 x_i.x_j leaves an error of up to about (4D + 4) u
+// max|x|^2 in D^2 (centred coordinates), a relative error of ln2 |c'| (4D + 4) u max|x|^2 in a kernel value.
+// Same super-tiles, triangle order and partial slots as k_kmv_f64_sym.  Block: 4 waves x NFR fragments of 16
+// targets (64 NFR targets); source tiles of 256 points in LDS with their c'|x_j|^2, 16 sources per MFMA step.
+// Lane l holds the pairs (target 4e + l/16 of a fragment, source l%16 of the step), e = 0..3: its row sums
+// are added over the 16 lanes of its group at the end, its column sums over the four groups every step.
+template <int D, int NFR>
+__global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__ X, const double* __restrict__ v,
+                                                      int Rp, double neg_c, int E, int NS, int64_t npad,
+                                                      double* __restrict__ part, int Rout) {
+  static_assert(D % 2 == 0 && D <= 16, "even dimensions up to 16");
+  constexpr int KC = (D + 3) / 4;          // K chunks of the cross term
+  constexpr int SD = 4 * KC + 1;           // LDS row stride of the source coordinates (doubles)
+  constexpr int TS = 256;
+  constexpr int TT = 4 * NFR * 16;         // targets per target tile
+  __shared__ double xs[TS * SD];
+  __shared__ double vs[TS];
+  __shared__ double ns[TS];
+  __shared__ double cacc[4][TS];
+
+  const int64_t nitems = (int64_t)NS * (NS + 1) / 2;
+  const int64_t per = (nitems + 7) / 8;
+  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= nitems) return;
+  int c = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) / 2);
+  if (c < 0) c = 0;
+  if (c > NS - 1) c = NS - 1;
+  auto col_start = [&](int64_t cc) { return cc * (cc + 1) / 2; };
+  while (c > 0 && col_start(c) > item) --c;
+  while (c + 1 < NS && col_start(c + 1) <= item) ++c;
+  const int r = (int)(item - col_start(c));
+  const bool diag = r == c;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t t0 = (int64_t)r * E, t1 = t0 + E < npad ? t0 + E : npad;
+  const int64_t s0 = (int64_t)c * E, s1 = s0 + E < npad ? s0 + E : npad;
+  const int ntile = (int)((s1 - s0) / TS);
+  const int ntt = (int)((t1 - t0) / TT);
+  const double m2c = -2.0 * neg_c;
+
+  auto run = [&](auto colflag) {
+    constexpr bool COL = decltype(colflag)::value;
+    for (int tt = 0; tt < ntt; ++tt) {
+      const int64_t rowf = t0 + (int64_t)tt * TT + (int64_t)wave * (16 * NFR);
+      double a[NFR][KC], an[NFR][4], vt[NFR][4], acc[NFR][4];
+#pragma unroll
+      for (int f = 0; f < NFR; ++f) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          const int k = 4 * kc + kq;
+          a[f][kc] = k < D ? X[(rowf + 16 * f + r16) * D + k] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = rowf + 16 * f + 4 * e + kq;
+          double nn = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) nn = __builtin_fma(X[row * D + k], X[row * D + k], nn);
+          an[f][e] = neg_c * nn;
+          vt[f][e] = COL ? v[row * Rp] : 0.0;
+          acc[f][e] = 0.0;
+        }
+      }
+      for (int t = 0; t < ntile; ++t) {
+        const int64_t jt = s0 + (int64_t)t * TS;
+        double* dst = part + (int64_t)r * npad + jt + tid;   // one column: dense partials
+        double prev = 0.0;
+        if (COL && tt > 0) prev = *dst;
+        __syncthreads();
+        {
+          double nn = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const double xv = X[(jt + tid) * D + k];
+            xs[tid * SD + k] = xv;
+            nn = __builtin_fma(xv, xv, nn);
+          }
+#pragma unroll
+          for (int k = D; k < 4 * KC; ++k) xs[tid * SD + k] = 0.0;
+          ns[tid] = neg_c * nn;
+          vs[tid] = v[(jt + tid) * Rp];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int st = 0; st < TS / 16; ++st) {
+          const int j = st * 16 + r16;
+          double b[KC];
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc) b[kc] = xs[j * SD + 4 * kc + kq];
+          const double bn = ns[j];
+          const double vj = vs[j];
+          f64x4 C[NFR];
+#pragma unroll
+          for (int f = 0; f < NFR; ++f) {
+            C[f] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) C[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][kc], b[kc], C[f], 0, 0, 0);
+          }
+          double cs = 0.0;
+#pragma unroll
+          for (int f = 0; f < NFR; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const double kv = exp2_neg_f64(__builtin_fma(m2c, C[f][e], an[f][e] + bn));
+              acc[f][e] = __builtin_fma(kv, vj, acc[f][e]);
+              if (COL) cs = __builtin_fma(kv, vt[f][e], cs);
+            }
+          if (COL) {
+            cs += __shfl_xor(cs, 16);
+            cs += __shfl_xor(cs, 32);
+            if (kq == 0) cacc[wave][j] = cs;
+          }
+        }
+        __syncthreads();
+        if (COL) *dst = prev + (((cacc[0][tid] + cacc[1][tid]) + cacc[2][tid]) + cacc[3][tid]);
+      }
+#pragma unroll
+      for (int f = 0; f < NFR; ++f)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double s = acc[f][e];
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
+          if (r16 == 0) part[(int64_t)c * npad + rowf + 16 * f + 4 * e + kq] = s;
+        }
+    }
+  };
+  if (diag) run(std::false_type{});
+  else run(std::true_type{});
+}
+
 // FP32 form: coordinates pre-scaled so that q = -||t'-s'||^2 is the exp2 argument.  Per pair: D subs,
 // D FMAs, one v_exp_f32, RC FMAs.  FP32 partial sums are folded into FP64 once per 256 sources.
 template <int D, int TM, int RC, int DV>

@@ -1,10 +1,11 @@
 """Tune the kernel MVM's launch table for the benchmark workloads on this GPU and write it as JSON.
 
-Usage: python -m paper_1905_10587_amd.tune [--out PATH] [--only NAME ...]
+Usage: python -m paper_1905_10587_amd.tune [--out PATH] [--only NAME ...] [--update]
 
 Each entry times every kernel variant, then the two fastest with their source split (or super-tile edge)
 halved and doubled, on a square product of the workload's size class (krr_autotune).  The bench loads
-the table from tuned/<arch>.json beside this file when it exists.
+the table from tuned/<arch>.json beside this file when it exists.  --update starts from that table, so that
+re-tuning some shapes keeps the entries of the others.
 """
 from __future__ import annotations
 
@@ -35,12 +36,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--out", default=None)
     ap.add_argument("--only", nargs="*", default=None)
+    ap.add_argument("--update", action="store_true", help="start from the committed table of this GPU")
     a = ap.parse_args(argv)
     import torch
     import paper_1905_10587_amd as krr
     krr.load()
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     out = a.out or table_path(arch)
+    if a.update and os.path.exists(table_path(arch)):
+        krr.autotune_load(table_path(arch))
     for name, prec, d, R, n in SHAPES:
         if a.only and name not in a.only:
             continue

@@ -4,7 +4,9 @@ Sizes span several 1024-row tiles with ragged tails, single points, cross-set pr
 several right-hand sides, the derivative kernel and the ridge shift.  Errors are measured
 per entry relative to sum_j K_ij |V_jc| (the scale of the sum, which avoids dividing by
 cancelled sums).  Bars:
-  FP64  <= 1e-14   (direct differences, FP64 exp from its series; measured <= 3e-16)
+  FP64  <= 1e-14   (direct differences, FP64 exp from its series; measured <= 3e-16); the symmetric form
+                   with the cross term on the FP64 matrix cores: the cancellation bar of
+                   _f64_cross_term_bar (at least 1e-14)
   FP32  <= 1e-6    (FP32 differences/exp/partial sums; measured <= 1.4e-7)
   MIXED <= 1e-6    (split-BF16 MFMA cross term with FP32 accumulation; measured <= 1e-7)
 """
@@ -242,7 +244,17 @@ SYM_CASES = [
 ]
 
 
-SYM_VARIANTS = {"mixed": (10, 11), "fp64": (3, 4)}
+SYM_VARIANTS = {"mixed": (10, 11), "fp64": (3, 4, 5, 6)}
+
+
+def _f64_cross_term_bar(X, eps):
+    """Bar of the FP64 symmetric forms whose cross term runs on the matrix cores (variants 5, 6): the exponent
+    q = c'(|x_i|^2 + |x_j|^2 - 2 x_i.x_j), c' = log2(e) / eps, on centred coordinates carries a rounding error
+    of at most about (4d + 4) u max|x - mean|^2 |c'|, i.e. a relative error ln2 times that in each kernel
+    value; twice that bound, and never below the direct form's bar."""
+    d = X.shape[1]
+    M = float(np.max(np.sum((X - X.mean(axis=0)) ** 2, axis=1)))
+    return max(TOL["fp64"], 2.0 * np.log(2.0) * (np.log2(np.e) / eps) * (4 * d + 4) * 2.0 ** -53 * M)
 
 
 @pytest.mark.gpu
@@ -268,10 +280,43 @@ def test_symmetric_square_product(gpu_lib, case, prec):
                                prec=prec).cpu().numpy()
         err_s = _scaled_err(Us, ref + beta * v, scale + beta * np.abs(v))
         form = gpu_lib.kmv_variant(d, 1, prec, square=True)
+        bar = _f64_cross_term_bar(X, eps) if prec == "fp64" and variant >= 5 else TOL[prec]
         print(f"symmetric {prec} n={n} d={d} variant={variant} {form}: max scaled error {err:.2e} "
-              f"(with shift {err_s:.2e})", flush=True)
-        assert err <= TOL[prec] and err_s <= TOL[prec]
+              f"(with shift {err_s:.2e}; bar {bar:.1e})", flush=True)
+        assert err <= bar and err_s <= bar
     gpu_lib.set_variant(d, 1, prec, -1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", [(3000, 4, 0.01, "uniform"), (2600, 16, 4.0, "normal")],
+                         ids=["d4_eps0.01_uniform", "d16_eps4_normal"])
+def test_fp64_cross_term_form_at_workload_arithmetic(gpu_lib, case):
+    """Variants 5 and 6 at the mixed workload's arithmetic (uniform points in the unit 4-cube, eps = 0.01: the
+    largest |c'| max|x|^2 of the workloads) and the adjoint workload's (d = 16, x ~ N(0, I/4), eps = 4), with
+    and without the shift, against the oracle within the cancellation bar; the direct symmetric form (variant
+    4) on the same data stays within the FP64 bar."""
+    n, d, eps, kind = case
+    rng = np.random.default_rng(n + d)
+    X = rng.random((n, d)) if kind == "uniform" else 0.5 * rng.standard_normal((n, d))
+    v = rng.standard_normal(n)
+    K = ok.kernel_matrix(X, X, eps)
+    ref, scale = K @ v, K @ np.abs(v)
+    bar = _f64_cross_term_bar(X, eps)
+    errs = {}
+    try:
+        for variant in (4, 5, 6):
+            gpu_lib.set_variant(d, 1, "fp64", variant)
+            U = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), prec="fp64").cpu().numpy()
+            Us = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), shift=1e-3,
+                                   prec="fp64").cpu().numpy()
+            errs[variant] = (_scaled_err(U, ref, scale),
+                             _scaled_err(Us, ref + 1e-3 * v, scale + 1e-3 * np.abs(v)))
+    finally:
+        gpu_lib.set_variant(d, 1, "fp64", -1)
+    print(f"fp64 d={d} eps={eps}: direct symmetric {errs[4][0]:.2e}, cross term on matrix cores {errs[5][0]:.2e} / "
+          f"{errs[6][0]:.2e} (bar {bar:.1e})", flush=True)
+    assert max(errs[4]) <= TOL["fp64"]
+    assert max(errs[5]) <= bar and max(errs[6]) <= bar
 
 
 @pytest.mark.gpu
