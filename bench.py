@@ -56,13 +56,13 @@ def peak_direct(d, prec, sym, variant=None):
     FP32 per pair d subtractions + d FMAs + exp + one FMA; FP64 per pair d subtractions + d FMAs + a
     16-instruction exp2 (scaling by -log2(e)/eps, reduction, degree-10 polynomial, 2^n) + one FMA, + one more
     FMA in the symmetric form, whose evaluated pair serves two pairs of the product.  The FP64 symmetric forms
-    with the cross term on the matrix cores (variants 5, 6) issue 19 VALU instructions per evaluated pair
-    whatever d (q from the two norms and the cross term: 2; exp2 without the scaling: 15; row and column FMAs:
-    2); their D/4 MFMAs per 256 pairs run on the matrix cores."""
+    with the exponent's cross term on the matrix cores (variants 5, 6) issue 19 VALU instructions per evaluated
+    pair whatever d (q from the two norms and the cross term: 2; exp2 without the scaling: 15; row and column
+    FMAs: 2), 17 where the norms are contracted with it (d = 2, 6); their MFMAs run on the matrix cores."""
     if prec == "fp32":
         return SLOTS / (2 * d + 3)
     if sym and variant is not None and variant >= 5:
-        return 2.0 * SLOTS / 19
+        return 2.0 * SLOTS / (17 if d % 4 == 2 else 19)
     return (2.0 * SLOTS / (2 * d + 18)) if sym else SLOTS / (2 * d + 17)
 # Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
 # for roofline.traffic only while these hash to the value recorded with it.
@@ -284,7 +284,8 @@ def mvm_roofline(prec, d, R, n, avg_ms, launches, variant, sym, traffic):
         peak = ser = peak_direct(d, prec, sym, variant)
         form = f"{'symmetric' if sym else 'direct'} form, {prec} VALU ops per pair"
         if prec == "fp64" and sym and variant is not None and variant >= 5:
-            form = "symmetric form, cross term on the FP64 matrix cores, 19 VALU ops per evaluated pair"
+            form = (f"symmetric form, exponent's cross term on the FP64 matrix cores, {17 if d % 4 == 2 else 19} "
+                    f"VALU ops per evaluated pair")
     rec = {"bound": "alu", "kernel": f"{prec} MVM, variant {variant}, {form}, d={d}",
            "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2), "unit": "Tpairs/s",
            "frac": round(achieved / peak, 3), "traffic": traffic,

@@ -401,10 +401,10 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
     if (nch <= 4) return 8;
     return mixed_max_nf(nch) >= 2 ? 1 : 0;
   }
-  // FP64 symmetric square product with the cross term on the matrix cores: 4 target fragments per wave up to
-  // d = 4, 2 above (n = 1e6, d = 4: 332 ms against 397 ms for the direct symmetric form; d = 6: 98 ms against
-  // 116 ms; d = 16, n = 2e5: 21 ms against 32 ms)
-  if (kmv_is_symmetric(prec, d, R, 0, square, 5)) return padded_dim(d) <= 4 ? 5 : 6;
+  // FP64 symmetric square product with the exponent's cross term on the matrix cores, 4 target fragments per
+  // wave (n = 1e6, d = 4: 331 ms against 392 ms for the direct symmetric form; n = 5e5, d = 6: 90.5 ms against
+  // 116 ms; n = 2e5, d = 16: 21 ms against 32 ms; 2 fragments per wave within 4% of it)
+  if (kmv_is_symmetric(prec, d, R, 0, square, 5)) return 5;
   if (padded_dim(d) >= 32) return 0;
   // FP64, more than 8 columns: the matrix-core kernel evaluates each pair once for up to 128 columns
   // (n = 2e5, d = 6: 2.05x faster than the 32-column chunks at R = 128, 1.14x at R = 16)

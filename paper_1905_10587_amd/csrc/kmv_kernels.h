@@ -301,13 +301,17 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
   else run(std::true_type{});
 }
 
-// Symmetric FP64 form with the cross term on the FP64 matrix cores (v_mfma_f64_16x16x4f64: exact products,
-// FP64 sums): q = c'|x_i|^2 + c'|x_j|^2 - 2c' x_i.x_j with c' = neg_c, so a pair costs two VALU operations
-// for q, the FP64 exp2 and the row and column FMAs, whatever D (the direct form adds D subtractions and D
-// FMAs).  The cancellation in |x_i|^2 + |x_j|^2 - 2 x_i.x_j leaves an error of up to about (4D + 4) u
-// max|x|^2 in D^2 (centred coordinates), a relative error of ln2 |c'| (4D + 4) u max|x|^2 in a kernel value.
+// Symmetric FP64 form with the exponent's cross term on the FP64 matrix cores (v_mfma_f64_16x16x4f64, FP64
+// products and sums): q = c'|x_i|^2 + c'|x_j|^2 - 2c' x_i.x_j (c' = neg_c).  When D + 2 fits the K padding
+// (D = 2, 6: FOLD) the whole of q is the contraction of a_i = [x_i, c'|x_i|^2, 1] with b_j = [-2c' x_j, 1,
+// c'|x_j|^2], and a pair costs the FP64 exp2 and the row and column FMAs on the VALU; otherwise the MFMA gives
+// x_i.x_j and q = fma(-2c', x_i.x_j, c'|x_i|^2 + c'|x_j|^2) adds two VALU operations (an extra K chunk costs
+// more than these, the MFMA work not being hidden behind the VALU work).  Either way the direct form's D
+// subtractions, D FMAs and scaling are gone.  The cancellation leaves an error of up to about (4D + 8) u |c'|
+// max|x|^2 in q (centred coordinates), a relative error ln2 times that in a kernel value.
 // Same super-tiles, triangle order and partial slots as k_kmv_f64_sym.  Block: 4 waves x NFR fragments of 16
-// targets (64 NFR targets); source tiles of 256 points in LDS with their c'|x_j|^2, 16 sources per MFMA step.
+// targets (64 NFR targets); source tiles of 256 points in LDS (b_j, or x_j and c'|x_j|^2), 16 sources per
+// MFMA step.
 // Lane l holds the pairs (target 4e + l/16 of a fragment, source l%16 of the step), e = 0..3: its row sums
 // are added over the 16 lanes of its group at the end, its column sums over the four groups every step.
 template <int D, int NFR>
@@ -315,14 +319,16 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
                                                       int Rp, double neg_c, int E, int NS, int64_t npad,
                                                       double* __restrict__ part, int Rout) {
   static_assert(D % 2 == 0 && D <= 16, "even dimensions up to 16");
-  constexpr int KC = (D + 3) / 4;          // K chunks of the cross term
-  constexpr int SD = 4 * KC + 1;           // LDS row stride of the source coordinates (doubles)
+  constexpr bool FOLD = D % 4 == 2;
+  constexpr int KC = (D + (FOLD ? 2 : 0) + 3) / 4;   // K chunks of the contraction
+  constexpr int SD = 4 * KC + 1;                     // LDS row stride of the source entries (doubles)
   constexpr int TS = 256;
-  constexpr int TT = 4 * NFR * 16;         // targets per target tile
+  constexpr int TT = 4 * NFR * 16;                   // targets per target tile
   __shared__ double xs[TS * SD];
   __shared__ double vs[TS];
-  __shared__ double ns[TS];
+  __shared__ double ns[FOLD ? 1 : TS];               // c'|x_j|^2 (without FOLD)
   __shared__ double cacc[4][TS];
+  const double m2c = -2.0 * neg_c;
 
   const int64_t nitems = (int64_t)NS * (NS + 1) / 2;
   const int64_t per = (nitems + 7) / 8;
@@ -346,28 +352,42 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
   const int64_t s0 = (int64_t)c * E, s1 = s0 + E < npad ? s0 + E : npad;
   const int ntile = (int)((s1 - s0) / TS);
   const int ntt = (int)((t1 - t0) / TT);
-  const double m2c = -2.0 * neg_c;
 
   auto run = [&](auto colflag) {
     constexpr bool COL = decltype(colflag)::value;
     for (int tt = 0; tt < ntt; ++tt) {
       const int64_t rowf = t0 + (int64_t)tt * TT + (int64_t)wave * (16 * NFR);
-      double a[NFR][KC], an[NFR][4], vt[NFR][4], acc[NFR][4];
+      double a[NFR][KC], an[NFR][FOLD ? 1 : 4], vt[NFR][4], acc[NFR][4];
 #pragma unroll
       for (int f = 0; f < NFR; ++f) {
+        const int64_t ra = rowf + 16 * f + r16;   // the A operand's row of this lane
+        if (FOLD) {
+          double nn = 0.0;
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-          const int k = 4 * kc + kq;
-          a[f][kc] = k < D ? X[(rowf + 16 * f + r16) * D + k] : 0.0;
+          for (int k = 0; k < D; ++k) nn = __builtin_fma(X[ra * D + k], X[ra * D + k], nn);
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc) {
+            const int k = 4 * kc + kq;
+            a[f][kc] = k < D ? X[ra * D + k] : k == D ? neg_c * nn : k == D + 1 ? 1.0 : 0.0;
+          }
+        } else {
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc) {
+            const int k = 4 * kc + kq;
+            a[f][kc] = k < D ? X[ra * D + k] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {   // c'|x|^2 of the result rows of this lane
+            const int64_t row = rowf + 16 * f + 4 * e + kq;
+            double nn = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) nn = __builtin_fma(X[row * D + k], X[row * D + k], nn);
+            an[f][FOLD ? 0 : e] = neg_c * nn;
+          }
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t row = rowf + 16 * f + 4 * e + kq;
-          double nn = 0.0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) nn = __builtin_fma(X[row * D + k], X[row * D + k], nn);
-          an[f][e] = neg_c * nn;
-          vt[f][e] = COL ? v[row * Rp] : 0.0;
+          vt[f][e] = COL ? v[(rowf + 16 * f + 4 * e + kq) * Rp] : 0.0;
           acc[f][e] = 0.0;
         }
       }
@@ -382,12 +402,17 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
 #pragma unroll
           for (int k = 0; k < D; ++k) {
             const double xv = X[(jt + tid) * D + k];
-            xs[tid * SD + k] = xv;
+            xs[tid * SD + k] = FOLD ? m2c * xv : xv;
             nn = __builtin_fma(xv, xv, nn);
           }
+          if (FOLD) {
+            xs[tid * SD + D] = 1.0;
+            xs[tid * SD + D + 1] = neg_c * nn;
+          } else {
+            ns[tid] = neg_c * nn;
+          }
 #pragma unroll
-          for (int k = D; k < 4 * KC; ++k) xs[tid * SD + k] = 0.0;
-          ns[tid] = neg_c * nn;
+          for (int k = D + (FOLD ? 2 : 0); k < 4 * KC; ++k) xs[tid * SD + k] = 0.0;
           vs[tid] = v[(jt + tid) * Rp];
         }
         __syncthreads();
@@ -397,8 +422,8 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
           double b[KC];
 #pragma unroll
           for (int kc = 0; kc < KC; ++kc) b[kc] = xs[j * SD + 4 * kc + kq];
-          const double bn = ns[j];
           const double vj = vs[j];
+          const double bn = FOLD ? 0.0 : ns[FOLD ? 0 : j];
           f64x4 C[NFR];
 #pragma unroll
           for (int f = 0; f < NFR; ++f) {
@@ -411,7 +436,8 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
           for (int f = 0; f < NFR; ++f)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const double kv = exp2_neg_f64(__builtin_fma(m2c, C[f][e], an[f][e] + bn));
+              const double q = FOLD ? C[f][e] : __builtin_fma(m2c, C[f][e], an[f][FOLD ? 0 : e] + bn);
+              const double kv = exp2_neg_f64(q);
               acc[f][e] = __builtin_fma(kv, vj, acc[f][e]);
               if (COL) cs = __builtin_fma(kv, vt[f][e], cs);
             }

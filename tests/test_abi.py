@@ -84,10 +84,9 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(4, 1, "mixed", square=False) == (3, False)
     assert krr.kmv_variant(8, 1, "mixed", deriv=2, square=True) == (9, False)
     assert krr.kmv_variant(30, 1, "mixed", square=True)[1] is False
-    # FP64 square products: the symmetric form with the cross term on the matrix cores, 4 target fragments
-    # per wave up to d = 4, 2 above
-    assert krr.kmv_variant(8, 1, "fp64", square=True) == (6, True)
-    assert krr.kmv_variant(4, 1, "fp64", square=True) == (5, True)
+    # FP64 square products: the symmetric form with the exponent's cross term on the matrix cores
+    assert krr.kmv_variant(8, 1, "fp64", square=True) == (5, True)
+    assert krr.kmv_variant(6, 1, "fp64", square=True) == (5, True)
     assert krr.kmv_variant(8, 1, "fp64", square=False)[1] is False
     assert krr.kmv_variant(3, 1, "fp64", square=True)[1] is False   # odd padded width: direct kernel
     assert krr.kmv_variant(8, 1, "fp32", square=True)[1] is False

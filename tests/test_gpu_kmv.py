@@ -248,13 +248,13 @@ SYM_VARIANTS = {"mixed": (10, 11), "fp64": (3, 4, 5, 6)}
 
 
 def _f64_cross_term_bar(X, eps):
-    """Bar of the FP64 symmetric forms whose cross term runs on the matrix cores (variants 5, 6): the exponent
-    q = c'(|x_i|^2 + |x_j|^2 - 2 x_i.x_j), c' = log2(e) / eps, on centred coordinates carries a rounding error
-    of at most about (4d + 4) u max|x - mean|^2 |c'|, i.e. a relative error ln2 times that in each kernel
-    value; twice that bound, and never below the direct form's bar."""
+    """Bar of the FP64 symmetric forms whose exponent is contracted on the matrix cores (variants 5, 6): q =
+    c'(|x_i|^2 + |x_j|^2 - 2 x_i.x_j), c' = log2(e) / eps, summed over d + 2 terms on centred coordinates,
+    carries a rounding error of at most about (4d + 8) u max|x - mean|^2 |c'|, i.e. a relative error ln2 times
+    that in each kernel value; twice that bound, and never below the direct form's bar."""
     d = X.shape[1]
     M = float(np.max(np.sum((X - X.mean(axis=0)) ** 2, axis=1)))
-    return max(TOL["fp64"], 2.0 * np.log(2.0) * (np.log2(np.e) / eps) * (4 * d + 4) * 2.0 ** -53 * M)
+    return max(TOL["fp64"], 2.0 * np.log(2.0) * (np.log2(np.e) / eps) * (4 * d + 8) * 2.0 ** -53 * M)
 
 
 @pytest.mark.gpu
