@@ -177,6 +177,53 @@ def kernels_only(a, wl, Xg, krr, torch):
     return 0
 
 
+def traffic_record(a):
+    """CPU only: summarise the FETCH_SIZE and WRITE_SIZE counter passes (rocprofv3 --pmc ... --output-format
+    csv -- python3 bench.py --kernels-only) into profiles/traffic_<workload>.json, the HBM bytes per launch of
+    the workload's mixed MVM kernel that the benchmark reports as roofline.traffic.  Each counter is scaled by
+    what it reads for the 1 GiB copy that --kernels-only runs first (bytes copied / counter)."""
+    import csv
+
+    def per_dispatch(path):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                d = acc.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])
+                d[1] += float(r["Counter_Value"])
+        return [acc[k] for k in sorted(acc)]
+
+    fetch, write = (per_dispatch(p) for p in a.traffic_record)
+    copy_bytes = 1 << 30
+
+    def copy_kib(rows):
+        c = [v for n, v in rows if "copy" in n.lower()]
+        if not c:
+            raise SystemExit("no copy kernel in the counter file")
+        return max(c)
+
+    def kernel_kib(rows):
+        v = [x for n, x in rows if a.kernel_name in n]
+        if not v:
+            raise SystemExit(f"no dispatch of a kernel named like {a.kernel_name!r}")
+        return v, [n for n, _ in rows if a.kernel_name in n][0]
+
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    (kf, name), (kw, _) = kernel_kib(fetch), kernel_kib(write)
+    fs, ws = copy_bytes / 1024 / cf, copy_bytes / 1024 / cw
+    mf, mw = sum(kf) / len(kf), sum(kw) / len(kw)
+    rec = {"workload": a.workload, "kernel": name[:80], "sources_sha256": kernel_sources_sha256(),
+           "files": list(KERNEL_SOURCES), "fetch_kib_per_launch_raw": round(mf, 1),
+           "write_kib_per_launch_raw": round(mw, 1), "launches": len(kf), "copy_bytes": copy_bytes,
+           "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw, "fetch_scale": round(fs, 4),
+           "write_scale": round(ws, 4), "hbm_bytes_per_launch": int(mf * 1024 * fs + mw * 1024 * ws)}
+    path = os.path.join(ROOT, "profiles", f"traffic_{a.workload}.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+    return 0
+
+
 def study_anchors(a, wl, Xg, Yg, krr, torch, datagen, prec, replace_every):
     """Anchor-selection variants on one workload (remark in Sec. 3; the l-versus-iterations tradeoff):
     Algorithm 1 (dense sketch), Algorithm 2 over r, random sampling, farthest point sampling and no
@@ -503,6 +550,10 @@ def main(argv=None):
                     help="profiling mode: a 1 GiB device copy (counter calibration), then the workload's "
                          "mixed and FP64 kernel MVMs; prints their HIP-event times")
     ap.add_argument("--reps", type=int, default=3, help="MVM launches per precision in --kernels-only")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="CPU only: write profiles/traffic_<workload>.json from the two counter passes")
+    ap.add_argument("--kernel-name", default="k_kmv_mixed_sym",
+                    help="kernel whose traffic --traffic-record summarises (a substring of its name)")
     ap.add_argument("--save-alpha", default=None, help="write the timed solve's alpha (.npy) after the run")
     ap.add_argument("--study", default=None, choices=["anchors", "cond"],
                     help="instead of the benchmark step: anchor-selection variants on the workload, or "
@@ -513,6 +564,8 @@ def main(argv=None):
                                    "(row sharding of the targets is designed, not implemented)",
                           "n_gpus": a.gpus}))
         return 2
+    if a.traffic_record:
+        return traffic_record(a)
 
     import numpy as np
     import torch
