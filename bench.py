@@ -575,6 +575,7 @@ def main(argv=None):
 
     krr.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
+    load_launch_table(krr, torch)   # every mode launches the tuned kernels (the default step records the path)
     if a.study == "cond":
         return study_cond(a, krr, torch, datagen)
     wl = datagen.make_workload(a.workload)
