@@ -131,3 +131,27 @@ def test_graph_automatic_choice(gpu_lib, small):
     _, _, _, st, _ = gpu_lib.pcg_solve(X, y, wl.eps, wl.betas[0], P, tol=wl.tol, maxit=5000, prec="fp64",
                                        timing=True)
     assert st["n_graph_cycles"] == 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,R,prec,rep", [(20000, 1, "mixed", 10), (7000, 3, "fp64", 0), (24000, 1, "fp32", 10)],
+                         ids=["n20000_R1_mixed", "n7000_R3_fp64", "n24000_R1_fp32"])
+def test_graph_two_stage_reductions(gpu_lib, n, R, prec, rep):
+    """Problems above the one-workgroup limit (n R > 16384): the gated two-stage column reductions and the
+    separate update kernels inside the captured cycles, against the host loop, bit for bit."""
+    rng = np.random.default_rng(n + R)
+    X = rng.random((n, 4))
+    Y = np.sin(3.0 * X[:, :1] + np.arange(R)[None, :]) + 0.1 * rng.standard_normal((n, R))
+    eps = 0.05
+    betas = [1e-2, 1e-1, 1e-2][:R]
+    k, l = 300, 320
+    idx, sign = datagen.sketch_sparse_draws(n, l, 16, n + R)
+    P = gpu_lib.Preconditioner(torch.from_numpy(X), eps, sorted(set(betas)), k, l, idx=torch.from_numpy(idx),
+                               sign=torch.from_numpy(sign), prec="mixed")
+    Yt = torch.from_numpy(Y if R > 1 else Y[:, 0].copy())
+    h, g = _both(gpu_lib, torch.from_numpy(X), Yt, eps, betas if R > 1 else betas[0], P, tol=1e-8, maxit=3000,
+                 replace_every=rep, prec=prec)
+    print(f"n={n} R={R} {prec}: its {h[1]}; host {h[3]['t_total_ms']:.1f} ms, graph {g[3]['t_total_ms']:.1f} ms "
+          f"({g[3]['n_graph_cycles']} cycles)")
+    _same(h, g)
+    assert h[4] == 0
