@@ -658,7 +658,7 @@ def solve_bench(a, wl, Xg, Yg, sk, betas_col, prec, replace_every, krr, torch):
     t_total = time.perf_counter() - t_start
     P, alpha, its, rel, st, status, t_build, t_step = results[-1]
     pcg_drivers = None
-    if not adjoint and float(wl.n) * wl.n * len(betas_col) <= 2.0 ** 34:
+    if not adjoint and float(wl.n) * wl.n * len(betas_col) <= 2.0 ** 34:   # (automatic mode: 2^30)
         # after the timed region: the same solve under each PCG driver (phase timers off), the second of two
         # calls timed (the first captures the graphs), and whether the two return the same bits
         pcg_drivers = {}

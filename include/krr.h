@@ -269,7 +269,7 @@ typedef struct {
  *      The convergence claims of the recursive residuals are decided on the device; a claim or a breakdown
  *      halts the cycle's remaining state updates, the host takes over at that iteration and runs the host
  *      loop until the next cycle boundary;
- *  -1: automatic (default): graph cycles when the product has at most 2^34 pair-columns (n^2 R), the host
+ *  -1: automatic (default): graph cycles when the product has at most 2^30 pair-columns (n^2 R), the host
  *      loop otherwise.
  * Graph cycles need replace_every <= 64 and timing == 0 (the host loop runs otherwise).
  */

@@ -489,14 +489,16 @@ void set_pcg_mode(int mode) { g_pcg_mode.store(mode); }
 constexpr int kGraphCycle = 16;
 
 // Automatic choice: graph cycles where launches and synchronisations are a visible share of an iteration
-// (products of at most 2^34 pair-columns: a few milliseconds of MVM at most).  Cycles are replace_every
-// iterations long (at most 64), or kGraphCycle without replacement.
+// (products of at most 2^30 pair-columns: n <= 32768 for one column).  Above that the products that run after
+// a halt cost more than the synchronisations saved (n = 1e5, R = 1: 501 ms against 491 ms for the host loop;
+// n = 2000: 19 ms against 22 ms).  Cycles are replace_every iterations long (at most 64), or kGraphCycle
+// without replacement.
 static bool use_graph_cycles(int64_t n, int R, int replace_every, bool timing) {
   if (timing || replace_every > 64) return false;
   const int mode = g_pcg_mode.load();
   if (mode == 0) return false;
   if (mode == 1) return true;
-  return (double)n * (double)n * (double)R <= 17179869184.0;
+  return (double)n * (double)n * (double)R <= 1073741824.0;
 }
 
 PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double* Y, int R, const double* betas,
