@@ -546,6 +546,8 @@ def main(argv=None):
     ap.add_argument("--budget-s", type=float, default=525.0,
                     help="wall-clock budget of the whole run; caps the full solve's iterations")
     ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--beta-columns", type=float, nargs="*", default=None,
+                    help="block workload: solve only the columns of these betas")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling mode: a 1 GiB device copy (counter calibration), then the workload's "
                          "mixed and FP64 kernel MVMs; prints their HIP-event times")
@@ -589,6 +591,15 @@ def main(argv=None):
     Yg = torch.from_numpy(Y).to(dev)
     if wl.col_beta is not None:
         betas_col = [float(b) for b in wl.col_beta]
+        if a.beta_columns:
+            # the columns of the listed betas only (their recurrences are independent of the others; the
+            # preconditioner is still built for every beta of the workload, as in the full run)
+            keep = [c for c, b in enumerate(betas_col) if any(abs(b - x) <= 1e-12 * x for x in a.beta_columns)]
+            if not keep:
+                raise SystemExit("--beta-columns selects no column")
+            Yg = Yg[:, keep].contiguous()
+            betas_col = [betas_col[c] for c in keep]
+            log(f"bench: {len(keep)} of {len(wl.col_beta)} columns (betas {sorted(set(betas_col))})")
     else:
         betas_col = [float(wl.betas[0])] * (1 if Y.ndim == 1 else Y.shape[1])
     if wl.r > 0:
