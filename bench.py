@@ -548,6 +548,8 @@ def main(argv=None):
     ap.add_argument("--maxit", type=int, default=20000)
     ap.add_argument("--beta-columns", type=float, nargs="*", default=None,
                     help="block workload: solve only the columns of these betas")
+    ap.add_argument("--column-slice", type=int, nargs=2, default=None, metavar=("START", "STOP"),
+                    help="with --beta-columns: the selected columns [START, STOP) only")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling mode: a 1 GiB device copy (counter calibration), then the workload's "
                          "mixed and FP64 kernel MVMs; prints their HIP-event times")
@@ -597,9 +599,12 @@ def main(argv=None):
             keep = [c for c, b in enumerate(betas_col) if any(abs(b - x) <= 1e-12 * x for x in a.beta_columns)]
             if not keep:
                 raise SystemExit("--beta-columns selects no column")
+            if a.column_slice:
+                keep = keep[a.column_slice[0]:a.column_slice[1]]
             Yg = Yg[:, keep].contiguous()
             betas_col = [betas_col[c] for c in keep]
-            log(f"bench: {len(keep)} of {len(wl.col_beta)} columns (betas {sorted(set(betas_col))})")
+            log(f"bench: {len(keep)} of {len(wl.col_beta)} columns (betas {sorted(set(betas_col))}, "
+                f"columns {keep[0]}..{keep[-1]})")
     else:
         betas_col = [float(wl.betas[0])] * (1 if Y.ndim == 1 else Y.shape[1])
     if wl.r > 0:
