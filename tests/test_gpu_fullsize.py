@@ -1,8 +1,9 @@
 """Parity at the workloads' full sizes, in the launch configuration the benchmark uses.
 
 The oracle cannot form these products whole, so outputs are checked on sampled rows it computes one by
-one (exact FP64 sums over all n sources), and the preconditioner through a property that holds at any
-size: applying it to (W W^T + beta I) x returns x.
+one (exact FP64 sums over all n sources); the preconditioner's factor on sampled rows of W W^T against the
+oracle's own EVD of the anchor block (given the GPU's anchors), and its apply through a property that holds
+at any size: applying it to (W W^T + beta I) x returns x.
 """
 import numpy as np
 import pytest
@@ -120,4 +121,38 @@ def test_fp32_workload_preconditioner_inverts_its_operator(gpu_lib):
         got = P.apply(b, betas=[beta], prec=prec)
         err = float(torch.linalg.norm(got - x) / torch.linalg.norm(x))
         print(f"fp32 workload preconditioner {prec}: ||P^-1 (WW^T + bI) x - x|| / ||x|| = {err:.2e}", flush=True)
+        assert err <= tol
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["fp32", "mixed"])
+def test_precond_factor_rows_against_oracle(gpu_lib, name):
+    """The Nystrom factor at full size (Algorithm 3 with Algorithm 2 anchors; n = 1e5, k = 1000 and n = 1e6,
+    k = 2000) against the oracle on sampled rows: W W^T restricted to the rows I (invariant under the EVD's
+    sign and order choices) equals C_I V diag(1/lambda) V^T C_I^T, with C_I = K(X_I, X_S) computed by the
+    oracle, K_SS's eigenpairs from numpy.linalg.eigh, the GPU's anchors S and its kept count (the largest
+    eigenvalues).  The FP32 copy of W is compared the same way at the FP32 rounding bar."""
+    wl = datagen.make_workload(name)
+    beta = wl.betas[0]
+    idx, sign = datagen.sketch_sparse_draws(wl.n, wl.l, wl.r, datagen.sketch_seed(name))
+    P = gpu_lib.Preconditioner(torch.from_numpy(wl.X), wl.eps, [beta], wl.k, wl.l, idx=torch.from_numpy(idx),
+                               sign=torch.from_numpy(sign), prec="mixed")
+    info = P.info()
+    S = np.array(info["S"], dtype=np.int64)
+    kept = int(info["kept"])
+    rng = np.random.default_rng(17)
+    rows = np.sort(rng.choice(wl.n, ROWS, replace=False))
+    Kss = ok.kernel_matrix(wl.X[S], wl.X[S], wl.eps)
+    lam, V = np.linalg.eigh(Kss)
+    lam, V = lam[::-1][:kept], V[:, ::-1][:, :kept]
+    C = ok.kernel_matrix(wl.X[rows], wl.X[S], wl.eps)
+    B = C @ V / np.sqrt(lam)
+    ref = B @ B.T
+    ridx = torch.from_numpy(rows).cuda()
+    for which, tol in ((P.W64, 1e-9), (P.W32, 1e-6)):
+        Wr = P.get(which)[ridx].double().cpu().numpy()
+        got = Wr @ Wr.T
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        print(f"{name} workload factor ({'FP64' if which == P.W64 else 'FP32'} copy): kept {kept} of {len(S)}, "
+              f"max |W_I W_I^T - oracle| / max|oracle| = {err:.2e}", flush=True)
         assert err <= tol
