@@ -133,9 +133,10 @@ struct DotEpilogue {
   int* halt = nullptr;
 };
 
-// The epilogue of column c's sum v (thread-level; out[c] = v first).
-__device__ __forceinline__ void dot_epilogue(const DotEpilogue& e, const Gate& gate, int c, int R, double v,
-                                             double* __restrict__ out) {
+// The epilogue of column c's sum v (thread-level; out[c] = v first).  Returns gamma_c (kGamma) or beta_c
+// (kBeta), 0 otherwise.
+__device__ __forceinline__ double dot_epilogue(const DotEpilogue& e, const Gate& gate, int c, int R, double v,
+                                               double* __restrict__ out) {
   out[c] = v;
   if (e.mode == DotEpilogue::kGamma) {
     double g = 0.0;
@@ -144,10 +145,12 @@ __device__ __forceinline__ void dot_epilogue(const DotEpilogue& e, const Gate& g
       else g = e.rho[c] / v;
     }
     e.gamma[c] = g;
+    return g;
   } else if (e.mode == DotEpilogue::kBeta) {
     double b = 0.0;
     if (e.active[c]) b = e.rho[c] != 0.0 ? v / e.rho[c] : 0.0;
     e.beta[c] = b;
+    return b;
   } else if (e.mode == DotEpilogue::kStatus) {
     const int it = (e.it_base ? *e.it_base : 0) + e.it_off;
     const bool claim = e.active[c] && it >= e.next_check[c] && sqrt(v) / e.ynorm[c] <= e.tol;
@@ -164,6 +167,7 @@ __device__ __forceinline__ void dot_epilogue(const DotEpilogue& e, const Gate& g
   } else if (e.mode == DotEpilogue::kCheck) {
     e.hs[c] = v;
   }
+  return 0.0;
 }
 
 // out[c] = sum_by part[by, c]: one block per column, fixed-order LDS tree (nby <= 256), then the epilogue.
@@ -224,6 +228,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_step_small(double* __restrict
                                                               DotEpilogue es, Gate gate) {
   if (gate.closed()) return;
   __shared__ double red[kSmallThreads];
+  __shared__ double sg[256];   // gamma per column (R <= 256)
   const int cl = threadIdx.x % CB;
   const int rl = threadIdx.x / CB;
   const int rows = kSmallThreads / CB;
@@ -233,14 +238,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_step_small(double* __restrict
     if (c < R)
       for (int64_t i = rl; i < n; i += rows) s = __builtin_fma(p[i * R + c], q[i * R + c], s);
     const double v = block_colsum(red, s, CB);
-    if (rl == 0 && c < R) dot_epilogue(eg, gate, c, R, v, pq);
+    if (rl == 0 && c < R) sg[c] = dot_epilogue(eg, gate, c, R, v, pq);
   }
   __syncthreads();   // every column's gamma and the breakdown flag are written
   for (int c0 = 0; c0 < R; c0 += CB) {
     const int c = c0 + cl;
     double s = 0.0;
     if (c < R) {
-      const double g = eg.gamma[c];
+      const double g = sg[c];
       for (int64_t i = rl; i < n; i += rows) {
         const int64_t t = i * R + c;
         x[t] = __builtin_fma(g, p[t], x[t]);
@@ -263,6 +268,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_dir_small(const double* __res
                                                              DotEpilogue eb, Gate gate) {
   if (gate.closed()) return;
   __shared__ double red[kSmallThreads];
+  __shared__ double sb[256];   // beta per column (R <= 256)
   const int cl = threadIdx.x % CB;
   const int rl = threadIdx.x / CB;
   const int rows = kSmallThreads / CB;
@@ -272,13 +278,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_dir_small(const double* __res
     if (c < R)
       for (int64_t i = rl; i < n; i += rows) s = __builtin_fma(r[i * R + c], z[i * R + c], s);
     const double v = block_colsum(red, s, CB);
-    if (rl == 0 && c < R) dot_epilogue(eb, gate, c, R, v, rho_new);
+    if (rl == 0 && c < R) sb[c] = dot_epilogue(eb, gate, c, R, v, rho_new);
   }
   __syncthreads();
   for (int c0 = 0; c0 < R; c0 += CB) {
     const int c = c0 + cl;
     if (c >= R) continue;
-    const double b = eb.beta[c];
+    const double b = sb[c];
     const bool act = active[c] != 0;
     for (int64_t i = rl; i < n; i += rows) {
       const int64_t t = i * R + c;
@@ -387,7 +393,11 @@ __global__ void k_cycle_begin(int* __restrict__ halt, int* __restrict__ it_base,
   }
 }
 
-__global__ void k_cycle_end(const int* __restrict__ halt, double* __restrict__ ctrl) {
+// ... and copy the cycle's statuses and check (written to device memory during the cycle) to the host-mapped
+// words in one pass, so that no iteration of the cycle waits on a store to host memory.
+__global__ void k_cycle_end(const int* __restrict__ halt, double* __restrict__ ctrl, const double* __restrict__ src,
+                            double* __restrict__ dst, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
   if (threadIdx.x == 0) ctrl[1] = (double)*halt;
 }
 
@@ -623,6 +633,10 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   double* hs = status_buffer(B * SS + R + 2);
   double* hcheck = hs + B * SS;
   double* hctrl = hcheck + R;
+  // the same statuses and check in device memory, for the captured cycles
+  DevBuf<double> dstat(graph_on ? B * SS + R : 0, s);
+  double* dhs = dstat.p;
+  double* dcheck = graph_on ? dstat.p + B * SS : nullptr;
   // Safeguards: the best iterate by true residual is kept per column.  The residual 2-norm of CG is
   // not monotone (CG minimises the A-norm of the error), so a column is only stopped (KRR_ENOCONV, best
   // iterate returned) when its true residual is not finite or exceeds 1e6 times its best, or when its
@@ -848,7 +862,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       enqueue_direction(cs, Gate());
       for (int u = 0; u < B; ++u) {
         Aw.apply(pp, betas, qq, cs);
-        step_dir(cs, true, epi_status(hs + u * SS, it_base_d, u + 1, halt_d), Gate{halt_d, u + 1}, u + 1 < B, pp,
+        step_dir(cs, true, epi_status(dhs + u * SS, it_base_d, u + 1, halt_d), Gate{halt_d, u + 1}, u + 1 < B, pp,
                  pp, Gate{halt_d, u + 2});
         if (u + 1 < B) std::swap(rho, rho_new);
       }
@@ -858,10 +872,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
                            Gate{halt_d, B});
         DotEpilogue ec;
         ec.mode = DotEpilogue::kCheck;
-        ec.hs = hcheck;
+        ec.hs = dcheck;
         red.dot(r.p, nullptr, n, rr, cs, ec, Gate{halt_d, B});
       }
-      hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, cs, (const int*)halt_d, hctrl);
+      hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(256), 0, cs, (const int*)halt_d, hctrl, (const double*)dhs, hs,
+                         (int)(B * SS + R));
       KRR_LAUNCH_CHECK();
     } catch (...) {
       (void)hipStreamEndCapture(cs, &graph);
