@@ -70,6 +70,10 @@ struct StagedVec {
   int64_t npad = 0;
   int R = 0;            // columns padded to a multiple of 8
   int Rreal = 0;
+  // column c of the staged vectors is column cols[c] of the caller's V (row stride ldv), and the products
+  // go to the same columns of U; nullptr: columns 0 .. Rreal - 1 of a V with Rreal columns
+  const int* cols = nullptr;
+  int ldv = 0;
   DevBuf<double> v64;   // npad x R
   DevBuf<float> v32;    // npad x R
   // block-MVM operands: BF16 parts in groups of four sources, V4[((j/4) * Rb + r) * 4 + j%4]
@@ -81,9 +85,11 @@ void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad
                          hipStream_t s);
 // Whether kmv_launch takes the block (multi right-hand side) path for these parameters.
 bool kmv_uses_block(int prec, int d, int R, int deriv);
-// perm: the operator's staged order (Staged::perm), nullptr for the caller's order.
+// perm: the operator's staged order (Staged::perm), nullptr for the caller's order.  cols (device, R entries)
+// and ldv: stage columns cols[0 .. R) of a V whose rows hold ldv values (a subset of its columns); the kernel
+// MVM then writes its products to those columns of U (one product without the derivative kernel).
 void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
-                   hipStream_t s, const int64_t* perm = nullptr);
+                   hipStream_t s, const int64_t* perm = nullptr, const int* cols = nullptr, int ldv = 0);
 
 // Core launcher: U[i, col0 + c] (row stride ldu) for the staged operands.
 //   deriv: 0 K, 1 K', 2 both (K columns first, then K' columns).

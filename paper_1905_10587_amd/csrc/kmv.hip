@@ -199,20 +199,24 @@ void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int
 }
 
 __global__ void k_stage_vec(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rp,
-                            const int64_t* __restrict__ perm, double* __restrict__ o64, float* __restrict__ o32) {
+                            const int64_t* __restrict__ perm, const int* __restrict__ cols, int ldv,
+                            double* __restrict__ o64, float* __restrict__ o32) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npad * Rp) return;
   int64_t i = idx / Rp;
   int c = (int)(idx % Rp);
-  double v = (i < n && c < R) ? V[(perm ? perm[i] : i) * R + c] : 0.0;
+  double v = (i < n && c < R) ? V[(perm ? perm[i] : i) * ldv + (cols ? cols[c] : c)] : 0.0;
   if (o64) o64[idx] = v;
   if (o32) o32[idx] = (float)v;
 }
 
 void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int prec,
-                   hipStream_t s, const int64_t* perm) {
+                   hipStream_t s, const int64_t* perm, const int* cols, int ldv) {
+  KRR_REQUIRE(!cols || (ldv >= R && !perm), "internal: a column subset needs its row stride and the caller's order");
   sv.npad = npad;
   sv.Rreal = R;
+  sv.cols = cols;
+  sv.ldv = cols ? ldv : R;
   // column chunks are at most 8 wide; FP64 with more than 8 columns pads to 16 for the matrix-core kernel
   sv.R = (int)round_up(R, prec == KRR_FP64 && R > 8 ? 16 : 8);
   const int64_t tot = npad * sv.R;
@@ -222,18 +226,19 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
   } else {
     if (sv.v32.n != cap) sv.v32.alloc(cap, s);
   }
-  hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R, perm,
-                     sv.v64.p, sv.v32.p);
+  hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R, perm, cols,
+                     sv.ldv, sv.v64.p, sv.v32.p);
   KRR_LAUNCH_CHECK();
 }
 
 __global__ void k_stage_v4(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rb, int nsplit,
-                           uint16_t* __restrict__ vh, uint16_t* __restrict__ vm, uint16_t* __restrict__ vl) {
+                           const int* __restrict__ cols, int ldv, uint16_t* __restrict__ vh,
+                           uint16_t* __restrict__ vm, uint16_t* __restrict__ vl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= npad * Rb) return;
   const int64_t j = t / Rb;
   const int r = (int)(t % Rb);
-  const double x = (j < n && r < R) ? V[j * R + r] : 0.0;
+  const double x = (j < n && r < R) ? V[j * ldv + (cols ? cols[r] : r)] : 0.0;
   const int64_t o = ((j >> 2) * Rb + r) * 4 + (j & 3);
   uint16_t h, m, l;
   split3(x, h, m, l);
@@ -255,7 +260,7 @@ void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad
   if (sv.vm.n != tot) sv.vm.alloc(tot, s);
   if (nsplit == 3 && sv.vl.n != tot) sv.vl.alloc(tot, s);
   hipLaunchKernelGGL(k_stage_v4, dim3((unsigned)ceil_div((int64_t)tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.Rb,
-                     nsplit, sv.vh.p, sv.vm.p, nsplit == 3 ? sv.vl.p : nullptr);
+                     nsplit, sv.cols, sv.cols ? sv.ldv : R, sv.vh.p, sv.vm.p, nsplit == 3 ? sv.vl.p : nullptr);
   KRR_LAUNCH_CHECK();
 }
 
@@ -269,7 +274,7 @@ struct ShiftArg {
 __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpad, int Rp, int Rout,
                              int deriv, int64_t m, int R, int has_shift, ShiftArg sh,
                              const double* __restrict__ Vraw, const int64_t* __restrict__ perm,
-                             double* __restrict__ U, int64_t ldu) {
+                             const int* __restrict__ cols, int ldv, double* __restrict__ U, int64_t ldu) {
   const int Rcols = deriv == 2 ? 2 * R : R;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * Rcols) return;
@@ -285,8 +290,9 @@ __global__ void k_kmv_finish(const double* __restrict__ part, int S, int64_t mpa
 #pragma unroll 16
   for (int p = 0; p < S; ++p) acc += part[((int64_t)p * mpad + i) * Rout + pc];
   const int64_t oi = perm ? perm[i] : i;   // staged row i is the caller's row oi
-  if (has_shift && kcol) acc += sh.v[oc] * Vraw[oi * R + oc];
-  U[oi * ldu + oc] = acc;
+  const int col = cols ? cols[oc] : oc;     // (a column subset: one product without the derivative kernel)
+  if (has_shift && kcol) acc += sh.v[oc] * Vraw[oi * ldv + col];
+  U[oi * ldu + col] = acc;
 }
 
 // ------------------------------------------------------------------ variants and launcher
@@ -574,6 +580,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
                 const double* Vraw, int prec, double* U, int64_t ldu, hipStream_t s, int variant,
                 DevBuf<double>* ws, const hipEvent_t* kev, int split_req) {
   KRR_REQUIRE(T.prec == prec && S.prec == prec, "staged precision mismatch");
+  KRR_REQUIRE(!V.cols || (deriv == 0 && ldu >= V.ldv), "internal: a column subset is for one K product into U");
   const int R = V.Rreal, Rp = V.R;
   KRR_REQUIRE(R >= 1 && R <= 256, "R must be in [1, 256]");
   const int DV = deriv == 0 ? 0 : 2;
@@ -770,7 +777,8 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   const int Rcols = deriv == 2 ? 2 * R : R;
   const int64_t tot = T.n * Rcols;
   hipLaunchKernelGGL(k_kmv_finish, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, part.p, (int)split,
-                     T.npad, RpK, RoutK, deriv, T.n, R, has_shift, sh, Vraw, (const int64_t*)T.perm.p, U, ldu);
+                     T.npad, RpK, RoutK, deriv, T.n, R, has_shift, sh, Vraw, (const int64_t*)T.perm.p, V.cols,
+                     V.cols ? V.ldv : R, U, ldu);
   KRR_LAUNCH_CHECK();
 }
 

@@ -484,9 +484,12 @@ struct Operator {
     const bool sort = prec == KRR_MIXED && R == 1 && cull_wanted(X, n, d, eps, s);
     stage_points(S, X, n, d, eps, prec, center, true, true, s, sort);
   }
-  // out = (K + diag(shift)) v   (shift may be null)
-  void apply(const double* v, const double* shift, double* out, hipStream_t s, const hipEvent_t* kev = nullptr) {
-    stage_vectors(V, v, n, S.npad, R, prec, s, S.perm.p);
+  // out = (K + diag(shift)) v   (shift may be null).  cols (device, ncols entries): only those columns of v are
+  // multiplied, into the same columns of out (shift then holds their ncols shifts); the others are not written.
+  void apply(const double* v, const double* shift, double* out, hipStream_t s, const hipEvent_t* kev = nullptr,
+             const int* cols = nullptr, int ncols = 0) {
+    if (cols) stage_vectors(V, v, n, S.npad, ncols, prec, s, nullptr, cols, R);
+    else stage_vectors(V, v, n, S.npad, R, prec, s, S.perm.p);
     kmv_launch(S, S, V, 0, shift, v, prec, out, R, s, -1, &ws, kev);
   }
 };
@@ -542,6 +545,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   WoodburyWork ww;
   if (P) ww.prepare(*P, R, bidx.data(), s);
   DevBuf<double> r(nR, s), z(nR, s), p(nR, s), q(nR, s), p2(nR, s), q2(nR, s);
+  for (double* b : {p.p, q.p, p2.p, q2.p}) KRR_CHECK_HIP(hipMemsetAsync(b, 0, sizeof(double) * nR, s));
   DevBuf<double> sc(8 * (size_t)R, s);   // rho (two buffers), pq, gamma, beta, rr, yy, ||y||
   // r^T z of the current iteration and of the next one; the host swaps the two when an iteration
   // advances, so a discarded look-ahead leaves rho as it was
@@ -582,12 +586,37 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     if (!(ynorm[c] > 0)) act[c] = 0;
   }
   std::vector<int> next_check(R, 0);
+  // Products of a block with frozen columns form only the active ones (their columns gathered when staged,
+  // scattered when finished); the frozen columns of q keep their last, finite values, which their zero step
+  // lengths never use.
+  std::vector<int> acols;
+  std::vector<double> ashift;
+  DevBuf<int> cols_d(R, s);
+  const int* colsp = nullptr;   // device list of the active columns, nullptr when every column takes part
+  int ncols = R;
+  bool graphs_stale = false;    // captured cycles launch products of the previous active set
   // device copies of the mask, the norms and the check schedule the status kernel decides claims with
   // (copied from host vectors: the stream is synchronised before they change)
   auto upload_state = [&]() {
     KRR_CHECK_HIP(hipMemcpyAsync(active.p, act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
     KRR_CHECK_HIP(hipMemcpyAsync(next_check_d, next_check.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    acols.clear();
+    ashift.clear();
+    for (int c = 0; c < R; ++c)
+      if (act[c]) {
+        acols.push_back(c);
+        ashift.push_back(betas[c]);
+      }
+    const bool sub = R > 1 && !acols.empty() && (int)acols.size() < R;
+    if (sub) KRR_CHECK_HIP(hipMemcpyAsync(cols_d.p, acols.data(), sizeof(int) * acols.size(), hipMemcpyHostToDevice, s));
+    if ((sub ? cols_d.p : nullptr) != colsp || (sub ? (int)acols.size() : R) != ncols) graphs_stale = true;
+    colsp = sub ? cols_d.p : nullptr;
+    ncols = sub ? (int)acols.size() : R;
     KRR_CHECK_HIP(hipStreamSynchronize(s));
+  };
+  // out = (K + diag(beta)) v with operator A over the active columns
+  auto product = [&](Operator& A, const double* v, double* out, hipStream_t st, const hipEvent_t* kev) {
+    A.apply(v, colsp ? ashift.data() : betas, out, st, kev, colsp, ncols);
   };
   KRR_CHECK_HIP(hipMemcpyAsync(ynorm_d, ynorm.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
   upload_state();
@@ -600,7 +629,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   KRR_CHECK_HIP(hipStreamSynchronize(s));
   if (hflags[0]) {
     tm.start(&res.st.t_mvm_fp64_ms);
-    Atrue->apply(x, betas, q.p, s);
+    product(*Atrue, x, q.p, s, nullptr);
     tm.stop();
     res.st.n_mvm_fp64++;
     KRR_CHECK_HIP(hipMemcpyAsync(r.p, Y, sizeof(double) * nR, hipMemcpyDeviceToDevice, s));
@@ -765,7 +794,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   // true residual in FP64 (replaces the recursive one), then the decisions
   auto check = [&](bool scheduled) {
     tm.start(&res.st.t_mvm_fp64_ms);
-    Atrue->apply(x, betas, qq, s);
+    product(*Atrue, x, qq, s, nullptr);
     tm.stop();
     res.st.n_mvm_fp64++;
     if (scheduled) res.st.n_replace++;
@@ -850,6 +879,11 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     }
   } graph_guard{graphs, cs};
   auto cycle_graph = [&]() -> hipGraphExec_t {
+    if (graphs_stale) {
+      for (auto& c : graphs) (void)hipGraphExecDestroy(c.exec);
+      graphs.clear();
+      graphs_stale = false;
+    }
     for (auto& c : graphs)
       if (c.pp == pp && c.qq == qq && c.rho == rho) return c.exec;
     if (!cs) KRR_CHECK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -861,13 +895,13 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
       hipLaunchKernelGGL(k_cycle_begin, dim3(1), dim3(64), 0, cs, halt_d, it_base_d, (const double*)hctrl);
       enqueue_direction(cs, Gate());
       for (int u = 0; u < B; ++u) {
-        Aw.apply(pp, betas, qq, cs);
+        product(Aw, pp, qq, cs, nullptr);
         step_dir(cs, true, epi_status(dhs + u * SS, it_base_d, u + 1, halt_d), Gate{halt_d, u + 1}, u + 1 < B, pp,
                  pp, Gate{halt_d, u + 2});
         if (u + 1 < B) std::swap(rho, rho_new);
       }
       if (cycle_check) {
-        Atrue->apply(x, betas, qq, cs);
+        product(*Atrue, x, qq, cs, nullptr);
         hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, cs, r.p, Y, qq, active.p, n, R,
                            Gate{halt_d, B});
         DotEpilogue ec;
@@ -963,7 +997,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     // q = (K + beta I) p in the working precision
     if (!have_next) {
       tm.start(&res.st.t_mvm_ms);
-      Aw.apply(pp, betas, qq, s, tm.external(&res.st.t_mvm_kernel_ms));
+      product(Aw, pp, qq, s, tm.external(&res.st.t_mvm_kernel_ms));
       tm.stop();
     }
     have_next = false;
@@ -977,7 +1011,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
     if (ahead) {
       direction(s, pp, pa, Gate());
       tm.start(&res.st.t_mvm_ms);
-      Aw.apply(pa, betas, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
+      product(Aw, pa, qa, s, tm.external(&res.st.t_mvm_kernel_ms));
       tm.stop();
     }
     KRR_CHECK_HIP(hipEventSynchronize(ev_status));
@@ -1008,7 +1042,7 @@ PcgResult pcg_solve(const double* X, int64_t n, int d, double eps, const double*
   bool unfinished = false;
   for (int c = 0; c < R; ++c) unfinished |= act[c] != 0;
   if (unfinished && !fresh_true) {   // (after a check in the last iteration its residuals are current)
-    Atrue->apply(x, betas, qq, s);
+    product(*Atrue, x, qq, s, nullptr);
     res.st.n_mvm_fp64++;
     hipLaunchKernelGGL(k_residual, dim3(nb(nR)), dim3(256), 0, s, r.p, Y, qq, active.p, n, R, Gate());
     red.dot(r.p, nullptr, n, rr, s);
