@@ -160,7 +160,10 @@ def kernels_only(a, wl, Xg, krr, torch):
     torch.cuda.synchronize()
     del src, flush, dst
     out = {"copy_bytes": nbytes}
-    v = torch.randn(wl.n, dtype=torch.float64, device=dev)
+    R = wl.y.shape[1] if wl.y.ndim == 2 else 1   # the workload's right-hand sides (the block MVM for R > 1)
+    v = torch.randn(wl.n, R, dtype=torch.float64, device=dev) if R > 1 else torch.randn(wl.n, dtype=torch.float64,
+                                                                                            device=dev)
+    out["columns"] = R
     for prec, reps in (("mixed", a.reps), ("fp64", 1)):
         times = []
         for _ in range(reps):
