@@ -51,18 +51,25 @@ def peak_mixed(d, sym):
     return (2.0 if sym else 1.0) * 256 * SIMD_CYCLES / ((64 if sym else 48) + 16 * nch)
 
 
+def f64_symm_slots(d):
+    """VALU instructions per evaluated pair of the FP64 symmetric matrix-core form (see peak_direct)."""
+    width = next((w for w in (2, 3, 4, 6, 8, 16) if d <= w), d)   # the kernel's padded width (no such form above 16)
+    return 17 if width % 4 == 2 else 18
+
+
 def peak_direct(d, prec, sym, variant=None):
     """VALU bound of the FP32 / FP64 forms (one lane-slot per VALU instruction, exp2 in FP32 counted as two):
     FP32 per pair d subtractions + d FMAs + exp + one FMA; FP64 per pair d subtractions + d FMAs + a
     16-instruction exp2 (scaling by -log2(e)/eps, reduction, degree-10 polynomial, 2^n) + one FMA, + one more
     FMA in the symmetric form, whose evaluated pair serves two pairs of the product.  The FP64 symmetric forms
-    with the exponent's cross term on the matrix cores (variants 5, 6) issue 19 VALU instructions per evaluated
-    pair whatever d (q from the two norms and the cross term: 2; exp2 without the scaling: 15; row and column
-    FMAs: 2), 17 where the norms are contracted with it (d = 2, 6); their MFMAs run on the matrix cores."""
+    with the exponent's cross term on the matrix cores (variants 5, 6) issue 18 VALU instructions per evaluated
+    pair whatever d (q from the contraction, which starts from the row norm, and the source norm: 1; exp2 without
+    the scaling: 15; row and column FMAs: 2), 17 where both norms are contracted with it (padded widths 2, 6);
+    their MFMAs run on the matrix cores."""
     if prec == "fp32":
         return SLOTS / (2 * d + 3)
     if sym and variant is not None and variant >= 5:
-        return 2.0 * SLOTS / (17 if d % 4 == 2 else 19)
+        return 2.0 * SLOTS / f64_symm_slots(d)
     return (2.0 * SLOTS / (2 * d + 18)) if sym else SLOTS / (2 * d + 17)
 # Files whose contents define the mixed MVM kernels and their launch: a stored counter summary is used
 # for roofline.traffic only while these hash to the value recorded with it.
@@ -334,7 +341,7 @@ def mvm_roofline(prec, d, R, n, avg_ms, launches, variant, sym, traffic):
         peak = ser = peak_direct(d, prec, sym, variant)
         form = f"{'symmetric' if sym else 'direct'} form, {prec} VALU ops per pair"
         if prec == "fp64" and sym and variant is not None and variant >= 5:
-            form = (f"symmetric form, exponent's cross term on the FP64 matrix cores, {17 if d % 4 == 2 else 19} "
+            form = (f"symmetric form, exponent's cross term on the FP64 matrix cores, {f64_symm_slots(d)} "
                     f"VALU ops per evaluated pair")
     rec = {"bound": "alu", "kernel": f"{prec} MVM, variant {variant}, {form}, d={d}",
            "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2), "unit": "Tpairs/s",

@@ -221,10 +221,12 @@ void stage_vectors(StagedVec& sv, const double* V, int64_t n, int64_t npad, int 
   sv.R = (int)round_up(R, prec == KRR_FP64 && R > 8 ? 16 : 8);
   const int64_t tot = npad * sv.R;
   const size_t cap = (size_t)(npad + kPrefetchRows) * sv.R;   // padding rows: read by the last prefetch only
+  // grow only: a solve whose active columns shrink reuses the buffer, so products captured into a graph after
+  // the first one allocate nothing
   if (prec == KRR_FP64) {
-    if (sv.v64.n != cap) sv.v64.alloc(cap, s);
+    if (sv.v64.n < cap) sv.v64.alloc(cap, s);
   } else {
-    if (sv.v32.n != cap) sv.v32.alloc(cap, s);
+    if (sv.v32.n < cap) sv.v32.alloc(cap, s);
   }
   hipLaunchKernelGGL(k_stage_vec, dim3(ceil_div(tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.R, perm, cols,
                      sv.ldv, sv.v64.p, sv.v32.p);
@@ -256,9 +258,9 @@ void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad
   sv.Rreal = R;
   sv.Rb = (int)round_up(R, rpad);
   const size_t tot = (size_t)npad * sv.Rb;
-  if (sv.vh.n != tot) sv.vh.alloc(tot, s);
-  if (sv.vm.n != tot) sv.vm.alloc(tot, s);
-  if (nsplit == 3 && sv.vl.n != tot) sv.vl.alloc(tot, s);
+  if (sv.vh.n < tot) sv.vh.alloc(tot, s);   // grow only, as in stage_vectors
+  if (sv.vm.n < tot) sv.vm.alloc(tot, s);
+  if (nsplit == 3 && sv.vl.n < tot) sv.vl.alloc(tot, s);
   hipLaunchKernelGGL(k_stage_v4, dim3((unsigned)ceil_div((int64_t)tot, 256)), dim3(256), 0, s, V, n, R, npad, sv.Rb,
                      nsplit, sv.cols, sv.cols ? sv.ldv : R, sv.vh.p, sv.vm.p, nsplit == 3 ? sv.vl.p : nullptr);
   KRR_LAUNCH_CHECK();

@@ -304,11 +304,14 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
 // Symmetric FP64 form with the exponent's cross term on the FP64 matrix cores (v_mfma_f64_16x16x4f64, FP64
 // products and sums): q = c'|x_i|^2 + c'|x_j|^2 - 2c' x_i.x_j (c' = neg_c).  When D + 2 fits the K padding
 // (D = 2, 6: FOLD) the whole of q is the contraction of a_i = [x_i, c'|x_i|^2, 1] with b_j = [-2c' x_j, 1,
-// c'|x_j|^2], and a pair costs the FP64 exp2 and the row and column FMAs on the VALU; otherwise the MFMA gives
-// x_i.x_j and q = fma(-2c', x_i.x_j, c'|x_i|^2 + c'|x_j|^2) adds two VALU operations (an extra K chunk costs
-// more than these, the MFMA work not being hidden behind the VALU work).  Either way the direct form's D
-// subtractions, D FMAs and scaling are gone.  The cancellation leaves an error of up to about (4D + 8) u |c'|
-// max|x|^2 in q (centred coordinates), a relative error ln2 times that in a kernel value.
+// c'|x_j|^2], and a pair costs the FP64 exp2 and the row and column FMAs on the VALU; otherwise the MFMA
+// contracts x_i with b_j = -2c' x_j on top of the accumulator input c'|x_i|^2 (the lane's four result rows),
+// and q = C + c'|x_j|^2 adds one VALU operation (an extra K chunk costs more than this, the MFMA work not
+// being hidden behind the VALU work).  Either way the direct form's D subtractions, D FMAs and scaling are
+// gone.  The cancellation leaves an error of up to about k u |c'| max|x|^2 in q (centred coordinates), a
+// relative error ln2 times that in a kernel value: the norms 2(D + 1), the scaled b_j 2, and D accumulation
+// steps on partial sums up to 3|c'| max|x|^2 plus the final addition 4 (k = 5D + 8), or with FOLD D + 2 steps
+// on partial sums up to 4|c'| max|x|^2 (k = 6D + 12).
 // Same super-tiles, triangle order and partial slots as k_kmv_f64_sym.  Block: 4 waves x NFR fragments of 16
 // targets (64 NFR targets); source tiles of 256 points in LDS (b_j, or x_j and c'|x_j|^2), 16 sources per
 // MFMA step.
@@ -357,7 +360,8 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
     constexpr bool COL = decltype(colflag)::value;
     for (int tt = 0; tt < ntt; ++tt) {
       const int64_t rowf = t0 + (int64_t)tt * TT + (int64_t)wave * (16 * NFR);
-      double a[NFR][KC], an[NFR][FOLD ? 1 : 4], vt[NFR][4], acc[NFR][4];
+      double a[NFR][KC], vt[NFR][4], acc[NFR][4];
+      f64x4 an[NFR];   // the MFMA's accumulator input: c'|x|^2 of the lane's four result rows (FOLD: zero)
 #pragma unroll
       for (int f = 0; f < NFR; ++f) {
         const int64_t ra = rowf + 16 * f + r16;   // the A operand's row of this lane
@@ -370,6 +374,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
             const int k = 4 * kc + kq;
             a[f][kc] = k < D ? X[ra * D + k] : k == D ? neg_c * nn : k == D + 1 ? 1.0 : 0.0;
           }
+          an[f] = f64x4{0.0, 0.0, 0.0, 0.0};
         } else {
 #pragma unroll
           for (int kc = 0; kc < KC; ++kc) {
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
             double nn = 0.0;
 #pragma unroll
             for (int k = 0; k < D; ++k) nn = __builtin_fma(X[row * D + k], X[row * D + k], nn);
-            an[f][FOLD ? 0 : e] = neg_c * nn;
+            an[f][e] = neg_c * nn;
           }
         }
 #pragma unroll
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
 #pragma unroll
           for (int k = 0; k < D; ++k) {
             const double xv = X[(jt + tid) * D + k];
-            xs[tid * SD + k] = FOLD ? m2c * xv : xv;
+            xs[tid * SD + k] = m2c * xv;
             nn = __builtin_fma(xv, xv, nn);
           }
           if (FOLD) {
@@ -427,16 +432,16 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
           f64x4 C[NFR];
 #pragma unroll
           for (int f = 0; f < NFR; ++f) {
-            C[f] = f64x4{0.0, 0.0, 0.0, 0.0};
+            C[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][0], b[0], an[f], 0, 0, 0);
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) C[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][kc], b[kc], C[f], 0, 0, 0);
+            for (int kc = 1; kc < KC; ++kc) C[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][kc], b[kc], C[f], 0, 0, 0);
           }
           double cs = 0.0;
 #pragma unroll
           for (int f = 0; f < NFR; ++f)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const double q = FOLD ? C[f][e] : __builtin_fma(m2c, C[f][e], an[f][FOLD ? 0 : e] + bn);
+              const double q = FOLD ? C[f][e] : C[f][e] + bn;
               const double kv = exp2_neg_f64(q);
               acc[f][e] = __builtin_fma(kv, vj, acc[f][e]);
               if (COL) cs = __builtin_fma(kv, vt[f][e], cs);

@@ -249,12 +249,18 @@ SYM_VARIANTS = {"mixed": (10, 11), "fp64": (3, 4, 5, 6)}
 
 def _f64_cross_term_bar(X, eps):
     """Bar of the FP64 symmetric forms whose exponent is contracted on the matrix cores (variants 5, 6): q =
-    c'(|x_i|^2 + |x_j|^2 - 2 x_i.x_j), c' = log2(e) / eps, summed over d + 2 terms on centred coordinates,
-    carries a rounding error of at most about (4d + 8) u max|x - mean|^2 |c'|, i.e. a relative error ln2 times
-    that in each kernel value; twice that bound, and never below the direct form's bar."""
+    c'(|x_i|^2 + |x_j|^2 - 2 x_i.x_j), c' = log2(e) / eps, on centred coordinates, carries a rounding error of at
+    most about k u max|x - mean|^2 |c'|: the norms 2(d + 1), the scaled source coordinates 2, and either
+    (padded width 4 mod 4: row norms as the contraction's accumulator input) d accumulation steps on partial
+    sums up to 3 |c'| max|x|^2 and a final addition of the source norm, 4, so k = 5d + 8, or (padded width
+    2 mod 4: both norms inside the contraction) d + 2 steps on partial sums up to 4 |c'| max|x|^2, so
+    k = 6d + 12; a relative error ln2 times that in each kernel value.  The bar is twice that bound, and never
+    below the direct form's."""
     d = X.shape[1]
+    width = next((w for w in (2, 3, 4, 6, 8, 16) if d <= w), d)   # the kernel's padded width (no such form above 16)
+    k = 6 * d + 12 if width % 4 == 2 else 5 * d + 8
     M = float(np.max(np.sum((X - X.mean(axis=0)) ** 2, axis=1)))
-    return max(TOL["fp64"], 2.0 * np.log(2.0) * (np.log2(np.e) / eps) * (4 * d + 8) * 2.0 ** -53 * M)
+    return max(TOL["fp64"], 2.0 * np.log(2.0) * (np.log2(np.e) / eps) * k * 2.0 ** -53 * M)
 
 
 @pytest.mark.gpu

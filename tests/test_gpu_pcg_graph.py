@@ -155,3 +155,26 @@ def test_graph_two_stage_reductions(gpu_lib, n, R, prec, rep):
           f"({g[3]['n_graph_cycles']} cycles)")
     _same(h, g)
     assert h[4] == 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec,rep", [("fp64", 0), ("mixed", 10)])
+def test_graph_active_set_shrinks(gpu_lib, small, prec, rep):
+    """Twenty columns, twelve at the larger beta: once columns converge the cycles' products form the active
+    columns only, in narrower staged blocks (20 columns stage as 32 in FP64 and in the mixed block form,
+    eight or fewer as 8 or 16).  The staging buffers keep their size, so the cycles captured after a column
+    set shrinks allocate nothing; the iterates stay bit-identical to the host loop's."""
+    wl, P = small
+    R = 20
+    rng = np.random.default_rng(17)
+    Y = np.sin(np.outer(wl.X[:, 0] + wl.X[:, 2], np.arange(1, R + 1))) + 0.05 * rng.standard_normal((wl.n, R))
+    betas = [1e-2] * 12 + [wl.betas[0]] * 8
+    h, g = _both(gpu_lib, torch.from_numpy(wl.X), torch.from_numpy(Y), wl.eps, betas, P, tol=1e-9, maxit=5000,
+                 replace_every=rep, prec=prec)
+    its = np.asarray(h[1])
+    print(f"{prec}: its {its.tolist()}; {g[3]['n_graph_cycles']} cycles, {g[3]['n_graph_iters']} iterations in "
+          f"cycles")
+    _same(h, g)
+    assert h[4] == 0
+    cycle = rep if rep else 16
+    assert its.max() - its.min() > 2 * cycle, "the active set should shrink well before the last column converges"
