@@ -390,12 +390,13 @@ bool kmv_uses_block(int prec, int d, int R, int deriv) {
 }
 
 int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square) {
-  // block MVM (measured at n = 5e5, d = 6): split-BF16 with two parts runs K = 32 contractions over
-  // 4 target fragments x 2 column groups (variant 7; the shared-tile form only ties it at R = 128); with
-  // three parts the exp/split work weighs more and the shared-tile form is 1.26x faster at R = 128 when at
-  // least 7/8 of its waves hold columns, else variant 7 (1.36x faster than variant 0)
+  // block MVM (measured at n = 5e5, d = 6): the shared-tile form (variant 12, each pair's exp/split once per
+  // 128 columns) against K = 32 contractions over 4 target fragments x 2 column groups (variant 7): with two
+  // parts (MIXED, three waves per SIMD) 316 against 348 ms at R = 128 on one machine, 321 against 324 ms
+  // (four products at n = 2.5e5) on another; with three parts (FP32) 1.26x faster;
+  // variant 12 when at least 7/8 of its waves hold columns (below, its idle waves cost more: 2.9x / 1.6x
+  // slower at R = 32 / 64), else variant 7 (1.36x faster than variant 0)
   if (rclass(prec, R) == 3) {
-    if (prec == KRR_MIXED) return 7;
     const int rb = (int)round_up(R, 32);
     return R >= 128 && 8 * rb >= 7 * 128 * (int)ceil_div(rb, 128) ? 12 : 7;
   }

@@ -90,9 +90,11 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(8, 1, "fp64", square=False)[1] is False
     assert krr.kmv_variant(3, 1, "fp64", square=True)[1] is False   # odd padded width: direct kernel
     assert krr.kmv_variant(8, 1, "fp32", square=True)[1] is False
-    # block products: two-part splits run variant 7; three-part splits run the shared-tile form (12) when
-    # at least 7/8 of its 32-column waves hold columns, else variant 7
-    assert krr.kmv_variant(6, 128, "mixed") == (7, False)
+    # block products run the shared-tile form (12) when at least 7/8 of its 32-column waves hold columns,
+    # else variant 7
+    assert krr.kmv_variant(6, 128, "mixed") == (12, False)
+    assert krr.kmv_variant(6, 64, "mixed") == (7, False)
+    assert krr.kmv_variant(6, 160, "mixed") == (7, False)
     assert krr.kmv_variant(6, 128, "fp32") == (12, False)
     assert krr.kmv_variant(6, 200, "fp32") == (12, False)    # 224 of 256 columns
     assert krr.kmv_variant(6, 160, "fp32") == (7, False)     # 160 of 256 columns
