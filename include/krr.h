@@ -167,6 +167,18 @@ int krr_fps(const double* X, int64_t n, int32_t d, int32_t k, int64_t start, int
             void* stream);
 
 /*
+ * Stable radix sort of (key, value) pairs by the key bits [0, end_bit), ascending; pairs whose bits are
+ * equal keep their input order.  The library orders the pivoted QR's candidate columns by norm with it
+ * (Algorithms 1-2, last steps) and the points of a culled operator by Morton code.
+ *   keys_in [dev] uint64 n, vals_in [dev] int64 n: inputs, not modified.
+ *   keys_out [dev] uint64 n, vals_out [dev] int64 n: outputs (keys with all their bits, reordered).
+ *   0 <= n < 2^31; 1 <= end_bit <= 64; the four arrays must not overlap.  Deterministic; allocates work
+ *   buffers of 2n + 131584 words through the registered allocator.
+ */
+int krr_radix_sort_pairs(const uint64_t* keys_in, uint64_t* keys_out, const int64_t* vals_in, int64_t* vals_out,
+                         int64_t n, int32_t end_bit, void* stream);
+
+/*
  * Rank for a target condition number on the data (Corollary tradeoff, Eq. condbound_gamma and
  * Eq. condbound): q_i are the side lengths of the bounding box of X (device reduction), h = sqrt(eps),
  *   gamma = (2/pi) sqrt(h^{-2} ln(Mbar n / (beta (xi - 1)))),   k = prod_i (floor(gamma q_i) + 1).

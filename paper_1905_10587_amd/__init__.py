@@ -27,7 +27,8 @@ import torch
 
 __all__ = ["load", "KRRError", "kernel_mv", "sketch", "qrcp", "Preconditioner", "pcg_solve", "grad",
            "KRRValLoss", "autotune", "autotune_save", "autotune_load", "set_variant", "num_variants", "kmv_variant",
-           "kmv_last_launch", "set_cull", "cull_stats", "set_pcg_mode", "PREC", "library_path"]
+           "kmv_last_launch", "set_cull", "cull_stats", "set_pcg_mode", "radix_sort_pairs", "fps", "rank_for_cond",
+           "PREC", "library_path"]
 
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 _STATUS = {0: "KRR_OK", -1: "KRR_EINVAL", -2: "KRR_ENOMEM", -3: "KRR_EHIP", -4: "KRR_ENOTSPD",
@@ -74,6 +75,7 @@ _SIGS = {
     "krr_build_precond_anchors": ([_vp, _i64, _i32, _f64, _vp, _i32, _vp, _i32, _i64, _f64, _i32,
                                    ctypes.POINTER(_vp), _vp], _i32),
     "krr_fps": ([_vp, _i64, _i32, _i32, _i64, _vp, _vp, _vp], _i32),
+    "krr_radix_sort_pairs": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
     "krr_rank_for_cond": ([_vp, _i64, _i32, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp], _i32),
     "krr_precond_info": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "krr_precond_get": ([_vp, _i32, _i32, _vp, _sz, _vp], _i32),
@@ -228,6 +230,19 @@ def fps(X, k: int, start: int = 0):
     dsel = torch.empty(int(k), dtype=torch.float64, device="cuda")
     _chk(lib, lib.krr_fps(_p(X), n, d, int(k), int(start), _p(S), _p(dsel), _stream()))
     return S, dsel
+
+
+def radix_sort_pairs(keys, vals, end_bit: int = 64):
+    """Stable device sort of (uint64 key, int64 value) pairs by key bits [0, end_bit): (keys, vals) sorted.
+    keys: a torch.int64 tensor holding the uint64 bit patterns; vals: torch.int64."""
+    lib = load()
+    keys = keys.to(device="cuda", dtype=torch.int64).contiguous()
+    vals = vals.to(device="cuda", dtype=torch.int64).contiguous()
+    if keys.shape != vals.shape or keys.dim() != 1:
+        raise ValueError("keys and vals must be 1-D tensors of one length")
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    _chk(lib, lib.krr_radix_sort_pairs(_p(keys), _p(ko), _p(vals), _p(vo), keys.numel(), int(end_bit), _stream()))
+    return ko, vo
 
 
 def rank_for_cond(X, eps: float, beta: float, xi: float, Mbar: Optional[float] = None):

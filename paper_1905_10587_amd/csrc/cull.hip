@@ -16,8 +16,8 @@
 
 #include "anchors.h"
 #include "kmv.h"
+#include "radix_sort.h"
 
-#include <hipcub/device/device_radix_sort.hpp>
 
 namespace krr {
 
@@ -153,12 +153,8 @@ void spatial_order(Staged& st, const double* X, const double* center, hipStream_
   hipLaunchKernelGGL(k_morton, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, X, n, d, lod.p, invd.p, b, code.p,
                      idx.p);
   KRR_LAUNCH_CHECK();
-  size_t tmp_bytes = 0;
-  KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, code.p, scode.p, idx.p, st.perm.p, (int)n, 0,
-                                                   b * d, s));
-  DevBuf<char> tmp(tmp_bytes, s);
-  KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, code.p, scode.p, idx.p, st.perm.p, (int)n, 0,
-                                                   b * d, s));
+  RadixSortWork rsw;
+  radix_sort_pairs(code.p, scode.p, idx.p, st.perm.p, n, b * d, rsw, s);
   const int64_t ng = st.npad / 16;
   st.box16.alloc((size_t)ng * 2 * dpad, s);
   hipLaunchKernelGGL(k_box16, dim3((unsigned)ceil_div(ng, 256)), dim3(256), 0, s, X, n, d, dpad,

@@ -12,11 +12,11 @@
 // (the residual norms are those of the trailing columns), without forming R or T (Sec. 2.3:
 // only the permutation is needed).
 #include <hip/hip_runtime.h>
-#include <hipcub/device/device_radix_sort.hpp>
 
 #include <cstdlib>
 
 #include "kmv_kernels.h"
+#include "radix_sort.h"
 #include "sketch_qrcp.h"
 
 namespace krr {
@@ -620,9 +620,8 @@ static void qrcp_cand(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t
   int* ok = flags.p;
   int* fail = flags.p + 1;
   KRR_CHECK_HIP(hipMemsetAsync(QT.p, 0, QT.bytes(), s));
-  size_t tmp_bytes = 0;
-  KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key.p, skey.p, idx.p, sidx.p, (int)N, 0, 64, s));
-  DevBuf<char> tmp(tmp_bytes, s);
+  RadixSortWork rsw;
+  rsw.reserve(N, s);
   // initial squared norms
   const dim3 g2((unsigned)nblk, (unsigned)nslab);
   hipLaunchKernelGGL((k_qr_slab<T, 1>), g2, dim3(kQrBlock), 0, s, Yt, ldy, N, l, slab, (const double*)nullptr,
@@ -641,7 +640,7 @@ static void qrcp_cand(const T* Yt, int64_t ldy, int64_t N, int l, int k, int64_t
     hipLaunchKernelGGL(k_qr_keys, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, s, (const double*)nrm2.p, N,
                        key.p, idx.p);
     KRR_LAUNCH_CHECK();
-    KRR_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, key.p, skey.p, idx.p, sidx.p, (int)N, 0, 64, s));
+    radix_sort_pairs(key.p, skey.p, idx.p, sidx.p, N, 64, rsw, s);
     hipLaunchKernelGGL(k_qr_gather<T>, dim3((unsigned)Tc), dim3(256), 0, s, Yt, ldy, l, (const int64_t*)sidx.p,
                        (const uint64_t*)skey.p, N, Tc, (const double*)nrm2.p, cidx.p, cnrm.p, Yc.p, tau.p);
     hipLaunchKernelGGL(k_qr_reset_ok, dim3(1), dim3(1), 0, s, ok);

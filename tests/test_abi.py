@@ -52,6 +52,11 @@ def test_host_validation_without_gpu(lib):
     assert st == -1 and b"eps" in lib.krr_last_error()
     st = lib.krr_kernel_mv(None, 10, None, 10, 0, 1.0, None, 1, None, 0, 0, None, None)
     assert st == -1 and b"d must" in lib.krr_last_error()
+    lib.krr_radix_sort_pairs.restype = ctypes.c_int
+    lib.krr_radix_sort_pairs.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
+    st = lib.krr_radix_sort_pairs(None, None, None, None, 5, 64, None)
+    assert st == -1 and b"null pointer" in lib.krr_last_error()
+    assert lib.krr_radix_sort_pairs(None, None, None, None, 0, 64, None) == 0   # nothing to sort
     lib.krr_version.restype = ctypes.c_int
     assert lib.krr_version() >= 10000
 
