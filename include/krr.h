@@ -257,20 +257,6 @@ typedef struct {
 } krr_solve_stats;
 
 /*
- * PCG on (K + beta_r I) alpha_r = y_r for R right-hand sides in lockstep (Algorithm 5):
- * one shared kernel MVM of the whole block per iteration, per-column FP64 scalars, converged
- * columns frozen.  Stops a column when its true relative residual
- * ||y - (K + beta I) alpha||_2 / ||y||_2 <= tol (checked with the FP64 operator).
- *
- *   X [dev] n x d;  Yrhs [dev] n x R;  betas [host] R values (each one of P's betas when P
- *   is given);  P: preconditioner or NULL (plain CG);  replace_every: every that many
- *   iterations the recursive residual is replaced by the FP64 true residual (0: never);
- *   alpha [dev] n x R: in = initial guess x0 (zeros for a cold start), out = solution;
- *   iters [host] R, relres [host] R: per-column iteration counts and final true relative
- *   residuals;  stats [host] optional (NULL);  timing != 0 records HIP-event phase times.
- *   Returns KRR_ENOCONV if some column did not reach tol within maxit.
- */
-/*
  * Driver of krr_pcg_solve (process-wide; Algorithm 5's loop).  Both drivers launch the same kernels in the
  * same order and return bit-identical iterates, iteration counts and residuals:
  *   0: host loop, one host synchronisation per iteration (the next iteration's preconditioner apply and
@@ -287,6 +273,21 @@ typedef struct {
  */
 int krr_set_pcg_mode(int32_t mode);
 
+/*
+ * PCG on (K + beta_r I) alpha_r = y_r for R right-hand sides in lockstep (Algorithm 5):
+ * one shared kernel MVM of the whole block per iteration, per-column FP64 scalars, converged
+ * columns frozen; once columns converge, the products are formed for the active columns only.  Stops a
+ * column when its true relative residual ||y - (K + beta I) alpha||_2 / ||y||_2 <= tol (checked with the
+ * FP64 operator).
+ *
+ *   X [dev] n x d;  Yrhs [dev] n x R;  betas [host] R values (each one of P's betas when P
+ *   is given);  P: preconditioner or NULL (plain CG);  replace_every: every that many
+ *   iterations the recursive residual is replaced by the FP64 true residual (0: never);
+ *   alpha [dev] n x R: in = initial guess x0 (zeros for a cold start), out = solution;
+ *   iters [host] R, relres [host] R: per-column iteration counts and final true relative
+ *   residuals;  stats [host] optional (NULL);  timing != 0 records HIP-event phase times.
+ *   Returns KRR_ENOCONV if some column did not reach tol within maxit.
+ */
 int krr_pcg_solve(const double* X, int64_t n, int32_t d, double eps,
                   const double* Yrhs, int32_t R, const double* betas,
                   const krr_precond* P, double tol, int32_t maxit, int32_t replace_every,
