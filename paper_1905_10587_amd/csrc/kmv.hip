@@ -352,11 +352,24 @@ std::string device_arch() {
 
 KmvLaunchInfo kmv_last_launch() { return t_last; }
 
+// The shared-tile block forms (variants 12, 13) cover 128 columns per block in 32-column waves; with fewer
+// than 7/8 of those waves holding columns the idle ones cost more than the shared exp/split saves.
+static bool shared_block_fits(int R) {
+  const int rb = (int)round_up(R, 32);
+  return R >= 128 && 8 * rb >= 7 * 128 * (int)ceil_div(rb, 128);
+}
+
 KmvChoice kmv_lookup(int prec, int d, int R, int64_t n, bool square) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (n > 0) {
     auto it = g_table.find(exact_key(d, R, prec, n, square));
-    if (it != g_table.end()) return it->second;
+    if (it != g_table.end()) {
+      // a tuned entry covers every column count of its shape class: a shared-tile block form tuned at a
+      // full count gives way to the per-wave form (variant 7) where its waves would idle, e.g. when a
+      // block solve's active columns shrink (forced variants are taken as they are)
+      if (rclass(prec, R) == 3 && it->second.variant >= 12 && !shared_block_fits(R)) return KmvChoice{7, 0};
+      return it->second;
+    }
   }
   auto it = g_table.find(vkey(d, R, prec));
   return it == g_table.end() ? KmvChoice{} : it->second;
@@ -396,10 +409,7 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
   // (four products at n = 2.5e5) on another; with three parts (FP32) 1.26x faster;
   // variant 12 when at least 7/8 of its waves hold columns (below, its idle waves cost more: 2.9x / 1.6x
   // slower at R = 32 / 64), else variant 7 (1.36x faster than variant 0)
-  if (rclass(prec, R) == 3) {
-    const int rb = (int)round_up(R, 32);
-    return R >= 128 && 8 * rb >= 7 * 128 * (int)ceil_div(rb, 128) ? 12 : 7;
-  }
+  if (rclass(prec, R) == 3) return shared_block_fits(R) ? 12 : 7;
   if (prec == KRR_MIXED) {
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)

@@ -140,6 +140,18 @@ def test_launch_table_size_classes(lib, tmp_path):
     assert krr.kmv_variant(4, 1, "mixed", square=False, n=70_000) == (8, False)
     krr.set_variant(4, 1, "mixed", -1)
     assert krr.kmv_variant(4, 1, "mixed", square=True, n=1_000_000) == (11, True)
+    # a tuned shared-tile block entry (variant 12) holds where its 32-column waves are full; with fewer
+    # columns of the same shape class (a block solve's shrinking active set) the per-wave form runs
+    f.write_text('{"arch": "", "entries": {"2:6:3:18:1": [12, 0]}}')
+    krr.autotune_load(str(f))
+    assert krr.kmv_variant(6, 128, "mixed", square=True, n=500_000) == (12, False)
+    assert krr.kmv_variant(6, 256, "mixed", square=True, n=500_000) == (12, False)
+    assert krr.kmv_variant(6, 96, "mixed", square=True, n=500_000) == (7, False)
+    assert krr.kmv_variant(6, 64, "mixed", square=True, n=500_000) == (7, False)
+    assert krr.kmv_variant(6, 160, "mixed", square=True, n=500_000) == (7, False)   # 5 of 8 waves
+    krr.set_variant(6, 64, "mixed", 12)                                                # forced: as given
+    assert krr.kmv_variant(6, 64, "mixed", square=True, n=500_000) == (12, False)
+    krr.set_variant(6, 64, "mixed", -1)
     f.write_text('{"arch": "", "entries": {"2:4:1:19": [9, 0]}}')                     # malformed key
     with pytest.raises(krr.KRRError):
         krr.autotune_load(str(f))
