@@ -1030,7 +1030,8 @@ __global__ __launch_bounds__(256) void k_kmv_mixed_lds(const uint4* __restrict__
 // partials per row in a fixed order.  Inside a block the pipelined LDS-staged tile loop of
 // k_kmv_mixed_lds runs once per target tile of 64 NF points; each lane's column partial for one step (its
 // source, over its 4 NF targets: FP32 over NF x 4 products) goes to LDS, and at the end of each source
-// tile the 16 partials of a source (4 waves x 4 lane groups) are added in FP64 in a fixed order.
+// tile the 16 partials of a source (4 waves x 4 lane groups) are added pairwise in FP32 and the sum is
+// added to the source's FP64 slot.  Row sums are folded from FP32 into FP64 every 512 sources.
 // Items are laid out so that each XCD (blocks b = x mod 8) walks a contiguous run of the triangle in
 // column order.
 //
@@ -1052,8 +1053,9 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
   // sources per LDS tile (two tiles, the column partials and the weights fit twice per CU)
   constexpr int TS = NCH == 1 ? 256 : (NCH == 2 ? 128 : 64);
   constexpr int SPT = TS / 16;
-  constexpr int TPF = 256 / TS;              // tiles per FP64 fold of the row sums (every 256 sources)
+  constexpr int TPF = 512 / TS;              // tiles per FP64 fold of the row sums (every 512 sources)
   constexpr int NI = (TS * RS + 63) / 64;
+  constexpr int NQ = (NI + 3) / 4;           // staging loads per wave and tile (wave w issues i = w, w + 4, ...)
   constexpr int SBU = NI * 64 + 16 * RS;
   constexpr int TM = 64 * NF;                // targets per target tile (4 waves x 16 NF)
   constexpr int VPER = 8 / NCH;
@@ -1078,7 +1080,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15;
   const int kq = lane >> 4;
   const int64_t t0 = (int64_t)r * E, t1 = t0 + E < npad ? t0 + E : npad;
@@ -1091,13 +1093,28 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
   double acc[NF][4];
   float a32[NF][4];
 
+  // LDS slot i * 64 + lane of a tile holds chunk u of source rr, slot = RS rr + u (rows padded to RS chunks;
+  // the pad chunk loads chunk 0 of its row and the slots past the tile chunk 0 of the tile's first source,
+  // neither of which is read).  Wave w stages slots tid + 256 q (i = w + 4 q), so (rr, u) advance by
+  // (256 / RS, 256 % RS) per load instead of being divided out again.
   auto issue = [&](uint4* dst, int64_t j0) {
-    for (int i = wave; i < NI; i += 4) {
-      const int slot = i * 64 + lane;
-      int rr = slot / RS, u = slot - rr * RS;
-      if (u == KV) u = 0;
-      if (rr >= TS) { rr = 0; u = 0; }
-      __builtin_amdgcn_global_load_lds(B + (j0 + rr) * KV + u, dst + i * 64, 16, 0, 0);
+    const uint4* src = B + j0 * KV;
+    int t = tid;
+    asm volatile("" : "+v"(t));   // recomputed per tile rather than held in registers across the tile loop
+    int rr = t / RS, u = t - rr * RS;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = wave + 4 * q;
+      if (i < NI) {
+        const int uu = u == KV ? 0 : u;
+        __builtin_amdgcn_global_load_lds(src + (rr < TS ? rr * KV + uu : 0), dst + i * 64, 16, 0, 0);
+      }
+      rr += 256 / RS;
+      u += 256 % RS;
+      if (u >= RS) {
+        u -= RS;
+        ++rr;
+      }
     }
   };
   auto vload = [&](int64_t j0) -> float { return tid < TS ? v[(j0 + tid) * Rp] : kZero; };
@@ -1239,10 +1256,11 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
       __syncthreads();
       if (COL && tid < TS) {
         float (*cb)[TS] = odd ? cb1 : cb0;
-        double cs = 0.0;
+        float h[8];
 #pragma unroll
-        for (int g = 0; g < 16; ++g) cs += (double)cb[g][tid];
-        *dst = prev + cs;
+        for (int g = 0; g < 8; ++g) h[g] = cb[2 * g][tid] + cb[2 * g + 1][tid];
+        const float cs = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+        *dst = prev + (double)cs;
       }
       if (t == ntile - 1) {   // row sums of this target tile -> part[c][rows]
         double* prow = part + (int64_t)c * npad + row0 + kq * 4;
