@@ -1134,7 +1134,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
     for (int ch = 0; ch < NCH; ++ch) q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ch], b[ch], q0, 0, 0, 0);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][ch], b[ch], q1, 0, 0, 0);
-#pragma unroll 1
+#pragma unroll 2
     for (int st = 0; st < SPT; ++st) {
       const int rn = (st + 1) * 16 + r16;
 #pragma unroll
