@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) bn[ch] = __builtin_bit_cast(bf16x8, sb[rn * RS + ch * 4 + kq]);
       const float vn = sv[rn];
-      float cs[4] = {0.f, 0.f, 0.f, 0.f};
+      float cs = 0.f;   // one chain over the NF x 4 targets (dependent FMAs issue back to back)
       const bool skip = SKIP && ((sk >> st) & 1u);
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
@@ -1160,7 +1160,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
           for (int e = 0; e < 4; ++e) {
             const float ex = __builtin_amdgcn_exp2f(q0[e]);
             a32[f][e] = __builtin_fmaf(ex, vj, a32[f][e]);
-            if (COL) cs[e] = __builtin_fmaf(ex, vt[f][e], cs[e]);
+            if (COL) cs = __builtin_fmaf(ex, vt[f][e], cs);
           }
         }
         q0 = q1;
@@ -1172,7 +1172,7 @@ __global__ __launch_bounds__(256, 2) void k_kmv_mixed_sym(const uint4* __restric
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (COL) cb[wave * 4 + kq][st * 16 + r16] = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+      if (COL) cb[wave * 4 + kq][st * 16 + r16] = cs;
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) b[ch] = bn[ch];
       vj = vn;
