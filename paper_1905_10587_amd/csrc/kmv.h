@@ -20,6 +20,10 @@ struct Staged {
   int prec = KRR_FP64;
   double eps = 0;
   DevBuf<double> x64;
+  // FP64 staging: every pair's base-2 exponent -log2(e) |x_i - x_j|^2 / eps is provably >= -1020 (the box
+  // of the points gives log2(e) diag^2 / eps <= 1000 and log2(e) max|x|^2 / eps <= 1e10, so the rounding of
+  // the matrix-core form's norms cannot take it past that), and the FP64 exp2 runs without its clamp
+  bool q_floor = false;
   DevBuf<float> x32;
   DevBuf<uint16_t> sa, sb;
   DevBuf<double> center;   // dpad

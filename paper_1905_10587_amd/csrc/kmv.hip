@@ -17,6 +17,7 @@
 // FP64) that evaluate each pair once for both of its rows.
 // Sources are split across the grid's y dimension; every block writes FP64 partial sums which a
 // finishing kernel adds in a fixed order (deterministic), together with the ridge term.
+#include "anchors.h"
 #include "kmv.h"
 #include "kmv_dispatch.h"
 
@@ -73,13 +74,15 @@ void point_mean(const double* X, int64_t n, int d, int dpad, double* center, hip
   }
 }
 
+// FP64 copy, translated by center when given (the kernel is translation invariant; centred coordinates keep
+// the norms, and so the cancellation of the matrix-core form, small)
 __global__ void k_stage_f64(const double* __restrict__ X, int64_t n, int d, int64_t npad, int dpad,
-                            double* __restrict__ out) {
+                            const double* __restrict__ center, double* __restrict__ out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npad * dpad) return;
   int64_t i = idx / dpad;
   int k = (int)(idx % dpad);
-  out[idx] = (i < n && k < d) ? X[i * d + k] : 0.0;
+  out[idx] = (i < n && k < d) ? X[i * d + k] - (center ? center[k] : 0.0) : 0.0;
 }
 
 __global__ void k_stage_f32(const double* __restrict__ X, int64_t n, int d, int64_t npad, int dpad,
@@ -165,9 +168,21 @@ void stage_points(Staged& st, const double* X, int64_t n, int d, double eps, int
   const int blk = 256;
   if (prec == KRR_FP64) {
     st.x64.alloc(tot, s);
-    hipLaunchKernelGGL(k_stage_f64, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad,
+    hipLaunchKernelGGL(k_stage_f64, dim3(ceil_div(tot, blk)), dim3(blk), 0, s, X, n, d, st.npad, st.dpad, center,
                        st.x64.p);
     KRR_LAUNCH_CHECK();
+    // the box of the points bounds every squared distance by diag2 and the staged squared norms by max2
+    std::vector<double> lo(d), hi(d), ctr(d, 0.0);
+    if (center) KRR_CHECK_HIP(hipMemcpyAsync(ctr.data(), center, sizeof(double) * d, hipMemcpyDeviceToHost, s));
+    bounding_box(X, n, d, lo.data(), hi.data(), s);   // synchronises the stream
+    double diag2 = 0.0, max2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+      diag2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+      const double a = lo[k] - ctr[k], b = hi[k] - ctr[k];
+      max2 += std::max(a * a, b * b);
+    }
+    const double c = kLog2e / eps;
+    st.q_floor = c * diag2 <= 1000.0 && c * max2 <= 1e10;
   } else {
     if (prec == KRR_FP32) {
       st.x32.alloc(tot, s);
@@ -695,7 +710,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     if (block)
       return launch_kmv_block(T.ka / 32, NT, NRC, prec == KRR_MIXED ? 3 : 6, k32, g, T.sa.p, S.sb.p, V.vh.p,
                               V.vm.p, prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);
-    if (f64sm) return launch_kmv_f64_symm(D, NF, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
+    if (f64sm) return launch_kmv_f64_symm(D, NF, !T.q_floor, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64 && sym) return launch_kmv_f64_sym(D, TM, g, T.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (f64m) return launch_kmv_f64_mfma(D, NRG, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);
     if (prec == KRR_FP64) return launch_kmv_f64(D, TM, RC, DV, g, T.x64.p, S.x64.p, V.v64.p, -kLog2e / T.eps, part.p, s);

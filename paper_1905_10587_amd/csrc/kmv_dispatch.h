@@ -27,8 +27,9 @@ bool launch_kmv_f64(int D, int TM, int RC, int DV, const KmvGrid& g, const doubl
 // Symmetric FP64 square product of one column (D in {2, 4, 6, 8, 16}, TM in {2, 4}).
 bool launch_kmv_f64_sym(int D, int TM, const KmvGrid& g, const double* x, const double* v, double neg_c,
                         double* part, hipStream_t s);
-// The same with the cross term on the FP64 matrix cores (NFR in {2, 4}: 64 NFR targets per target tile).
-bool launch_kmv_f64_symm(int D, int NFR, const KmvGrid& g, const double* x, const double* v, double neg_c,
+// The same with the cross term on the FP64 matrix cores (NFR in {2, 4}: 64 NFR targets per target tile);
+// clamp false only when every pair's base-2 exponent is known to be >= -1020 (Staged::q_floor).
+bool launch_kmv_f64_symm(int D, int NFR, bool clamp, const KmvGrid& g, const double* x, const double* v, double neg_c,
                          double* part, hipStream_t s);
 bool kmv_f64_has_sym(int D);
 // FP64 many-column product on the FP64 matrix cores: D <= 16 (instantiated D), NRG in {1, 2, 4, 8} groups

@@ -65,22 +65,24 @@ bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, con
   return false;
 }
 
-template <int D, int NFR>
+template <int D, int NFR, bool CLAMP>
 static void go64sm(const KmvGrid& g, const double* x, const double* v, double neg_c, double* part, hipStream_t s) {
   if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_symm<D, NFR>, 256, 0));
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_symm<D, NFR, CLAMP>, 256, 0));
     return;
   }
-  hipLaunchKernelGGL((k_kmv_f64_symm<D, NFR>), g.grid, dim3(256), 0, s, x, v, g.Rp, neg_c, g.E, g.NS, g.mpad, part,
-                     g.Rout);
+  hipLaunchKernelGGL((k_kmv_f64_symm<D, NFR, CLAMP>), g.grid, dim3(256), 0, s, x, v, g.Rp, neg_c, g.E, g.NS, g.mpad,
+                     part, g.Rout);
 }
 
-bool launch_kmv_f64_symm(int D, int NFR, const KmvGrid& g, const double* x, const double* v, double neg_c,
-                         double* part, hipStream_t s) {
-#define KRR_SM64(DD)                                                               \
-  if (D == DD) {                                                                   \
-    if (NFR == 2) { go64sm<DD, 2>(g, x, v, neg_c, part, s); return true; }         \
-    if (NFR == 4) { go64sm<DD, 4>(g, x, v, neg_c, part, s); return true; }         \
+bool launch_kmv_f64_symm(int D, int NFR, bool clamp, const KmvGrid& g, const double* x, const double* v,
+                         double neg_c, double* part, hipStream_t s) {
+#define KRR_SM64(DD)                                                                                 \
+  if (D == DD) {                                                                                     \
+    if (NFR == 2) { clamp ? go64sm<DD, 2, true>(g, x, v, neg_c, part, s)                             \
+                          : go64sm<DD, 2, false>(g, x, v, neg_c, part, s); return true; }            \
+    if (NFR == 4) { clamp ? go64sm<DD, 4, true>(g, x, v, neg_c, part, s)                             \
+                          : go64sm<DD, 4, false>(g, x, v, neg_c, part, s); return true; }            \
   }
   KRR_SM64(2) KRR_SM64(4) KRR_SM64(6) KRR_SM64(8) KRR_SM64(16)
 #undef KRR_SM64

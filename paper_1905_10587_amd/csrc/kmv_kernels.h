@@ -14,10 +14,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------------ FP64 2^q, q <= 0
 // 2^q = 2^n * 2^f with n = rint(q) and f = q - n (exact, |f| <= 1/2); 2^f by a degree-10
 // near-minimax polynomial (Chebyshev fit in 50-digit arithmetic, coefficients rounded to double;
-// worst relative error 3.1e-16 on [-1/2, 1/2]; derived by gen_exp2_poly.py).  q is clamped at
-// -1020 so ldexp stays in the normal range: values below 2^-1020 come out as ~1e-307 instead of 0.
+// worst relative error 3.1e-16 on [-1/2, 1/2]; derived by gen_exp2_poly.py).  CLAMP: q is clamped at
+// -1020 so ldexp stays in the normal range and a q of -inf cannot give NaN; values below 2^-1020 come out
+// as ~1e-307 instead of 0.  Without it (for callers that know q >= -1020 and finite) one operation less.
+template <bool CLAMP = true>
 __device__ __forceinline__ double exp2_neg_f64(double q) {
-  q = q > -1020.0 ? q : -1020.0;
+  if (CLAMP) q = q > -1020.0 ? q : -1020.0;
   const double n = __builtin_rint(q);
   const double f = q - n;
   double p = 0x1.e6063f7217bc6p-28;
@@ -317,7 +319,9 @@ __global__ __launch_bounds__(256) void k_kmv_f64_sym(const double* __restrict__ 
 // MFMA step.
 // Lane l holds the pairs (target 4e + l/16 of a fragment, source l%16 of the step), e = 0..3: its row sums
 // are added over the 16 lanes of its group at the end, its column sums over the four groups every step.
-template <int D, int NFR>
+// CLAMP false: the caller guarantees q >= -1020 for every pair (c'|x_i - x_j|^2 bounded by the points' box),
+// so the exp2 needs no clamp.
+template <int D, int NFR, bool CLAMP>
 __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__ X, const double* __restrict__ v,
                                                       int Rp, double neg_c, int E, int NS, int64_t npad,
                                                       double* __restrict__ part, int Rout) {
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_symm(const double* __restrict__
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const double q = FOLD ? C[f][e] : C[f][e] + bn;
-              const double kv = exp2_neg_f64(q);
+              const double kv = exp2_neg_f64<CLAMP>(q);
               acc[f][e] = __builtin_fma(kv, vj, acc[f][e]);
               if (COL) cs = __builtin_fma(kv, vt[f][e], cs);
             }

@@ -344,3 +344,29 @@ def test_fp64_many_columns(gpu_lib, R, d):
         err = _scaled_err(U, ref, scale)
         print(f"fp64 R={R} d={d} square={same}: max scaled error {err:.2e}", flush=True)
         assert err <= TOL["fp64"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eps", [0.05, 1e-3, 1e-5], ids=["exponent_bounded", "exponent_unbounded", "isolated"])
+def test_fp64_cross_term_form_exp_clamp(gpu_lib, eps):
+    """The FP64 matrix-core symmetric form runs its exp2 without the clamp at -1020 only when the points' box
+    bounds every exponent log2(e) |x_i - x_j|^2 / eps by 1000 (eps = 0.05 in the unit 4-cube: at most 115);
+    with eps = 1e-3 (exponents down to -5771: far pairs underflow, the oracle's values are exactly zero) and
+    1e-5 (most points isolated: their products are v_i itself) the clamped exp2 runs.  All against the oracle
+    within the cancellation bar, finite everywhere."""
+    n, d = 2500, 4
+    rng = np.random.default_rng(97)
+    X = rng.random((n, d))
+    v = rng.standard_normal(n)
+    K = ok.kernel_matrix(X, X, eps)
+    ref, scale = K @ v, K @ np.abs(v)
+    bar = _f64_cross_term_bar(X, eps)
+    try:
+        gpu_lib.set_variant(d, 1, "fp64", 5)
+        U = gpu_lib.kernel_mv(torch.from_numpy(X), None, eps, torch.from_numpy(v), prec="fp64").cpu().numpy()
+    finally:
+        gpu_lib.set_variant(d, 1, "fp64", -1)
+    err = _scaled_err(U, ref, scale)
+    print(f"fp64 variant 5 eps={eps}: max scaled error {err:.2e} (bar {bar:.1e})", flush=True)
+    assert np.all(np.isfinite(U))
+    assert err <= bar
