@@ -142,6 +142,36 @@ def _chk(lib, status):
     return status
 
 
+def _tensor(t):
+    return t if isinstance(t, torch.Tensor) else torch.as_tensor(t)
+
+
+def _need(cond, msg):
+    """Shape checks of the binding: the C ABI takes plain pointers and sizes and cannot see a buffer's extent,
+    so a mismatched shape would make the library read or write past it."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _points(X, name="X", d=None):
+    X = _tensor(X)
+    _need(X.dim() == 2 and X.shape[0] >= 1 and X.shape[1] >= 1, f"{name} must be a non-empty n x d matrix")
+    _need(d is None or X.shape[1] == d, f"{name} has {X.shape[1]} columns, expected d = {d}")
+    return X
+
+
+def _rows(V, n, name):
+    V = _tensor(V)
+    _need(V.dim() in (1, 2) and V.shape[0] == n, f"{name} must have {n} rows (got shape {tuple(V.shape)})")
+    return V
+
+
+def _betas(betas, R):
+    betas = [float(betas)] * R if isinstance(betas, (int, float)) else [float(b) for b in betas]
+    _need(len(betas) == R, f"{R} columns need {R} betas (got {len(betas)})")
+    return betas
+
+
 def _dev(t, dtype=torch.float64):
     if not isinstance(t, torch.Tensor):
         t = torch.as_tensor(t)
@@ -171,6 +201,10 @@ def _prec(prec):
 def kernel_mv(Xt, Xs, eps: float, V, shift=None, deriv: int = 0, prec="fp64"):
     """U = K(Xt, Xs) V (+ shift * V); deriv=1: K' V, deriv=2: [K V, K' V] (m x 2R)."""
     lib = load()
+    Xt = _points(Xt, "Xt")
+    Xs = None if Xs is None else _points(Xs, "Xs", Xt.shape[1])
+    V = _rows(V, Xt.shape[0] if Xs is None else Xs.shape[0], "V")
+    shift = None if shift is None else _betas(shift, 1 if V.dim() == 1 else V.shape[1])
     Xt, Xs = _dev(Xt), (None if Xs is None else _dev(Xs))
     same = Xs is None
     if same:
@@ -185,7 +219,7 @@ def kernel_mv(Xt, Xs, eps: float, V, shift=None, deriv: int = 0, prec="fp64"):
     U = torch.empty((m, cols), dtype=torch.float64, device=Xt.device)
     sh = None
     if shift is not None:
-        sh, _ = _host_f64([shift] * R if isinstance(shift, (int, float)) else shift)
+        sh, _ = _host_f64(shift)
     _chk(lib, lib.krr_kernel_mv(_p(Xt), m, _p(Xs), n, d, float(eps), _p(V2), R, sh, deriv, _prec(prec), _p(U),
                                 _stream()))
     if vec and deriv != 2:
@@ -196,8 +230,10 @@ def kernel_mv(Xt, Xs, eps: float, V, shift=None, deriv: int = 0, prec="fp64"):
 def sketch(X, eps: float, omega=None, idx=None, sign=None, prec="fp64"):
     """Algorithm 1 (omega: n x l Gaussian) or Algorithm 2 (idx/sign: l x r) sketch Y (n x l)."""
     lib = load()
-    X = _dev(X)
+    X = _points(X)
     n, d = X.shape
+    _check_draws(n, omega, idx, sign)
+    X = _dev(X)
     if omega is not None:
         omega = _dev(omega)
         l, r = omega.shape[1], 0
@@ -210,10 +246,23 @@ def sketch(X, eps: float, omega=None, idx=None, sign=None, prec="fp64"):
     return Y
 
 
+def _check_draws(n, omega, idx, sign, l=None):
+    """Shapes of the sketch randomness: omega n x l, or idx and sign both l x r."""
+    if omega is not None:
+        omega = _tensor(omega)
+        _need(omega.dim() == 2 and omega.shape[0] == n, f"omega must be n x l with n = {n}")
+        _need(l is None or omega.shape[1] == l, f"omega must have l = {l} columns")
+        return
+    _need(idx is not None and sign is not None, "give omega, or idx and sign")
+    idx, sign = _tensor(idx), _tensor(sign)
+    _need(idx.dim() == 2 and tuple(sign.shape) == tuple(idx.shape), "idx and sign must both be l x r")
+    _need(l is None or idx.shape[0] == l, f"idx and sign must have l = {l} rows")
+
+
 def qrcp(Y, k: int, prec="fp64"):
     """First k pivots of the column-pivoted QR of Y^T (Y is n x l). Returns (piv int64 k, rdiag k)."""
     lib = load()
-    Y = _dev(Y)
+    Y = _dev(_points(Y, "Y"))
     n, l = Y.shape
     piv = torch.empty(k, dtype=torch.int64, device=Y.device)
     rdiag = torch.empty(k, dtype=torch.float64, device=Y.device)
@@ -224,7 +273,7 @@ def qrcp(Y, k: int, prec="fp64"):
 def fps(X, k: int, start: int = 0):
     """Farthest point sampling on the device: (S int64 k, dsel float64 k), dsel[0] = inf."""
     lib = load()
-    X = _dev(X)
+    X = _dev(_points(X))
     n, d = X.shape
     S = torch.empty(int(k), dtype=torch.int64, device="cuda")
     dsel = torch.empty(int(k), dtype=torch.float64, device="cuda")
@@ -248,7 +297,7 @@ def radix_sort_pairs(keys, vals, end_bit: int = 64):
 def rank_for_cond(X, eps: float, beta: float, xi: float, Mbar: Optional[float] = None):
     """Corollary tradeoff on the data: (gamma, k bound as a float, bounding-box side lengths q)."""
     lib = load()
-    X = _dev(X)
+    X = _dev(_points(X))
     n, d = X.shape
     g, kb = ctypes.c_double(), ctypes.c_double()
     q = (ctypes.c_double * d)()
@@ -271,15 +320,18 @@ class Preconditioner:
         (random sampling: the caller draws them)."""
         lib = load()
         self._lib = lib
-        X = _dev(X)
+        self._h = None
+        X = _points(X)
         self.n, self.d = X.shape
+        if anchors is None and l is not None:
+            _check_draws(self.n, omega, idx, sign, int(l))
+        X = _dev(X)
         self.eps = float(eps)
         self.betas = [float(b) for b in betas]
         self.k = int(k)
         self.prec = _prec(prec)
         bh, nb = _host_f64(self.betas)
         h = ctypes.c_void_p()
-        self._h = None
         if anchors is not None:
             self.l = 0
             S = None if isinstance(anchors, str) and anchors == "fps" else _dev(anchors, torch.int64)
@@ -337,11 +389,11 @@ class Preconditioner:
         return out
 
     def apply(self, x, betas=None, prec=None):
-        x = _dev(x)
+        x = _dev(_rows(x, self.n, "x"))
         vec = x.dim() == 1
         x2 = x.reshape(x.shape[0], -1)
         R = x2.shape[1]
-        betas = [self.betas[0]] * R if betas is None else betas
+        betas = [self.betas[0]] * R if betas is None else _betas(betas, R)
         bh, _ = _host_f64(betas)
         out = torch.empty_like(x2)
         _chk(self._lib, self._lib.krr_precond_apply(self._h, _p(x2), R, bh,
@@ -353,13 +405,14 @@ class Preconditioner:
         """The Woodbury apply into the caller's `out` (n or n x R FP64 on the device, same shape as x) through
         krr_precond_apply_noalloc: the library allocates nothing (its scratch is a fixed device array)."""
         vec = x.dim() == 1
+        _rows(x, self.n, "x")
         x2 = x.reshape(x.shape[0], -1)
         R = x2.shape[1]
         if x2.dtype != torch.float64 or not x2.is_cuda or not x2.is_contiguous():
             raise ValueError("x must be a contiguous FP64 device tensor")
         if out.shape != x.shape or out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
             raise ValueError("out must be a contiguous FP64 device tensor shaped like x")
-        betas = [self.betas[0]] * R if betas is None else betas
+        betas = [self.betas[0]] * R if betas is None else _betas(betas, R)
         bh, _ = _host_f64(betas)
         _chk(self._lib, self._lib.krr_precond_apply_noalloc(self._h, _p(x2), R, bh,
                                                             self.prec if prec is None else _prec(prec), _p(out),
@@ -380,12 +433,16 @@ def pcg_solve(X, Y, eps: float, betas, P: Optional[Preconditioner] = None, *, to
               replace_every=0, prec="fp64", x0=None, timing=False):
     """Algorithm 5 for R right-hand sides. Returns (alpha, iters list, relres list, stats dict, status)."""
     lib = load()
+    X = _points(X)
+    n, d = X.shape
+    Y = _rows(Y, n, "Y")
+    R = 1 if Y.dim() == 1 else Y.shape[1]
+    _need(x0 is None or _tensor(x0).numel() == n * R, f"x0 must hold n x R = {n} x {R} values")
+    _need(P is None or (P.n, P.d) == (n, d), "the preconditioner was built for another point set")
+    betas = _betas(betas, R)
     X, Y = _dev(X), _dev(Y)
     vec = Y.dim() == 1
     Y2 = Y.reshape(Y.shape[0], -1)
-    n, d = X.shape
-    R = Y2.shape[1]
-    betas = [float(betas)] * R if isinstance(betas, (int, float)) else [float(b) for b in betas]
     bh, _ = _host_f64(betas)
     alpha = torch.zeros_like(Y2) if x0 is None else _dev(x0).reshape(n, R).clone()
     iters = (ctypes.c_int32 * R)()
@@ -406,9 +463,14 @@ def grad(Xtr, ytr, Xval, yval, eps: float, beta: float, P: Optional[Precondition
     loss and gradients come from unconverged iterates); errors raise KRRError.  With return_stats, a
     seventh element: the forward and adjoint solves' statistics (two dicts)."""
     lib = load()
-    Xtr, ytr, Xval, yval = _dev(Xtr), _dev(ytr), _dev(Xval), _dev(yval)
+    Xtr = _points(Xtr, "Xtr")
     n, d = Xtr.shape
+    Xval = _points(Xval, "Xval", d)
     m = Xval.shape[0]
+    _need(_tensor(ytr).numel() == n, f"ytr must hold n = {n} values")
+    _need(_tensor(yval).numel() == m, f"yval must hold m = {m} values")
+    _need(P is None or (P.n, P.d) == (n, d), "the preconditioner was built for another point set")
+    Xtr, ytr, Xval, yval = _dev(Xtr), _dev(ytr), _dev(Xval), _dev(yval)
     loss, ge, gb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     alpha = torch.empty(n, dtype=torch.float64, device=Xtr.device)
     lam = torch.empty(n, dtype=torch.float64, device=Xtr.device)

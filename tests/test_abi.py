@@ -155,3 +155,36 @@ def test_launch_table_size_classes(lib, tmp_path):
     f.write_text('{"arch": "", "entries": {"2:4:1:19": [9, 0]}}')                     # malformed key
     with pytest.raises(krr.KRRError):
         krr.autotune_load(str(f))
+
+
+def test_binding_rejects_mismatched_shapes(lib):
+    """The binding checks every buffer's shape against the sizes it passes to the C ABI (which cannot see a
+    buffer's extent) before anything reaches the device, so these raise on a machine without a GPU too."""
+    import numpy as np
+
+    import paper_1905_10587_amd as krr
+    X = np.zeros((10, 3))
+    with pytest.raises(ValueError, match="columns"):
+        krr.kernel_mv(X, np.zeros((12, 2)), 1.0, np.zeros(12))          # sources of another dimension
+    with pytest.raises(ValueError, match="rows"):
+        krr.kernel_mv(X, None, 1.0, np.zeros(9))                        # V shorter than the sources
+    with pytest.raises(ValueError, match="betas"):
+        krr.kernel_mv(X, None, 1.0, np.zeros((10, 3)), shift=[1.0, 2.0])
+    with pytest.raises(ValueError, match="n x d"):
+        krr.kernel_mv(np.zeros(10), None, 1.0, np.zeros(10))
+    with pytest.raises(ValueError, match="rows"):
+        krr.pcg_solve(X, np.zeros(11), 1.0, 1e-3)
+    with pytest.raises(ValueError, match="betas"):
+        krr.pcg_solve(X, np.zeros((10, 2)), 1.0, [1e-3])
+    with pytest.raises(ValueError, match="x0"):
+        krr.pcg_solve(X, np.zeros(10), 1.0, 1e-3, x0=np.zeros(9))
+    with pytest.raises(ValueError, match="ytr"):
+        krr.grad(X, np.zeros(9), np.zeros((4, 3)), np.zeros(4), 1.0, 1e-2)
+    with pytest.raises(ValueError, match="columns"):
+        krr.grad(X, np.zeros(10), np.zeros((4, 2)), np.zeros(4), 1.0, 1e-2)
+    with pytest.raises(ValueError, match="omega"):
+        krr.sketch(X, 1.0, omega=np.zeros((9, 4)))
+    with pytest.raises(ValueError, match="l x r"):
+        krr.sketch(X, 1.0, idx=np.zeros((4, 2), dtype=np.int64), sign=np.zeros((4, 3)))
+    with pytest.raises(ValueError, match="l = 5"):
+        krr.Preconditioner(X, 1.0, [1e-3], 3, 5, idx=np.zeros((4, 2), dtype=np.int64), sign=np.zeros((4, 2)))
