@@ -35,7 +35,7 @@ SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_PAIRS = SLOTS / 3.0
 PEAK_PAIRS_SYM = SLOTS / 2.0
 # The mixed forms also issue NCH MFMAs (v_mfma_f32_16x16x32_bf16, 16 cycles each at full rate) per 256
-# evaluated pairs, and on this part MFMA and VALU work do not overlap (measured with a register-only probe
+# evaluated pairs, and on this part MFMA and VALU work barely overlap (about 6%, measured with a register-only probe
 # and with the kernel's own counters), so the bound is VALU cycles + MFMA cycles per 256 evaluated pairs:
 # direct 48 + 16 NCH, symmetric 64 + 16 NCH (symmetric: two product pairs per evaluated pair).
 SIMD_CYCLES = 256 * 4 * 2.4e9
