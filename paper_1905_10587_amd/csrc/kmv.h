@@ -83,8 +83,12 @@ struct StagedVec {
   // block-MVM operands: BF16 parts in groups of four sources, V4[((j/4) * Rb + r) * 4 + j%4]
   int Rb = 0;
   DevBuf<uint16_t> vh, vm, vl;
+  // staged-V block form: the parts in the MFMA B-operand lane layout, per 32-source step and 16-column tile
+  DevBuf<uint16_t> vt;
 };
 // Block path: stage V into the BF16 parts (Rb = R padded to rpad).
+// Staged-V block form: stage V into the B-operand lane layout (Rb = R padded to 16).
+void stage_vectors_vt(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int nsplit, hipStream_t s);
 void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int rpad, int nsplit,
                          hipStream_t s);
 // Whether kmv_launch takes the block (multi right-hand side) path for these parameters.

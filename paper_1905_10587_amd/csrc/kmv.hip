@@ -267,6 +267,40 @@ __global__ void k_stage_v4(const double* __restrict__ V, int64_t n, int R, int64
   if (vl) vl[o] = l;
 }
 
+// Block-MVM operands in the B-operand lane layout of the staged-V form (k_kmv_block32v): per 32-source step
+// st, 16-column tile ct and part p, 64 lanes x 8 BF16 values; lane kq * 16 + r16 holds column 16 ct + r16 and
+// the sources 4 kq + e (values 0..3) and 16 + 4 kq + e (values 4..7) of the step.
+__global__ void k_stage_vt(const double* __restrict__ V, int64_t n, int R, int64_t npad, int Rb, int nsplit,
+                           const int* __restrict__ cols, int ldv, uint16_t* __restrict__ vt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npad * Rb) return;
+  const int64_t j = t / Rb;
+  const int r = (int)(t % Rb);
+  const double x = (j < n && r < R) ? V[j * ldv + (cols ? cols[r] : r)] : 0.0;
+  uint16_t h, m, l;
+  split3(x, h, m, l);
+  if (nsplit == 2) m = bf16_rn((float)(x - bf16_to_double(h)));   // two parts: the remainder x - hi
+  const int np = nsplit == 2 ? 2 : 3;
+  const int jj = (int)(j & 31);
+  const int lanev = ((jj & 15) >> 2) * 16 + (r & 15);
+  const int pos = (jj & 3) + 4 * (jj >> 4);
+  const int64_t base = (((j >> 5) * (Rb / 16) + r / 16) * np) * 64 + lanev;
+  vt[(base + 0 * 64) * 8 + pos] = h;
+  vt[(base + 1 * 64) * 8 + pos] = m;
+  if (np == 3) vt[(base + 2 * 64) * 8 + pos] = l;
+}
+
+void stage_vectors_vt(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int nsplit, hipStream_t s) {
+  sv.npad = npad;
+  sv.Rreal = R;
+  sv.Rb = (int)round_up(R, 16);
+  const size_t tot = (size_t)npad * sv.Rb * (nsplit == 2 ? 2 : 3);
+  if (sv.vt.n < tot) sv.vt.alloc(tot, s);   // grow only, as in stage_vectors
+  hipLaunchKernelGGL(k_stage_vt, dim3((unsigned)ceil_div(npad * (int64_t)sv.Rb, 256)), dim3(256), 0, s, V, n, R, npad,
+                     sv.Rb, nsplit, sv.cols, sv.cols ? sv.ldv : R, sv.vt.p);
+  KRR_LAUNCH_CHECK();
+}
+
 void stage_vectors_block(StagedVec& sv, const double* V, int64_t n, int64_t npad, int R, int rpad, int nsplit,
                          hipStream_t s) {
   sv.npad = npad;
@@ -382,7 +416,11 @@ KmvChoice kmv_lookup(int prec, int d, int R, int64_t n, bool square) {
       // a tuned entry covers every column count of its shape class: a shared-tile block form tuned at a
       // full count gives way to the per-wave form (variant 7) where its waves would idle, e.g. when a
       // block solve's active columns shrink (forced variants are taken as they are)
-      if (rclass(prec, R) == 3 && it->second.variant >= 12 && !shared_block_fits(R)) return KmvChoice{7, 0};
+      if (rclass(prec, R) == 3 && (it->second.variant == 12 || it->second.variant == 13) && !shared_block_fits(R))
+        return KmvChoice{7, 0};
+      // the staged-V form likewise gives way to variant 7 at 32 columns or fewer (its exp per pair then
+      // serves too few contractions)
+      if (rclass(prec, R) == 3 && it->second.variant == 14 && R <= 32) return KmvChoice{7, 0};
       return it->second;
     }
   }
@@ -396,8 +434,9 @@ void kmv_set_tuned(int prec, int d, int R, int64_t n, bool square, KmvChoice c) 
 }
 
 int kmv_num_variants(int prec, int R) {
-  // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile (64 targets), 13 shared tile (128 targets)
-  if (rclass(prec, R) == 3) return 14;
+  // block: 0..5 K = 16, 6..11 K = 32 tile shapes, 12 shared tile (64 targets), 13 shared tile (128 targets),
+  // 14 staged V (64 targets, each wave all of the block's columns)
+  if (rclass(prec, R) == 3) return 15;
   // mixed: 0..3 plain (NF 1, 2, 4, 8), 4..6 pipelined (NF 2, 4, 8), 7..9 pipelined + LDS tiles (NF 2, 4, 8),
   // 10..11 symmetric square product (NF 4, 8; other shapes run variant 8 / 9);
   // FP64 one column: 0..2 direct (TM 1, 2, 4), 3..4 symmetric square product (TM 2, 4; else variant 1 / 2),
@@ -423,8 +462,13 @@ int kmv_default_variant(int prec, int d, int R, int64_t m, int64_t, bool square)
   // parts (MIXED, three waves per SIMD) 316 against 348 ms at R = 128 on one machine, 321 against 324 ms
   // (four products at n = 2.5e5) on another; with three parts (FP32) 1.26x faster;
   // variant 12 when at least 7/8 of its waves hold columns (below, its idle waves cost more: 2.9x / 1.6x
-  // slower at R = 32 / 64), else variant 7 (1.36x faster than variant 0)
-  if (rclass(prec, R) == 3) return shared_block_fits(R) ? 12 : 7;
+  // slower at R = 32 / 64), else variant 7 (1.36x faster than variant 0).
+  // The staged-V form (variant 14: each wave contracts its own exp'd fragment with all of the block's
+  // columns, V staged through LDS one step ahead) beats both from R = 64 on (n = 2e5, d = 6, MIXED: R = 64
+  // 24.1 against 26.5 ms for variant 7, R = 128 34.1 against 51.5 for variant 12, R = 256 67.2 against 102.4;
+  // n = 5e5, R = 128: 205.8 against 317.6, FP32 364 against 466), not at R = 32 (20.4 against 13.9 for
+  // variant 7).
+  if (rclass(prec, R) == 3) return R > 32 ? 14 : 7;
   if (prec == KRR_MIXED) {
     // one K chunk: the exp/FMA stream bounds the kernel and the plain NF 8 form is fastest; two to four
     // chunks: the MFMA stream grows and the LDS-staged pipelined form wins (measured on MI355X, d = 4 / 8)
@@ -631,9 +675,15 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   int NRG = 8;
   const bool block = kmv_uses_block(prec, T.d, R, deriv);
   int NT = 1, NRC = 1, Rpart = Rp;
-  bool k32 = false, shared = false;
+  bool k32 = false, shared = false, vtile = false;
   int shared_fw = 1;   // fragments per wave of the shared-tile form
-  if (block) {
+  if (block && variant == 14) {   // staged-V form: 64 targets and up to 128 columns per block
+    vtile = true;
+    stage_vectors_vt(V, Vraw, S.n, S.npad, R, prec == KRR_MIXED ? 2 : 3, s);
+    Rpart = V.Rb;
+    rows = 64;
+    gz = (int)ceil_div(V.Rb, 128);
+  } else if (block) {
     shared = variant >= 12;
     shared_fw = variant == 13 ? 2 : 1;
     const int vb = shared ? 1 : variant % 6;
@@ -704,6 +754,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
   DevBuf<double> own;
   DevBuf<double>& part = ws ? *ws : own;
   auto run = [&](const KmvGrid& g) -> bool {
+    if (vtile) return launch_kmv_block_vt(T.ka / 32, prec == KRR_MIXED ? 3 : 6, g, T.sa.p, S.sb.p, V.vt.p, part.p, s);
     if (block && shared)
       return launch_kmv_block_shared(T.ka / 32, prec == KRR_MIXED ? 3 : 6, shared_fw, g, T.sa.p, S.sb.p, V.vh.p, V.vm.p,
                                      prec == KRR_MIXED ? nullptr : V.vl.p, part.p, s);

@@ -55,6 +55,32 @@ static void gobs(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const u
                      part, g.mpad, g.Rout);
 }
 
+template <int NCH, int NS>
+static void gobv(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
+                 hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32v<NCH, NS>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_block32v<NCH, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint4*>(VT), g.Rp, g.src_len, g.n_src,
+                     part, g.mpad, g.Rout);
+}
+
+bool launch_kmv_block_vt(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT,
+                         double* part, hipStream_t s) {
+#define KRR_BV(C)                                                                  \
+  if (NCH == C) {                                                                  \
+    if (NS == 3) gobv<C, 3>(g, A, B, VT, part, s);                                 \
+    else gobv<C, 6>(g, A, B, VT, part, s);                                         \
+    return true;                                                                   \
+  }
+  if (NS != 3 && NS != 6) return false;
+  KRR_BV(1) KRR_BV(2) KRR_BV(3) KRR_BV(4)
+#undef KRR_BV
+  return false;
+}
+
 bool launch_kmv_block_shared(int NCH, int NS, int FW, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                              const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s) {
 #define KRR_BSH(C)                                                                     \

@@ -56,6 +56,9 @@ bool launch_kmv_block(int NCH, int NT, int NRC, int NS, bool k32, const KmvGrid&
                       hipStream_t s);
 // Shared-tile block MVM: 64 FW targets x 128 right-hand sides per block (V staged with a multiple of 32 columns),
 // FW in {1, 2} fragments evaluated per wave.
+// Staged-V block form (k_kmv_block32v): NCH in {1, 2, 3, 4}, NS in {3, 6}.
+bool launch_kmv_block_vt(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT,
+                         double* part, hipStream_t s);
 bool launch_kmv_block_shared(int NCH, int NS, int FW, const KmvGrid& g, const uint16_t* A, const uint16_t* B,
                              const uint16_t* Vh, const uint16_t* Vm, const uint16_t* Vl, double* part, hipStream_t s);
 

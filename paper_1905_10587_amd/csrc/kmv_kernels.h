@@ -1677,4 +1677,146 @@ void k_kmv_block32s(const uint4* __restrict__ A, const uint4* __restrict__ B, co
     }
 }
 
+
+// Block MVM, staged-V form: a block covers 64 targets (wave w owns fragment w) and up to 128 right-hand sides
+// (grid.z walks the rest).  Each wave evaluates the cross term, exp2 and BF16 split of its own fragment and
+// contracts it with every column of the block, so no wave waits for another's exp'd tile; what the four waves
+// share is the step's V tile (and the cross term's source fragments), which the block moves into LDS with
+// direct global->LDS loads one 32-source step ahead (double buffered), one barrier per step.  V is staged in
+// the B-operand lane layout of v_mfma_f32_16x16x32_bf16 (VT: per 32-source step, 16-column tile and part,
+// 64 lanes x 8 BF16 values, lane r16 + 16 kq holding column r16 and sources {4kq + e, 16 + 4kq + e}), so a
+// tile is a contiguous run of the staged array.  Accumulation order per (target, column) is that of
+// k_kmv_block32s: the NS products of a step in the same order, FP32 over 256 sources, then FP64.
+// Chunk swizzle of a staged source row of KV chunks in LDS: the 16 rows a lane group reads at one chunk land
+// in distinct banks (rows 16 + r carry the swizzle of row r).  The staging lambda writes the same expression
+// out: a lambda of a kernel that calls a device function leaves the kernel without its host launch stub.
+template <int KV>
+__device__ __forceinline__ int blk_sw(int row) {
+  return KV == 8 ? (row >> 1) & 7 : KV == 16 ? row & 15 : (row >> 2) & 3;
+}
+
+template <int NCH, int NS>
+__global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ A, const uint4* __restrict__ B,
+                                                      const uint4* __restrict__ VT, int Rb, int64_t src_len,
+                                                      int64_t n_src, double* __restrict__ part, int64_t mpad,
+                                                      int Rout) {
+  constexpr int KV = NCH * 4;
+  constexpr int NP = NS == 6 ? 3 : 2;     // BF16 parts of V and of the exp'd tile
+  constexpr int NIS = 32 * KV / 64;       // 64-lane staging loads per step for the sources
+  __shared__ uint4 vs0[8 * NP * 64], vs1[8 * NP * 64];   // V tiles, double buffered: [column tile x part][lane]
+  __shared__ uint4 ss0[NIS * 64], ss1[NIS * 64];         // source rows: [row x KV + (chunk ^ blk_sw(row))]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int nctt = Rb / 16;                           // column tiles of the staged V
+  const int ct0 = blockIdx.z * 8;
+  const int nct = nctt - ct0 < 8 ? nctt - ct0 : 8;   // this block's column tiles (block-uniform)
+  const int nvi = nct * NP;                           // 64-lane staging loads of V per step
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+  const int nsteps = (int)((je - jb) / 32);
+
+  bf16x8 tg[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) tg[ch] = __builtin_bit_cast(bf16x8, A[(row0 + r16) * KV + ch * 4 + kq]);
+  double acc[8][4];
+  f32x4 a32[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    a32[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[c][e] = 0.0;
+  }
+
+  // staging of step st: V tiles (VT is contiguous per step and column tile) and the sources' split rows
+  // (LDS slot row x KV + position holds chunk position ^ blk_sw(row))
+  auto issue = [&](uint4* vdst, uint4* sdst, int st) {
+    const uint4* vsrc = VT + ((int64_t)(jb / 32 + st) * nctt + ct0) * NP * 64;
+    for (int i = wave; i < nvi; i += 4) __builtin_amdgcn_global_load_lds(vsrc + i * 64 + lane, vdst + i * 64, 16, 0, 0);
+    const uint4* bsrc = B + (jb + 32 * (int64_t)st) * KV;
+    for (int i = wave; i < NIS; i += 4) {
+      const int slot = i * 64 + lane;
+      const int rr = slot / KV, pos = slot - rr * KV;
+      const int swr = KV == 8 ? (rr >> 1) & 7 : KV == 16 ? rr & 15 : (rr >> 2) & 3;   // blk_sw<KV>(rr)
+      __builtin_amdgcn_global_load_lds(bsrc + rr * KV + (pos ^ swr), sdst + i * 64, 16, 0, 0);
+    }
+  };
+
+  if (nsteps > 0) issue(vs0, ss0, 0);
+  for (int st = 0; st < nsteps; ++st) {
+    const int cur = st & 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();   // step st staged by every wave; step st - 1's buffer no longer read
+    if (st + 1 < nsteps) {
+      if (cur) issue(vs0, ss0, st + 1);
+      else issue(vs1, ss1, st + 1);
+    }
+    const uint4* vsc = cur ? vs1 : vs0;
+    const uint4* ssc = cur ? ss1 : ss0;
+    // this wave's fragment: cross term (sources as MFMA rows), exp2, BF16 parts in the A-operand layout
+    f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int pos = (ch * 4 + kq) ^ blk_sw<KV>(r16);
+      qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ssc[r16 * KV + pos]), tg[ch], qa, 0, 0,
+                                                   0);
+      qb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ssc[(16 + r16) * KV + pos]), tg[ch],
+                                                   qb, 0, 0, 0);
+    }
+    bf16x8 ph, pm, pl;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {   // round-to-nearest-even splits, two values per v_cvt_pk_bf16_f32
+      const f32x2 p = {__builtin_amdgcn_exp2f(e < 4 ? qa[e] : qb[e - 4]),
+                       __builtin_amdgcn_exp2f(e < 4 ? qa[e + 1] : qb[e - 3])};
+      const bf16x2 h = __builtin_convertvector(p, bf16x2);
+      const f32x2 r1 = p - __builtin_convertvector(h, f32x2);
+      const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+      ph[e] = h[0]; ph[e + 1] = h[1];
+      pm[e] = m[0]; pm[e + 1] = m[1];
+      if (NS == 6) {
+        const bf16x2 lo = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+        pl[e] = lo[0]; pl[e + 1] = lo[1];
+      }
+    }
+    // contraction with the block's column tiles
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c < nct) {
+        const bf16x8 vh = __builtin_bit_cast(bf16x8, vsc[(c * NP + 0) * 64 + lane]);
+        const bf16x8 vm = __builtin_bit_cast(bf16x8, vsc[(c * NP + 1) * 64 + lane]);
+        a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vh, a32[c], 0, 0, 0);
+        a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vm, a32[c], 0, 0, 0);
+        a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm, vh, a32[c], 0, 0, 0);
+        if (NS == 6) {
+          const bf16x8 vl = __builtin_bit_cast(bf16x8, vsc[(c * NP + 2) * 64 + lane]);
+          a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph, vl, a32[c], 0, 0, 0);
+          a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl, vh, a32[c], 0, 0, 0);
+          a32[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pm, vm, a32[c], 0, 0, 0);
+        }
+      }
+    }
+    if ((st & 7) == 7 || st + 1 == nsteps) {   // FP64 fold every 256 sources
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[c][e] += (double)a32[c][e];
+          a32[c][e] = 0.0f;
+        }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = row0 + kq * 4 + e;
+    double* prow = part + ((int64_t)blockIdx.y * mpad + i) * Rout + ct0 * 16 + r16;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < nct) prow[16 * c] = acc[c][e];
+  }
+}
+
 }  // namespace krr

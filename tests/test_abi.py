@@ -97,13 +97,13 @@ def test_kmv_variant_introspection(lib):
     assert krr.kmv_variant(8, 1, "fp32", square=True)[1] is False
     # block products run the shared-tile form (12) when at least 7/8 of its 32-column waves hold columns,
     # else variant 7
-    assert krr.kmv_variant(6, 128, "mixed") == (12, False)
-    assert krr.kmv_variant(6, 64, "mixed") == (7, False)
-    assert krr.kmv_variant(6, 160, "mixed") == (7, False)
-    assert krr.kmv_variant(6, 128, "fp32") == (12, False)
-    assert krr.kmv_variant(6, 200, "fp32") == (12, False)    # 224 of 256 columns
-    assert krr.kmv_variant(6, 160, "fp32") == (7, False)     # 160 of 256 columns
-    assert krr.kmv_variant(6, 64, "fp32") == (7, False)
+    assert krr.kmv_variant(6, 128, "mixed") == (14, False)   # staged-V form above 32 columns
+    assert krr.kmv_variant(6, 64, "mixed") == (14, False)
+    assert krr.kmv_variant(6, 160, "mixed") == (14, False)
+    assert krr.kmv_variant(6, 32, "mixed") == (7, False)
+    assert krr.kmv_variant(6, 128, "fp32") == (14, False)
+    assert krr.kmv_variant(6, 200, "fp32") == (14, False)
+    assert krr.kmv_variant(6, 16, "fp32") == (7, False)
     # FP64 with more than 8 columns: the FP64 matrix-core kernel (variant 3)
     assert krr.kmv_variant(6, 128, "fp64") == (3, False)
     assert krr.kmv_variant(16, 9, "fp64") == (3, False)
@@ -152,6 +152,12 @@ def test_launch_table_size_classes(lib, tmp_path):
     krr.set_variant(6, 64, "mixed", 12)                                                # forced: as given
     assert krr.kmv_variant(6, 64, "mixed", square=True, n=500_000) == (12, False)
     krr.set_variant(6, 64, "mixed", -1)
+    # a tuned staged-V entry (variant 14) holds down to 33 columns and gives way to variant 7 at 32 or fewer
+    f.write_text('{"arch": "", "entries": {"2:6:3:18:1": [14, 0]}}')
+    krr.autotune_load(str(f))
+    assert krr.kmv_variant(6, 128, "mixed", square=True, n=500_000) == (14, False)
+    assert krr.kmv_variant(6, 40, "mixed", square=True, n=500_000) == (14, False)
+    assert krr.kmv_variant(6, 32, "mixed", square=True, n=500_000) == (7, False)
     f.write_text('{"arch": "", "entries": {"2:4:1:19": [9, 0]}}')                     # malformed key
     with pytest.raises(krr.KRRError):
         krr.autotune_load(str(f))
