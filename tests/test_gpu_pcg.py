@@ -157,17 +157,21 @@ def test_unattainable_tolerance_returns_best_iterate(gpu_lib):
 
 
 @pytest.mark.gpu
-def test_block_pcg_mixed_many_columns(gpu_lib):
-    """16 systems (4 labels x 4 betas) in one lockstep solve through the block MVM, vs dense Cholesky."""
+@pytest.mark.parametrize("nlab", [4, 10])
+def test_block_pcg_mixed_many_columns(gpu_lib, nlab):
+    """4 nlab systems (nlab labels x 4 betas) in one lockstep solve through the block MVM, vs dense Cholesky.
+    16 columns run the per-wave form (variant 7); 40 the staged-V form (variant 14), whose products go over
+    the active columns only once the beta = 0.1 columns converge, and back to variant 7 from 32 on."""
     rng = np.random.default_rng(21)
     n, d, eps = 2500, 6, 0.5
     X = rng.random((n, d))
-    a = 2.0 * rng.standard_normal((4, d))
-    b = 2 * np.pi * rng.random(4)
-    labels = np.sin(X @ a.T + b) + 0.05 * rng.standard_normal((n, 4))
+    a = 2.0 * rng.standard_normal((nlab, d))
+    b = 2 * np.pi * rng.random(nlab)
+    labels = np.sin(X @ a.T + b) + 0.05 * rng.standard_normal((n, nlab))
     betas = [1e-4, 1e-3, 1e-2, 1e-1]
     Y = np.repeat(labels, 4, axis=1)
-    col_beta = np.tile(np.array(betas), 4)
+    assert gpu_lib.kmv_variant(d, 4 * nlab, "mixed", square=True)[0] == (14 if nlab == 10 else 7)
+    col_beta = np.tile(np.array(betas), nlab)
     idx, sign = datagen.sketch_sparse_draws(n, 220, 16, seed=5)
     P = gpu_lib.Preconditioner(torch.from_numpy(X), eps, betas, 200, 220, idx=torch.from_numpy(idx),
                                sign=torch.from_numpy(sign), prec="mixed")
@@ -177,7 +181,7 @@ def test_block_pcg_mixed_many_columns(gpu_lib):
     print(f"block mixed PCG: iterations {its}, max relres {max(rel):.2e}, replacements {st['n_replace']}")
     assert status == 0 and max(rel) <= 1e-8
     K = ok.kernel_matrix(X, X, eps)
-    for c in range(16):
+    for c in range(4 * nlab):
         ref = np.linalg.solve(K + col_beta[c] * np.eye(n), Y[:, c])
         kappa = np.linalg.cond(K + col_beta[c] * np.eye(n))
         err = np.linalg.norm(A[:, c] - ref) / np.linalg.norm(ref)
