@@ -1,6 +1,6 @@
 // Block-MVM (many right-hand sides) kernel instantiations.
 #include "kmv_dispatch.h"
-#include "kmv_kernels.h"
+#include "kmv_block_kernels.h"
 
 namespace krr {
 
@@ -55,16 +55,24 @@ static void gobs(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const u
                      part, g.mpad, g.Rout);
 }
 
+template <int NCH, int NS, bool FULL>
+static void gobv_full(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
+                      hipStream_t s) {
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32v<NCH, NS, FULL>, 256, 0));
+    return;
+  }
+  hipLaunchKernelGGL((k_kmv_block32v<NCH, NS, FULL>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+                     reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint4*>(VT), g.Rp, g.src_len, g.n_src,
+                     part, g.mpad, g.Rout);
+}
+
 template <int NCH, int NS>
 static void gobv(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
                  hipStream_t s) {
-  if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32v<NCH, NS>, 256, 0));
-    return;
-  }
-  hipLaunchKernelGGL((k_kmv_block32v<NCH, NS>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
-                     reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint4*>(VT), g.Rp, g.src_len, g.n_src,
-                     part, g.mpad, g.Rout);
+  // every block holds 128 columns when the padded count is a multiple of 128
+  if (g.Rp % 128 == 0) gobv_full<NCH, NS, true>(g, A, B, VT, part, s);
+  else gobv_full<NCH, NS, false>(g, A, B, VT, part, s);
 }
 
 bool launch_kmv_block_vt(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT,

@@ -107,6 +107,8 @@ BLOCK_CASES = [
     (800, 1300, 6, 200),     # shared-tile form over two 128-column groups (224 padded columns: 3 live waves in the second)
     (1, 1, 3, 64),           # one target, one source
     (5, 3001, 8, 130),       # few targets, ragged sources, 130 columns (one live wave in the second group)
+    (1100, 1000, 3, 128),    # staged-V form with every block full (static tile loop), one K chunk
+    (700, 900, 16, 256),     # the same over two full column groups, four K chunks (one tile read ahead)
 ]
 
 
