@@ -55,14 +55,14 @@ static void gobs(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const u
                      part, g.mpad, g.Rout);
 }
 
-template <int NCH, int NS, bool FULL>
-static void gobv_full(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
-                      hipStream_t s) {
+template <int NCH, int NS, int NCTF>
+static void gobv_tiles(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
+                       hipStream_t s) {
   if (g.occ) {
-    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32v<NCH, NS, FULL>, 256, 0));
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_block32v<NCH, NS, NCTF>, 256, 0));
     return;
   }
-  hipLaunchKernelGGL((k_kmv_block32v<NCH, NS, FULL>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
+  hipLaunchKernelGGL((k_kmv_block32v<NCH, NS, NCTF>), g.grid, dim3(256), 0, s, reinterpret_cast<const uint4*>(A),
                      reinterpret_cast<const uint4*>(B), reinterpret_cast<const uint4*>(VT), g.Rp, g.src_len, g.n_src,
                      part, g.mpad, g.Rout);
 }
@@ -70,9 +70,18 @@ static void gobv_full(const KmvGrid& g, const uint16_t* A, const uint16_t* B, co
 template <int NCH, int NS>
 static void gobv(const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT, double* part,
                  hipStream_t s) {
-  // every block holds 128 columns when the padded count is a multiple of 128
-  if (g.Rp % 128 == 0) gobv_full<NCH, NS, true>(g, A, B, VT, part, s);
-  else gobv_full<NCH, NS, false>(g, A, B, VT, part, s);
+  // static column-tile count: every block holds 128 columns when the padded count is a multiple of 128; one
+  // block of 3 to 7 tiles covers 48 to 112 columns; otherwise the last block's count is read at run time
+  const int nctt = g.Rp / 16;
+  switch (nctt % 8 == 0 ? 8 : nctt < 8 ? nctt : 0) {
+    case 8: gobv_tiles<NCH, NS, 8>(g, A, B, VT, part, s); break;
+    case 7: gobv_tiles<NCH, NS, 7>(g, A, B, VT, part, s); break;
+    case 6: gobv_tiles<NCH, NS, 6>(g, A, B, VT, part, s); break;
+    case 5: gobv_tiles<NCH, NS, 5>(g, A, B, VT, part, s); break;
+    case 4: gobv_tiles<NCH, NS, 4>(g, A, B, VT, part, s); break;
+    case 3: gobv_tiles<NCH, NS, 3>(g, A, B, VT, part, s); break;
+    default: gobv_tiles<NCH, NS, 0>(g, A, B, VT, part, s);
+  }
 }
 
 bool launch_kmv_block_vt(int NCH, int NS, const KmvGrid& g, const uint16_t* A, const uint16_t* B, const uint16_t* VT,

@@ -402,9 +402,10 @@ void k_kmv_block32s(const uint4* __restrict__ A, const uint4* __restrict__ B, co
 // 64 lanes x 8 BF16 values, lane r16 + 16 kq holding column r16 and sources {4kq + e, 16 + 4kq + e}), so a
 // tile is a contiguous run of the staged array.  Accumulation order per (target, column) is that of
 // k_kmv_block32s: the NS products of a step in the same order, FP32 over 256 sources, then FP64.
-// FULL (column count a multiple of 128): every block holds eight column tiles, so the contraction and the V
-// staging have static trip counts and the compiler can issue a step's V reads ahead of their products
-// instead of branching per tile and waiting on each read.
+// NCTF > 0: every block holds NCTF column tiles (the padded column count a multiple of 128 with NCTF = 8, or
+// NCTF tiles in all, fewer than eight), so the contraction and the V staging have static trip counts and the
+// compiler can issue a step's V reads ahead of their products instead of branching per tile and waiting on
+// each read.  NCTF = 0: the count is read at run time (a last block of fewer columns).
 // Chunk swizzle of a staged source row of KV chunks in LDS: the 16 rows a lane group reads at one chunk land
 // in distinct banks (rows 16 + r carry the swizzle of row r).  The staging lambda writes the same expression
 // out: a lambda of a kernel that calls a device function leaves the kernel without its host launch stub.
@@ -413,7 +414,7 @@ __device__ __forceinline__ int blk_sw(int row) {
   return KV == 8 ? (row >> 1) & 7 : KV == 16 ? row & 15 : (row >> 2) & 3;
 }
 
-template <int NCH, int NS, bool FULL>
+template <int NCH, int NS, int NCTF>
 __global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ A, const uint4* __restrict__ B,
                                                       const uint4* __restrict__ VT, int Rb, int64_t src_len,
                                                       int64_t n_src, double* __restrict__ part, int64_t mpad,
@@ -432,8 +433,8 @@ __global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ 
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int nctt = Rb / 16;                           // column tiles of the staged V
   const int ct0 = blockIdx.z * 8;
-  // this block's column tiles (block-uniform; FULL: every block holds eight, a static trip count)
-  const int nct = FULL ? 8 : nctt - ct0 < 8 ? nctt - ct0 : 8;
+  // this block's column tiles (block-uniform; a static trip count when NCTF > 0)
+  const int nct = NCTF > 0 ? NCTF : nctt - ct0 < 8 ? nctt - ct0 : 8;
   const int nvi = nct * NP;                           // 64-lane staging loads of V per step
   const int64_t jb = (int64_t)blockIdx.y * src_len;
   const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
@@ -492,14 +493,14 @@ __global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ 
       sa[ch] = __builtin_bit_cast(bf16x8, ssc[r16 * KV + pos]);
       sb[ch] = __builtin_bit_cast(bf16x8, ssc[(16 + r16) * KV + pos]);
     }
-    // FULL: the V operands of the first PF column tiles are read now, behind the cross term and the exp;
+    // NCTF > 0: the V operands of the first PF column tiles are read now, behind the cross term and the exp;
     // each later tile's are read PF tiles ahead of its products (a ring of PF + 1), so no product waits on
     // LDS.  PF = 1 where a second tile in flight would cost the third wave per SIMD (above 168 registers).
     constexpr int PF = NS == 3 && NCH == 4 ? 1 : 2;
     bf16x8 vr[PF + 1][NP];
-    if (FULL) {
+    if (NCTF > 0) {
 #pragma unroll
-      for (int c = 0; c < PF; ++c)
+      for (int c = 0; c < PF && c < NCTF; ++c)
 #pragma unroll
         for (int p = 0; p < NP; ++p) vr[c][p] = __builtin_bit_cast(bf16x8, vsc[(c * NP + p) * 64 + lane]);
       __builtin_amdgcn_sched_barrier(0);
@@ -529,10 +530,10 @@ __global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ 
       }
     }
     // contraction with the block's column tiles
-    if (FULL) {
+    if (NCTF > 0) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c + PF < 8) {
+      for (int c = 0; c < NCTF; ++c) {
+        if (c + PF < NCTF) {
 #pragma unroll
           for (int p = 0; p < NP; ++p)
             vr[(c + PF) % (PF + 1)][p] = __builtin_bit_cast(bf16x8, vsc[((c + PF) * NP + p) * 64 + lane]);
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(256) void k_kmv_block32v(const uint4* __restrict__ 
     }
     if ((st & 7) == 7 || st + 1 == nsteps) {   // FP64 fold every 256 sources
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
+      for (int c = 0; c < (NCTF > 0 ? NCTF : 8); ++c)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           acc[c][e] += (double)a32[c][e];

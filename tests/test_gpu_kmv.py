@@ -109,6 +109,8 @@ BLOCK_CASES = [
     (5, 3001, 8, 130),       # few targets, ragged sources, 130 columns (one live wave in the second group)
     (1100, 1000, 3, 128),    # staged-V form with every block full (static tile loop), one K chunk
     (700, 900, 16, 256),     # the same over two full column groups, four K chunks (one tile read ahead)
+    (600, 1400, 8, 112),     # staged-V form, one block of seven column tiles (static tile loop)
+    (400, 900, 4, 70),       # one block of five column tiles, 70 real columns
 ]
 
 
