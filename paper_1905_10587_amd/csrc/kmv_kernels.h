@@ -196,6 +196,85 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__
   }
 }
 
+// FP64 product with 128 columns per block (NRG = 8): the work and the order of every sum as in
+// k_kmv_f64_mfma<D, 8>, with the source tiles (16 sources: coordinates and V rows) moved into LDS by direct
+// global->LDS loads one tile ahead (double buffered, 38 KB per block at D = 6), one barrier per tile, so
+// the loads of the next tile overlap the products of this one instead of stalling the block between two
+// barriers.  In a last, partly filled column block the lanes whose 16 bytes of a V row fall in dead
+// column groups load nothing; those groups' products read stale LDS values and are not stored.
+template <int D>
+__global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restrict__ xt,
+                                                         const double* __restrict__ xs,
+                                                         const double* __restrict__ v, int Rp, int64_t src_len,
+                                                         int64_t n_src, double neg_c, double* __restrict__ part,
+                                                         int64_t mpad, int Rout, int64_t m_store, int n_store) {
+  constexpr int TS = 16;
+  constexpr int VS = 128 + 16;      // LDS row stride (doubles), as in k_kmv_f64_mfma
+  constexpr int NXU = TS * D / 2;   // 16-byte units of a tile's source coordinates
+  __shared__ __align__(16) double sx0[TS * D], sx1[TS * D];
+  __shared__ __align__(16) double sv0[TS * VS], sv1[TS * VS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int c0 = blockIdx.z * 128;
+  const int ng = (Rp - c0) / 16 < 8 ? (Rp - c0) / 16 : 8;   // live column groups of this block
+  const bool vlive = 2 * lane < 16 * ng;
+  const int64_t jb = (int64_t)blockIdx.y * src_len;
+  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
+  const int ntiles = (int)((je - jb) / TS);
+  double xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = xt[(row0 + r16) * D + k];
+  f64x4 acc[8];
+#pragma unroll
+  for (int g = 0; g < 8; ++g) acc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // staging of the tile at source jt: V row r by wave r % 4 (one 1 KB row per wave instruction), the
+  // coordinates by the first NXU threads
+  auto issue = [&](double* dx, double* dv, int64_t jt) {
+    for (int r = wave; r < TS; r += 4)
+      if (vlive) __builtin_amdgcn_global_load_lds(v + (jt + r) * Rp + c0 + 2 * lane, dv + r * VS, 16, 0, 0);
+    if (tid < NXU) __builtin_amdgcn_global_load_lds(xs + jt * D + 2 * tid, dx + 128 * wave, 16, 0, 0);
+  };
+
+  if (ntiles > 0) issue(sx0, sv0, jb);
+  for (int t = 0; t < ntiles; ++t) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();   // tile t staged by every wave; tile t - 1's buffers no longer read
+    if (t + 1 < ntiles) {
+      if (t & 1) issue(sx0, sv0, jb + (int64_t)(t + 1) * TS);
+      else issue(sx1, sv1, jb + (int64_t)(t + 1) * TS);
+    }
+    const double* sx = (t & 1) ? sx1 : sx0;
+    const double* sv = (t & 1) ? sv1 : sv0;
+#pragma unroll
+    for (int s4 = 0; s4 < TS; s4 += 4) {
+      const int js = s4 + kq;
+      double d2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double df = xi[k] - sx[js * D + k];
+        d2 = __builtin_fma(df, df, d2);
+      }
+      const double e = exp2_neg_f64(d2 * neg_c);
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e, sv[js * VS + 16 * g + r16], acc[g], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t row = row0 + 4 * e + kq;
+    double* prow = part + ((int64_t)blockIdx.y * mpad + row) * Rout + c0 + r16;
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      if (g < ng && row < m_store && c0 + 16 * g + r16 < n_store) prow[16 * g] = acc[g][e];
+  }
+}
+
 // Symmetric FP64 form for the square product u = K(X, X) v (one column), D even and <= 16.  Super-tiles
 // and partial slots as in k_kmv_mixed_sym: block b owns one pair (r, c <= ...) of the upper triangle,
 // evaluates the E x E tile once and writes its row sums to part[c][rows of r] and, off the diagonal, its
