@@ -13,7 +13,7 @@
 //         exp2 and one FMA with v per pair.
 // Many right-hand sides: the exp'd tile is itself an MFMA operand.  MIXED and FP32 split it into BF16
 // parts and contract with split-BF16 V on v_mfma_f32_16x16x32_bf16 (block kernels); FP64 contracts it on
-// v_mfma_f64_16x16x4_f64 (k_kmv_f64_mfma).  Square one-column products have symmetric forms (MIXED and
+// v_mfma_f64_16x16x4_f64 (k_kmv_f64_mfma_db).  Square one-column products have symmetric forms (MIXED and
 // FP64) that evaluate each pair once for both of its rows.
 // Sources are split across the grid's y dimension; every block writes FP64 partial sums which a
 // finishing kernel adds in a fixed order (deterministic), together with the ridge term.

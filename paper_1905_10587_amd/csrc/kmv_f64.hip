@@ -43,22 +43,13 @@ static void go64s(const KmvGrid& g, const double* x, const double* v, double neg
 template <int D, int NRG>
 static void go64m(const KmvGrid& g, const double* xt, const double* xs, const double* v, double neg_c,
                   double* part, hipStream_t s) {
-  if constexpr (NRG == 8) {   // 128 columns per block: the double-buffered form
-    if (g.occ) {
-      KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_mfma128<D>, 256, 0));
-      return;
-    }
-    hipLaunchKernelGGL((k_kmv_f64_mfma128<D>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src, neg_c,
-                       part, g.mpad, g.Rout, g.m_store > 0 ? g.m_store : g.mpad, g.n_store > 0 ? g.n_store : g.Rp);
-  } else {
-    if (g.occ) {
-      KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_mfma<D, NRG>, 256, 0));
-      return;
-    }
-    hipLaunchKernelGGL((k_kmv_f64_mfma<D, NRG>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
-                       neg_c, part, g.mpad, g.Rout, g.m_store > 0 ? g.m_store : g.mpad,
-                       g.n_store > 0 ? g.n_store : g.Rp);
+  if (g.occ) {
+    KRR_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occ, k_kmv_f64_mfma_db<D, NRG>, 256, 0));
+    return;
   }
+  hipLaunchKernelGGL((k_kmv_f64_mfma_db<D, NRG>), g.grid, dim3(256), 0, s, xt, xs, v, g.Rp, g.src_len, g.n_src,
+                     neg_c, part, g.mpad, g.Rout, g.m_store > 0 ? g.m_store : g.mpad,
+                     g.n_store > 0 ? g.n_store : g.Rp);
 }
 
 bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, const double* xs, const double* v,

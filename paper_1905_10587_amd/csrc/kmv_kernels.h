@@ -127,89 +127,24 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // FP64 product with many right-hand sides on the FP64 matrix cores (v_mfma_f64_16x16x4_f64, A 16 x 4,
 // B 4 x 16, exact FP64 products and sums).  A block covers 64 targets (wave w: targets row0 + 16 w ..) and
-// 16 * NRG columns; sources and their V rows stream through LDS in tiles of 32.  At each 4-source step
-// lane l evaluates the one pair (target l % 16, source l / 16) in FP64 direct differences, which is its
-// A-operand element, and the NRG MFMAs contract it with the V rows of the four sources.  The kernel value
-// of a pair is evaluated once for all 16 * NRG columns; the column-chunked VALU kernel evaluates it once
-// per chunk of 32.  The last column block may be partly filled: groups of 16 columns at or beyond Rp
-// (a multiple of 16) are zero in LDS and contracted like the others (a branch around their MFMAs slows
-// the loop far more than the wasted products cost) but not stored.
+// 16 * NRG columns.  At each 4-source step lane l evaluates the one pair (target l % 16, source l / 16) in
+// FP64 direct differences, which is its A-operand element, and the NRG MFMAs contract it with the V rows of
+// the four sources: the kernel value of a pair is evaluated once for all 16 * NRG columns.  The source tiles
+// (16 sources: coordinates and V rows) move into LDS by direct global->LDS loads one tile ahead (double
+// buffered, 38 KB per block at D = 6 and 128 columns), one barrier per tile, so the loads of the next tile
+// overlap the products of this one.  A V row of the block (16 NRG doubles) is one wave instruction, its
+// lanes past 8 NRG idle.  The last column block may be partly filled: the lanes whose 16 bytes fall in its
+// dead column groups load nothing, and those groups' products read stale LDS values and are not stored (a
+// branch around their MFMAs would cost more than the wasted products).
 template <int D, int NRG>
-__global__ __launch_bounds__(256) void k_kmv_f64_mfma(const double* __restrict__ xt, const double* __restrict__ xs,
-                                                      const double* __restrict__ v, int Rp, int64_t src_len,
-                                                      int64_t n_src, double neg_c, double* __restrict__ part,
-                                                      int64_t mpad, int Rout, int64_t m_store, int n_store) {
-  constexpr int TS = 32;
-  constexpr int RCH = 16 * NRG;
-  constexpr int VS = RCH + 16;   // LDS row stride (doubles): consecutive rows start 128 bytes apart in the banks
-  __shared__ double sx[TS * D];
-  __shared__ double sv[TS * VS];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int r16 = lane & 15;
-  const int kq = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int c0 = blockIdx.z * RCH;
-  const int ng = (Rp - c0) / 16 < NRG ? (Rp - c0) / 16 : NRG;   // live column groups of this block
-  const int64_t jb = (int64_t)blockIdx.y * src_len;
-  const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
-  double xi[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) xi[k] = xt[(row0 + r16) * D + k];
-  f64x4 acc[NRG];
-#pragma unroll
-  for (int g = 0; g < NRG; ++g) acc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t jt = jb; jt < je; jt += TS) {
-    __syncthreads();
-    for (int u = threadIdx.x; u < TS * D; u += 256) sx[u] = xs[jt * D + u];
-    for (int u = threadIdx.x; u < TS * RCH; u += 256) {
-      const int r = u / RCH, c = u % RCH;
-      sv[r * VS + c] = c < 16 * ng ? v[(jt + r) * Rp + c0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int s4 = 0; s4 < TS; s4 += 4) {
-      const int js = s4 + kq;
-      double d2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const double df = xi[k] - sx[js * D + k];
-        d2 = __builtin_fma(df, df, d2);
-      }
-      const double e = exp2_neg_f64(d2 * neg_c);
-#pragma unroll
-      for (int g = 0; g < NRG; ++g)
-        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e, sv[js * VS + 16 * g + r16], acc[g], 0, 0, 0);
-    }
-  }
-  // result element e of the lane: target row0 + 4 e + l / 16, column c0 + 16 g + l % 16 (the FP64 16 x 16
-  // result interleaves its rows, unlike the FP32 16 x 16 results; checked by a lane-layout probe on gfx950).
-  // Rows at or beyond m_store and columns at or beyond n_store are not stored (a caller writing the final
-  // m x n_store result in place passes its sizes; the partial buffers pass mpad and Rp).
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t row = row0 + 4 * e + kq;
-    double* prow = part + ((int64_t)blockIdx.y * mpad + row) * Rout + c0 + r16;
-#pragma unroll
-    for (int g = 0; g < NRG; ++g)
-      if (g < ng && row < m_store && c0 + 16 * g + r16 < n_store) prow[16 * g] = acc[g][e];
-  }
-}
-
-// FP64 product with 128 columns per block (NRG = 8): the work and the order of every sum as in
-// k_kmv_f64_mfma<D, 8>, with the source tiles (16 sources: coordinates and V rows) moved into LDS by direct
-// global->LDS loads one tile ahead (double buffered, 38 KB per block at D = 6), one barrier per tile, so
-// the loads of the next tile overlap the products of this one instead of stalling the block between two
-// barriers.  In a last, partly filled column block the lanes whose 16 bytes of a V row fall in dead
-// column groups load nothing; those groups' products read stale LDS values and are not stored.
-template <int D>
-__global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restrict__ xt,
+__global__ __launch_bounds__(256) void k_kmv_f64_mfma_db(const double* __restrict__ xt,
                                                          const double* __restrict__ xs,
                                                          const double* __restrict__ v, int Rp, int64_t src_len,
                                                          int64_t n_src, double neg_c, double* __restrict__ part,
                                                          int64_t mpad, int Rout, int64_t m_store, int n_store) {
   constexpr int TS = 16;
-  constexpr int VS = 128 + 16;      // LDS row stride (doubles), as in k_kmv_f64_mfma
+  constexpr int RCH = 16 * NRG;
+  constexpr int VS = RCH + 16;      // LDS row stride (doubles): consecutive rows start 128 bytes apart in the banks
   constexpr int NXU = TS * D / 2;   // 16-byte units of a tile's source coordinates
   __shared__ __align__(16) double sx0[TS * D], sx1[TS * D];
   __shared__ __align__(16) double sv0[TS * VS], sv1[TS * VS];
@@ -219,8 +154,8 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restric
   const int r16 = lane & 15;
   const int kq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int c0 = blockIdx.z * 128;
-  const int ng = (Rp - c0) / 16 < 8 ? (Rp - c0) / 16 : 8;   // live column groups of this block
+  const int c0 = blockIdx.z * RCH;
+  const int ng = (Rp - c0) / 16 < NRG ? (Rp - c0) / 16 : NRG;   // live column groups of this block
   const bool vlive = 2 * lane < 16 * ng;
   const int64_t jb = (int64_t)blockIdx.y * src_len;
   const int64_t je = jb + src_len < n_src ? jb + src_len : n_src;
@@ -228,12 +163,12 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restric
   double xi[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xi[k] = xt[(row0 + r16) * D + k];
-  f64x4 acc[8];
+  f64x4 acc[NRG];
 #pragma unroll
-  for (int g = 0; g < 8; ++g) acc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < NRG; ++g) acc[g] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  // staging of the tile at source jt: V row r by wave r % 4 (one 1 KB row per wave instruction), the
-  // coordinates by the first NXU threads
+  // staging of the tile at source jt: V row r by wave r % 4 (one row of up to 1 KB per wave instruction),
+  // the coordinates by the first NXU threads
   auto issue = [&](double* dx, double* dv, int64_t jt) {
     for (int r = wave; r < TS; r += 4)
       if (vlive) __builtin_amdgcn_global_load_lds(v + (jt + r) * Rp + c0 + 2 * lane, dv + r * VS, 16, 0, 0);
@@ -261,7 +196,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restric
       }
       const double e = exp2_neg_f64(d2 * neg_c);
 #pragma unroll
-      for (int g = 0; g < 8; ++g)
+      for (int g = 0; g < NRG; ++g)
         acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(e, sv[js * VS + 16 * g + r16], acc[g], 0, 0, 0);
     }
   }
@@ -270,7 +205,7 @@ __global__ __launch_bounds__(256) void k_kmv_f64_mfma128(const double* __restric
     const int64_t row = row0 + 4 * e + kq;
     double* prow = part + ((int64_t)blockIdx.y * mpad + row) * Rout + c0 + r16;
 #pragma unroll
-    for (int g = 0; g < 8; ++g)
+    for (int g = 0; g < NRG; ++g)
       if (g < ng && row < m_store && c0 + 16 * g + r16 < n_store) prow[16 * g] = acc[g][e];
   }
 }
