@@ -634,7 +634,7 @@ bool kernel_times_matrix_f64(const double* Xt, int64_t m, const double* Xs, int6
   // (about 112 VALU cycles), over ceil(Rp / 16 NRG) column blocks
   int NRG = 8;
   double best = 1e300;
-  for (int nr : {8, 4, 2, 1}) {
+  for (int nr : {8, 6, 4, 2, 1}) {
     const double cost = (double)ceil_div(Rp, 16 * nr) * (64.0 * nr + 112.0);
     if (cost < best * (1 - 1e-9)) { best = cost; NRG = nr; }
   }
@@ -717,7 +717,7 @@ void kmv_launch(const Staged& T, const Staged& S, StagedVec& V, int deriv, const
     // block width 16 * NRG: per 4-source step a block costs NRG MFMAs (64 cycles each) plus the pair's
     // distance and exp (about 112 VALU cycles); dead groups of a partly filled last block are contracted too
     double best = 1e300;
-    for (int nr : {8, 4, 2, 1}) {
+    for (int nr : {8, 6, 4, 2, 1}) {
       const double cost = (double)ceil_div(Rp, 16 * nr) * (64.0 * nr + 112.0);
       if (cost < best * (1 - 1e-9)) { best = cost; NRG = nr; }
     }

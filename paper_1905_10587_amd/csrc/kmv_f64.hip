@@ -59,6 +59,7 @@ bool launch_kmv_f64_mfma(int D, int NRG, const KmvGrid& g, const double* xt, con
     if (NRG == 1) { go64m<DD, 1>(g, xt, xs, v, neg_c, part, s); return true; }    \
     if (NRG == 2) { go64m<DD, 2>(g, xt, xs, v, neg_c, part, s); return true; }    \
     if (NRG == 4) { go64m<DD, 4>(g, xt, xs, v, neg_c, part, s); return true; }    \
+    if (NRG == 6) { go64m<DD, 6>(g, xt, xs, v, neg_c, part, s); return true; }    \
     if (NRG == 8) { go64m<DD, 8>(g, xt, xs, v, neg_c, part, s); return true; }    \
   }
   KRR_M64(2) KRR_M64(3) KRR_M64(4) KRR_M64(6) KRR_M64(8) KRR_M64(16)

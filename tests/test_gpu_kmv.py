@@ -147,7 +147,7 @@ def test_block_mv_parity(gpu_lib, prec, tol, case):
 
 F64_MANY_CASES = [
     # (m, n, d, R): FP64 products with several columns; variant 3 runs the FP64 matrix-core kernel
-    # (16 * NRG columns per block, NRG = 1, 2, 4, 8, the last block possibly partly filled; more than 8
+    # (16 * NRG columns per block, NRG = 1, 2, 4, 6, 8, the last block possibly partly filled; more than 8
     # columns are padded to a multiple of 16)
     (1500, 1700, 6, 16),
     (2100, 1100, 4, 48),     # 48 columns: one block of 64, three live groups of 16
@@ -161,6 +161,8 @@ F64_MANY_CASES = [
     (1000, 1000, 8, 256),    # two 128-column blocks
     (1, 1, 2, 16),           # one target, one source
     (3, 4099, 16, 128),      # three targets, a ragged source tail
+    (800, 900, 5, 90),       # 90 columns padded to 96: NRG 6, one block
+    (500, 700, 4, 80),       # 80 columns: NRG 6 with one dead column group
 ]
 
 
